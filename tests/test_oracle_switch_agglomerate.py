@@ -1,0 +1,111 @@
+"""Pins for the switch (Sec. 2.2, Sec. 4.2) and greedy agglomeration (Sec. 3)."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle.agglomerate import build_hierarchy, coarsen_topology, splitmix64, vertex_connected
+from oracle.mesh import Topology
+from oracle.switch import consistent_switch, is_consistent, natural_switch
+from workloads import mesh2d_jittered_delaunay, mesh3d_kuhn, quad_grid
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_splitmix64_published_values():
+    # First outputs of the SplitMix64 generator seeded with 0 are splitmix64
+    # applied to the states 0, g, 2g, ... with g = 0x9E3779B97F4A7C15 folded
+    # into the output function; reference values of the published generator.
+    g = 0x9E3779B97F4A7C15
+    vals = [splitmix64((k * g) & ((1 << 64) - 1)) for k in range(3)]
+    assert vals == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+@pytest.mark.parametrize("d,n", [(2, 8), (2, 17), (3, 3)])
+def test_consistent_switch(d, n):
+    m = mesh2d_jittered_delaunay(n, 2) if d == 2 else mesh3d_kuhn(n, 2)
+    topo = Topology(m.e2v, m.coords)
+    host = consistent_switch(topo.interior, topo.n_elem)
+    deg, hosted, ok = is_consistent(topo.interior, topo.n_elem, host)
+    assert ok.all()
+    assert np.all(np.abs(2 * hosted - deg) <= 1)          # balanced orientation
+    for f, (a, _, b, _) in enumerate(topo.interior):
+        assert host[f] in (a, b)
+
+
+def test_natural_switch_is_an_enumeration():
+    m = mesh2d_jittered_delaunay(6, 3)
+    topo = Topology(m.e2v, m.coords)
+    host = natural_switch(topo.interior, topo.n_elem)
+    for f, (a, _, b, _) in enumerate(topo.interior):
+        assert host[f] == min(a, b)
+    # an element hosts exactly its facets towards higher-numbered neighbours
+    deg, hosted, ok = is_consistent(topo.interior, topo.n_elem, host)
+    assert not ok.all()  # the natural switch is not consistent in general
+
+
+def _check_partition(elem_verts, parent):
+    nb = int(parent.max()) + 1
+    assert parent.min() >= 0
+    assert set(np.unique(parent)) == set(range(nb))
+    for b in range(nb):
+        assert vertex_connected(elem_verts, np.nonzero(parent == b)[0])
+
+
+@pytest.mark.parametrize("d,n,seed", [(2, 16, 11), (2, 23, 5), (3, 4, 13)])
+def test_partition_validity_every_level(d, n, seed):
+    m = mesh2d_jittered_delaunay(n, 1) if d == 2 else mesh3d_kuhn(n, 1)
+    topo = Topology(m.e2v, m.coords)
+    parents = build_hierarchy(m.e2v, topo.neighbor_pairs(), 20, seed)
+    ev = [sorted(int(v) for v in row) for row in m.e2v]
+    pairs = [tuple(p) for p in topo.neighbor_pairs()]
+    for par in parents:
+        assert len(par) == len(ev)
+        _check_partition(ev, par)
+        ev, pairs = coarsen_topology(ev, pairs, par)
+    assert len(ev) == 1  # Alg. 1 runs until a single element remains
+
+
+def _read_golden_blocks(path):
+    out = {}
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, vals = line.split(":")
+            out[key.strip()] = [int(v) for v in vals.split()]
+    return out
+
+
+@pytest.mark.parametrize("seed", [0, 1, 7, 11])
+def test_quad_grid_regular_hierarchy(seed):
+    # Fig. 2 caption and the regular hierarchy of Fig. 5 (8 x 8 square mesh):
+    # the vertex patch of a corner quad is an aligned 2 x 2 block ("8 sided"
+    # polygon) and four such blocks merge at the next level ("16 sided").
+    gold = _read_golden_blocks(os.path.join(GOLDEN, "quad8_regular_hierarchy.txt"))
+    e2v, pairs = quad_grid(8)
+    parents = build_hierarchy(e2v, pairs, 10, seed)
+    assert [int(p.max()) + 1 for p in parents] == gold["level_sizes"]
+    anc = np.arange(64)
+    for lvl, par in enumerate(parents, start=1):
+        anc = par[anc]
+        tile = np.array(gold["tile_level%d" % lvl])
+        # same partition as the aligned tiling, up to block numbering
+        pairs_same = anc[:, None] == anc[None, :]
+        tiles_same = tile[:, None] == tile[None, :]
+        assert np.array_equal(pairs_same, tiles_same)
+
+
+def test_cost_is_near_linear():
+    # O(n log n) cost (Sec. 3.2): level-0 time for 4x the elements stays well
+    # below 8x.
+    import time
+    ts = []
+    for n in (24, 48):
+        m = mesh2d_jittered_delaunay(n, 1)
+        pairs = Topology(m.e2v, m.coords).neighbor_pairs()
+        t0 = time.perf_counter()
+        build_hierarchy(m.e2v, pairs, 2, 3)
+        ts.append(time.perf_counter() - t0)
+    assert ts[1] / ts[0] < 8.0
