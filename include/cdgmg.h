@@ -1,0 +1,220 @@
+/*
+ * cdgmg.h - C ABI of libcdgmg: agglomeration-based geometric multigrid for the
+ * Compact Discontinuous Galerkin (CDG) discretisation of
+ *
+ *     -div(kappa grad u) = f  in the unit square / cube,  u = 0 on Dirichlet facets,
+ *
+ * on unstructured simplex meshes, after Pan & Persson, "Agglomeration-based
+ * geometric multigrid solvers for compact discontinuous Galerkin discretizations
+ * on unstructured meshes".  The solve is a flexible CG (or PCG) in FP64,
+ * preconditioned by a V(nu1,nu2) cycle with damped block-Jacobi smoothing on a
+ * fixed agglomerated hierarchy (Alg. 3), run in FP32 or FP64 on one gfx950 GPU.
+ *
+ * Conventions (every entry point):
+ *   - Return value: 0 = success, >0 = warning, <0 = error; the message of the
+ *     last error on the calling thread is returned by cdgmg_last_error().
+ *   - Host arrays passed in are read during the call only; nothing is retained.
+ *   - Device arrays (suffix _dev) are caller-owned device memory, read or
+ *     written on the stream given at setup.  The library owns the device
+ *     memory it allocates at setup and frees it in cdgmg_destroy.
+ *   - Per-element vectors are float64 [n_elem][n_p] in the caller's element
+ *     order; n_p = C(p+d, d).  Level-0 coefficients are nodal values at the
+ *     equispaced nodes of each simplex, ordered (with x = v0 + sum_k xi_k (v_k - v0)):
+ *       d = 2: for j in 0..p, for i in 0..p-j:            xi = (i/p, j/p)
+ *       d = 3: for k in 0..p, for j in 0..p-k, for i in 0..p-j-k: xi = (i/p, j/p, k/p)
+ *   - Mesh: e2v lists d+1 vertices per element with positive orientation;
+ *     local facet i of an element is the one opposite its local vertex i.
+ *   - A call that runs device work returns after that work is enqueued, except
+ *     where stated (solves synchronise once per outer iteration to test
+ *     convergence).
+ */
+#ifndef CDGMG_H
+#define CDGMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define CDGMG_OK 0
+#define CDGMG_NOT_CONVERGED 1
+#define CDGMG_ERR_ARG (-1)
+#define CDGMG_ERR_MESH (-2)
+#define CDGMG_ERR_HIERARCHY (-3)
+#define CDGMG_ERR_SINGULAR (-4)
+#define CDGMG_ERR_DEVICE (-5)
+#define CDGMG_ERR_NOMEM (-6)
+#define CDGMG_ERR_NAN (-7)
+
+/* options */
+#define CDGMG_MG_FP64 0          /* V-cycle in FP64 */
+#define CDGMG_MG_FP32 1          /* V-cycle in FP32 inside the FP64 outer solve */
+#define CDGMG_OUTER_FCG 0        /* flexible CG, one previous direction (Notay 2000) */
+#define CDGMG_OUTER_PCG 1        /* preconditioned CG */
+#define CDGMG_COARSEN_PRIMAL 0   /* A_{l+1} = L^T A_l L (Galerkin / RAT, Sec. 3.5) */
+#define CDGMG_COARSEN_FLUX 1     /* flux-form coarsening + Schur complement (Sec. 4.1) */
+#define CDGMG_SWITCH_CONSISTENT 0
+#define CDGMG_SWITCH_NATURAL 1
+
+/* kernel classes timed when cdgmg_options.profile != 0 */
+#define CDGMG_K_SPMV 0           /* outer FP64 y = A_0 x (+ fused dots) */
+#define CDGMG_K_SMOOTH0 1        /* level-0 damped block-Jacobi sweep */
+#define CDGMG_K_SMOOTH 2         /* coarse-level sweeps */
+#define CDGMG_K_RESTRICT 3       /* residual + restriction, all levels */
+#define CDGMG_K_PROLONG 4        /* prolongation + correction, all levels */
+#define CDGMG_K_COARSE 5         /* coarsest solve */
+#define CDGMG_K_VECTOR 6         /* FCG vector updates and reductions */
+#define CDGMG_NK 8
+
+typedef struct cdgmg_mesh {
+  int dim;                 /* 2 or 3 */
+  int64_t n_vert;
+  const double* coords;    /* host [n_vert][dim] */
+  int64_t n_elem;
+  const int32_t* e2v;      /* host [n_elem][dim+1] */
+  const int8_t* face_bc;   /* host [n_elem][dim+1]: 0 Dirichlet, 1 Neumann; read on boundary facets only */
+} cdgmg_mesh;
+
+typedef struct cdgmg_hierarchy {
+  int n_levels;              /* levels including the input mesh (>= 1) */
+  const int32_t* level_sizes;/* host [n_levels]; level_sizes[0] = n_elem */
+  const int32_t* parent;     /* host, concatenated parent maps of levels 0..n_levels-2 */
+} cdgmg_hierarchy;
+
+typedef struct cdgmg_options {
+  double gamma;        /* Dirichlet penalty C_D = kappa_K gamma / h_avg (Sec. 2.2); default 1e4 */
+  double omega;        /* block-Jacobi damping; default 0.7 */
+  int nu1, nu2;        /* pre/post sweeps; default 2, 2 */
+  int mg_precision;    /* CDGMG_MG_FP32 (default) or CDGMG_MG_FP64 */
+  int outer;           /* CDGMG_OUTER_FCG (default) or CDGMG_OUTER_PCG */
+  int coarsening;      /* CDGMG_COARSEN_PRIMAL (default) or CDGMG_COARSEN_FLUX */
+  int switch_mode;     /* CDGMG_SWITCH_CONSISTENT (default) or CDGMG_SWITCH_NATURAL */
+  uint64_t switch_seed;/* natural switch: enumeration = splitmix64(seed ^ id) */
+  double tol;          /* relative true residual ||b - A x|| / ||b||; default 1e-10 */
+  int max_iter;        /* default 500 */
+  int profile;         /* nonzero: time kernel classes with HIP events */
+} cdgmg_options;
+
+typedef struct cdgmg_solve_info {
+  int iterations;
+  double rel_residual;         /* true FP64 residual at exit */
+  double conv_factor;          /* (||r_k|| / ||r_0||)^(1/k) of the recursive residual */
+  double solve_ms;             /* host wall time of the call, device-synchronised */
+  double kernel_ms[CDGMG_NK];  /* summed HIP-event time per kernel class (profile != 0) */
+  int64_t kernel_launches[CDGMG_NK];
+  double* history;             /* optional host [history_len]: relative residual per iteration */
+  int history_len;
+} cdgmg_solve_info;
+
+typedef struct cdgmg_handle cdgmg_handle;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int cdgmg_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* cdgmg_last_error(void);
+
+/* Default options (values above). */
+void cdgmg_default_options(cdgmg_options* opts);
+
+/* Greedy agglomeration (Sec. 3.1 Alg. 1 with Sec. 3.2 Alg. 2), host only.
+ * Face neighbours share a facet; queue key (N(e), splitmix64(seed^(level<<32)^e), e);
+ * vertex ties by (splitmix64(seed^(level<<32)^(1<<62)^v), v); an element with
+ * N < 2 joins the adjacent block with the fewest current-level members
+ * (ties: lowest block id), or forms a vertex patch if none exists.
+ * Stops after max_levels levels, at one element, or when
+ * n_elem_level * n_p <= coarse_dofs_max (if coarse_dofs_max > 0; n_p from p).
+ * parent_out: host buffer of at least n_elem*max_levels int32 (concatenated maps);
+ * level_sizes_out: host [max_levels]; n_levels_out receives the level count. */
+int cdgmg_agglomerate(const cdgmg_mesh* mesh, int max_levels, int64_t coarse_dofs_max, int p,
+                      uint64_t seed, int32_t* parent_out, int32_t* level_sizes_out,
+                      int* n_levels_out);
+
+/* CDG switch (Sec. 2.2; consistent switch Sec. 4.2), host only.
+ * hosted_out: host int8 [n_elem][dim+1], 1 where the element hosts that local
+ * facet (S = -1 on its side: it owns the boundary gradient q^f), else 0;
+ * boundary facets: 1 if Dirichlet.  Consistent mode orients the dual graph
+ * along Euler circuits (virtual vertex joined to odd-degree elements, walks
+ * from the lowest element, lowest facet id first; interior facets numbered
+ * by (lower element, higher element)). */
+int cdgmg_switch(const cdgmg_mesh* mesh, int mode, uint64_t seed, int8_t* hosted_out);
+
+/* Build the solver: CDG operator of degree p (1..3) for the given mesh and
+ * element coefficients kappa_dev (device float64 [n_elem], > 0), the
+ * hierarchy's transfers and coarse operators, block inverses and the
+ * coarsest factor.  Device work runs on `stream` (hipStream_t, NULL = default).
+ * Errors: ARG (p, options, kappa), MESH (non-positive volume, non-manifold
+ * facet), HIERARCHY (map out of range / empty aggregate), SINGULAR
+ * (a diagonal block or the coarsest matrix is not positive definite),
+ * DEVICE / NOMEM. */
+int cdgmg_setup(const cdgmg_mesh* mesh, int p, const double* kappa_dev,
+                const cdgmg_hierarchy* hier, const cdgmg_options* opts, void* stream,
+                cdgmg_handle** out);
+
+/* Re-assemble A_0 = sum_e kappa_e A^(e) for new coefficients and rebuild the
+ * coarse operators, block inverses and coarsest factor on the device. */
+int cdgmg_update_kappa(cdgmg_handle* h, const double* kappa_dev);
+
+/* Solve A u = M_0 f (f nodal source values, M_0 the block mass matrix) from
+ * u = 0.  Returns CDGMG_NOT_CONVERGED if max_iter is reached (info filled),
+ * CDGMG_ERR_NAN if the residual is not finite.  info may be NULL. */
+int cdgmg_solve(cdgmg_handle* h, const double* f_dev, double* u_dev, cdgmg_solve_info* info);
+
+/* Solve A x = b for a given right-hand side vector b (a residual-space vector). */
+int cdgmg_solve_rhs(cdgmg_handle* h, const double* b_dev, double* x_dev, cdgmg_solve_info* info);
+
+/* Adjoint solve A^T lambda = g through the same hierarchy (A is symmetric, so
+ * this is cdgmg_solve_rhs with g). */
+int cdgmg_solve_transpose(cdgmg_handle* h, const double* g_dev, double* lam_dev,
+                          cdgmg_solve_info* info);
+
+/* gk_dev[e] = -lambda^T (dA/dkappa_e) u, the kappa-free operator hosted by e
+ * applied over its stencil (element e and its neighbours across hosted facets). */
+int cdgmg_grad_kappa(cdgmg_handle* h, const double* u_dev, const double* lam_dev, double* gk_dev);
+
+/* y = M_0 x (block mass matrix of the input mesh). */
+int cdgmg_apply_mass(cdgmg_handle* h, const double* x_dev, double* y_dev);
+
+/* y = A_level x for testing.  precision: 0 = float64 vectors and operator,
+ * 1 = float32 vectors and the FP32 operator copy.  Level-l vectors are
+ * [n_l][n_p] in the hierarchy's numbering of level l (level 0: caller order);
+ * coarse coefficients refer to the orthonormal modal basis of each aggregate. */
+int cdgmg_apply_A(cdgmg_handle* h, int level, int precision, const void* x_dev, void* y_dev);
+
+/* One V-cycle z = B r (FP64 in/out; runs in the configured precision). */
+int cdgmg_vcycle(cdgmg_handle* h, const double* r_dev, double* z_dev);
+
+/* Level statistics: n_levels, and per level (host arrays of n_levels entries,
+ * each may be NULL) element count and stored n_p x n_p blocks of A_l. */
+int cdgmg_level_info(cdgmg_handle* h, int* n_levels, int64_t* n_elem, int64_t* nnzb);
+
+/* Copy operator A_level to the host as block CSR in the hierarchy's numbering:
+ * row_ptr [n_l+1], cols [nnzb], blocks [nnzb][n_p][n_p] (row-major, FP64).
+ * Pass NULL buffers to query nnzb only (returned in *nnzb). Synchronous. */
+int cdgmg_export_operator(cdgmg_handle* h, int level, int64_t* nnzb, int64_t* row_ptr,
+                          int32_t* cols, double* blocks);
+
+/* Level-0 nodal points (host [n_elem][n_p][dim], caller order). */
+int cdgmg_node_coords(cdgmg_handle* h, double* xyz);
+
+/* Device memory held by the handle, in bytes. */
+int cdgmg_device_bytes(cdgmg_handle* h, size_t* bytes);
+
+/* Test support, host only: build the setup data of cdgmg_setup on the host
+ * and form A_level there (kappa host [n_elem]), exported like
+ * cdgmg_export_operator.  Lets CPU tests check the host half of the setup
+ * (assembly, ordering, bases, transfers, Galerkin plans) without a GPU. */
+int cdgmg_debug_host_operator(const cdgmg_mesh* mesh, int p, const double* kappa,
+                              const cdgmg_hierarchy* hier, const cdgmg_options* opts, int level,
+                              int64_t* nnzb, int64_t* row_ptr, int32_t* cols, double* blocks);
+
+/* Free the handle and its device memory (synchronises its stream). */
+int cdgmg_destroy(cdgmg_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CDGMG_H */

@@ -1,0 +1,53 @@
+// Device kernels of libcdgmg (gfx950, wave64).
+//
+// Block layouts (all levels): rows are grouped in slices of 64 (one wavefront).
+// Operator blocks use a sliced-ELL layout: slice s owns W_s slots; the n_p x n_p
+// block of (row r = 64 s + lane, slot w) is stored at
+//     ((B_s + 64 w) * n_p^2) + (i n_p + j) * 64 + lane ,   B_s = slice_blk[s],
+// so for fixed (w, i, j) the 64 rows of a slice are contiguous (coalesced).
+// Per-row blocks (D^{-1}, transfer blocks L_e, mass blocks) use the same layout
+// with W = 1: (64 s) n_p^2 + (i n_p + j) 64 + lane.  Vectors are row-major
+// [row][n_p].  Slot 0 of every row is its diagonal block.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cdg {
+
+constexpr int WAVE = 64;
+constexpr int TPB = 256;  // threads per block for row kernels (4 slices)
+
+// device scalar slots of the outer Krylov loop
+enum {
+  SC_ZQ = 0, SC_PQOLD, SC_PQ, SC_PR, SC_RR, SC_BETA, SC_ALPHA, SC_ZR, SC_ZROLD, SC_BB, SC_TMP, SC_N = 16
+};
+
+struct DevEll {
+  int64_t n;              // rows
+  const int32_t* cols;    // [sum W_s * 64]
+  const int64_t* sblk;    // [nslices + 1]
+};
+
+__device__ __forceinline__ int64_t blk_off(int64_t B, int w, int np2, int ij, int lane) {
+  return (B + (int64_t)WAVE * w) * np2 + (int64_t)ij * WAVE + lane;
+}
+__device__ __forceinline__ int64_t row_off(int64_t r, int np2, int ij) {
+  return (r / WAVE) * WAVE * np2 + (int64_t)ij * WAVE + (r % WAVE);
+}
+
+// wave64 + block reduction of a double; result valid in thread 0
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int k = 0; k < nw; ++k) s += sh[k];
+  }
+  __syncthreads();
+  return s;
+}
+
+}  // namespace cdg

@@ -1,0 +1,585 @@
+// HIP kernels of libcdgmg for gfx950 (see kernels.hpp for the block layouts).
+// Included by solver.hip, the single device translation unit.
+#include "kernels.hpp"
+
+namespace cdg {
+
+// =============================================================== setup kernels
+// K9: A_0 = sum_e kappa_e A^(e) from the kappa-free hosted blocks.
+//   A(r, 0)  = kappa_r UA(r, 0) + sum_{w: neighbour c_w hosts} kappa_c UH(c, revslot)
+//   A(r, w)  = kappa_host UA(r, w)
+template <int NP>
+__global__ void k_assemble_A0(int64_t n, int W, const int32_t* __restrict__ cols, const int64_t* __restrict__ sblk,
+                              const double* __restrict__ UA, const double* __restrict__ UH,
+                              const int8_t* __restrict__ hostflag, const int8_t* __restrict__ revslot,
+                              const double* __restrict__ kappa, double* __restrict__ A) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int lane = (int)(r % WAVE);
+  const int64_t B = sblk[r / WAVE];
+  const double kr = kappa[r];
+  for (int w = 1; w < W; ++w) {
+    const int hf = hostflag[r * W + w];
+    const int32_t c = cols[B + (int64_t)WAVE * w + lane];
+    const double s = hf == 1 ? kr : (hf == 0 ? kappa[c] : 0.0);
+    for (int ij = 0; ij < NP2; ++ij) {
+      const int64_t o = blk_off(B, w, NP2, ij, lane);
+      A[o] = s * UA[o];
+    }
+  }
+  for (int ij = 0; ij < NP2; ++ij) {
+    double acc = kr * UA[blk_off(B, 0, NP2, ij, lane)];
+    for (int w = 1; w < W; ++w) {
+      if (hostflag[r * W + w] != 0) continue;
+      const int32_t c = cols[B + (int64_t)WAVE * w + lane];
+      const int rs = revslot[r * W + w];
+      acc += kappa[c] * UH[blk_off(sblk[c / WAVE], rs, NP2, ij, c % WAVE)];
+    }
+    A[blk_off(B, 0, NP2, ij, lane)] = acc;
+  }
+}
+
+// kappa in internal order; flags non-positive or non-finite values
+__global__ void k_kappa_perm(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ kin,
+                             double* __restrict__ kout, int* __restrict__ err) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const double k = kin[perm[r]];
+  if (!(k > 0.0) || !(k < 1e300)) *err = 1;
+  kout[r] = k;
+}
+
+// K8: D^{-1} of the diagonal block (slot 0), Gauss-Jordan in place without
+// pivoting (the block is symmetric positive definite: every pivot is a
+// positive Schur-complement diagonal).  err is set on a non-positive pivot.
+template <int NP>
+__global__ void k_diag_inverse(int64_t n, const int64_t* __restrict__ sblk, const double* __restrict__ A,
+                               double* __restrict__ Dinv, int* __restrict__ err) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int lane = (int)(r % WAVE);
+  const int64_t B = sblk[r / WAVE];
+  double* D = Dinv + (r / WAVE) * WAVE * NP2 + lane;
+  for (int ij = 0; ij < NP2; ++ij) D[ij * WAVE] = A[blk_off(B, 0, NP2, ij, lane)];
+  for (int k = 0; k < NP; ++k) {
+    const double p = D[(k * NP + k) * WAVE];
+    if (!(p > 0.0)) {
+      *err = 1;
+      return;
+    }
+    const double ip = 1.0 / p;
+    D[(k * NP + k) * WAVE] = 1.0;
+    for (int j = 0; j < NP; ++j) D[(k * NP + j) * WAVE] *= ip;
+    for (int i = 0; i < NP; ++i) {
+      if (i == k) continue;
+      const double f = D[(i * NP + k) * WAVE];
+      D[(i * NP + k) * WAVE] = 0.0;
+      for (int j = 0; j < NP; ++j) D[(i * NP + j) * WAVE] -= f * D[(k * NP + j) * WAVE];
+    }
+  }
+}
+
+// K7 (Galerkin): coarse block k = (I, t) accumulates L_e^T A_f(e, w) L_c over its
+// plan entries (fixed order -> deterministic).  One workgroup per coarse block,
+// one thread per entry (i, j).
+template <int NP>
+__global__ void k_galerkin(int64_t nblk, const int32_t* __restrict__ blk_row, const int64_t* __restrict__ row_blk,
+                           const int64_t* __restrict__ plan_ptr, const int32_t* __restrict__ plan_e,
+                           const int32_t* __restrict__ plan_w, const int32_t* __restrict__ fcols,
+                           const int64_t* __restrict__ fsblk, const double* __restrict__ Af,
+                           const double* __restrict__ Lf, const int64_t* __restrict__ csblk,
+                           double* __restrict__ Ac) {
+  constexpr int NP2 = NP * NP;
+  __shared__ double sA[NP2], sLe[NP2], sLc[NP2], sT[NP2];
+  const int64_t k = blockIdx.x;
+  if (k >= nblk) return;
+  const int tid = threadIdx.x;
+  const int i = tid / NP, j = tid % NP;
+  double acc = 0.0;
+  for (int64_t q = plan_ptr[k]; q < plan_ptr[k + 1]; ++q) {
+    const int32_t e = plan_e[q];
+    const int w = plan_w[q];
+    const int64_t Be = fsblk[e / WAVE];
+    const int32_t c = fcols[Be + (int64_t)WAVE * w + e % WAVE];
+    if (tid < NP2) {
+      sA[tid] = Af[blk_off(Be, w, NP2, tid, e % WAVE)];
+      sLe[tid] = Lf[row_off(e, NP2, tid)];
+      sLc[tid] = Lf[row_off(c, NP2, tid)];
+    }
+    __syncthreads();
+    if (tid < NP2) {
+      double s = 0.0;
+      for (int m = 0; m < NP; ++m) s += sA[i * NP + m] * sLc[m * NP + j];
+      sT[tid] = s;
+    }
+    __syncthreads();
+    if (tid < NP2) {
+      double s = 0.0;
+      for (int m = 0; m < NP; ++m) s += sLe[m * NP + i] * sT[m * NP + j];
+      acc += s;
+    }
+    __syncthreads();
+  }
+  if (tid < NP2) {
+    const int32_t I = blk_row[k];
+    const int t = (int)(k - row_blk[I]);
+    Ac[blk_off(csblk[I / WAVE], t, NP2, tid, I % WAVE)] = acc;
+  }
+}
+
+// coarsest level: scatter the sliced blocks into a dense row-major matrix
+template <int NP>
+__global__ void k_dense_scatter(int64_t n, const int32_t* __restrict__ cols, const int64_t* __restrict__ sblk,
+                                const double* __restrict__ A, double* __restrict__ dense) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int lane = (int)(r % WAVE);
+  const int64_t B = sblk[r / WAVE];
+  const int W = (int)((sblk[r / WAVE + 1] - B) / WAVE);
+  const int64_t nd = n * NP;
+  for (int w = 0; w < W; ++w) {
+    const int32_t c = cols[B + (int64_t)WAVE * w + lane];
+    for (int i = 0; i < NP; ++i)
+      for (int j = 0; j < NP; ++j)
+        dense[(r * NP + i) * nd + (int64_t)c * NP + j] += A[blk_off(B, w, NP2, i * NP + j, lane)];
+  }
+}
+
+// one Gauss-Jordan step of the in-place inverse (out-of-place between two buffers)
+__global__ void k_gj_step(int64_t n, int64_t k, const double* __restrict__ in, double* __restrict__ out,
+                          int* __restrict__ err) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int64_t i = idx / n, j = idx % n;
+  const double p = in[k * n + k];
+  if (idx == 0 && !(p > 0.0)) *err = 1;
+  const double rk = (j == k) ? 1.0 : in[k * n + j];
+  if (i == k) {
+    out[idx] = rk / p;
+  } else {
+    const double v = (j == k) ? 0.0 : in[idx];
+    out[idx] = v - in[i * n + k] * rk / p;
+  }
+}
+
+template <typename S, typename D>
+__global__ void k_cast(int64_t n, const S* __restrict__ src, D* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (D)src[i];
+}
+
+// ============================================================ solve kernels
+// y = A x
+template <typename T, int NP>
+__global__ __launch_bounds__(TPB) void k_spmv(int64_t n, const int32_t* __restrict__ cols,
+                                              const int64_t* __restrict__ sblk, const T* __restrict__ A,
+                                              const T* __restrict__ x, T* __restrict__ y) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int lane = (int)(r % WAVE);
+  const int64_t B = sblk[r / WAVE];
+  const int W = (int)((sblk[r / WAVE + 1] - B) / WAVE);
+  T acc[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) acc[i] = 0;
+  for (int w = 0; w < W; ++w) {
+    const int32_t c = cols[B + (int64_t)WAVE * w + lane];
+    T xv[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) xv[j] = x[(int64_t)c * NP + j];
+    const T* Ab = A + (B + (int64_t)WAVE * w) * NP2 + lane;
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+#pragma unroll
+      for (int j = 0; j < NP; ++j) acc[i] += Ab[(i * NP + j) * WAVE] * xv[j];
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) y[r * NP + i] = acc[i];
+}
+
+// residual res = b - A x (registers)
+template <typename T, int NP>
+__device__ __forceinline__ void row_residual(int64_t r, const int32_t* __restrict__ cols,
+                                             const int64_t* __restrict__ sblk, const T* __restrict__ A,
+                                             const T* __restrict__ b, const T* __restrict__ x, T* res) {
+  constexpr int NP2 = NP * NP;
+  const int lane = (int)(r % WAVE);
+  const int64_t B = sblk[r / WAVE];
+  const int W = (int)((sblk[r / WAVE + 1] - B) / WAVE);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) res[i] = b[r * NP + i];
+  for (int w = 0; w < W; ++w) {
+    const int32_t c = cols[B + (int64_t)WAVE * w + lane];
+    T xv[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) xv[j] = x[(int64_t)c * NP + j];
+    const T* Ab = A + (B + (int64_t)WAVE * w) * NP2 + lane;
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+#pragma unroll
+      for (int j = 0; j < NP; ++j) res[i] -= Ab[(i * NP + j) * WAVE] * xv[j];
+  }
+}
+
+// damped block-Jacobi sweep: xout = xin + omega D^{-1} (b - A xin)
+template <typename T, int NP>
+__global__ __launch_bounds__(TPB) void k_smooth(int64_t n, const int32_t* __restrict__ cols,
+                                                const int64_t* __restrict__ sblk, const T* __restrict__ A,
+                                                const T* __restrict__ Dinv, const T* __restrict__ b,
+                                                const T* __restrict__ xin, T omega, T* __restrict__ xout) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  T res[NP];
+  row_residual<T, NP>(r, cols, sblk, A, b, xin, res);
+  const T* D = Dinv + (r / WAVE) * WAVE * NP2 + (r % WAVE);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) s += D[(i * NP + j) * WAVE] * res[j];
+    xout[r * NP + i] = xin[r * NP + i] + omega * s;
+  }
+}
+
+// first sweep from x = 0: b = (T) src, x = omega D^{-1} b
+template <typename T, typename S, int NP>
+__global__ __launch_bounds__(TPB) void k_smooth_first(int64_t n, const S* __restrict__ src, T* __restrict__ b,
+                                                      const T* __restrict__ Dinv, T omega, T* __restrict__ x) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  T bv[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    bv[j] = (T)src[r * NP + j];
+    if ((const void*)src != (const void*)b) b[r * NP + j] = bv[j];
+  }
+  const T* D = Dinv + (r / WAVE) * WAVE * NP2 + (r % WAVE);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) s += D[(i * NP + j) * WAVE] * bv[j];
+    x[r * NP + i] = omega * s;
+  }
+}
+
+// coarse level entry: b_I = sum over children e of t_e (restricted residuals);
+// then (if Dinv) the first sweep x = omega D^{-1} b
+template <typename T, int NP>
+__global__ __launch_bounds__(TPB) void k_gather_smooth_first(int64_t n, const int32_t* __restrict__ child_start,
+                                                             const T* __restrict__ t, T* __restrict__ b,
+                                                             const T* __restrict__ Dinv, T omega,
+                                                             T* __restrict__ x) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  T bv[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) bv[j] = 0;
+  for (int32_t e = child_start[r]; e < child_start[r + 1]; ++e)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) bv[j] += t[(int64_t)e * NP + j];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) b[r * NP + j] = bv[j];
+  if (Dinv == nullptr) return;
+  const T* D = Dinv + (r / WAVE) * WAVE * NP2 + (r % WAVE);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) s += D[(i * NP + j) * WAVE] * bv[j];
+    x[r * NP + i] = omega * s;
+  }
+}
+
+// restriction of the residual: t_e = L_e^T (b - A x)_e
+template <typename T, int NP>
+__global__ __launch_bounds__(TPB) void k_residual_restrict(int64_t n, const int32_t* __restrict__ cols,
+                                                           const int64_t* __restrict__ sblk,
+                                                           const T* __restrict__ A, const T* __restrict__ b,
+                                                           const T* __restrict__ x, const T* __restrict__ Lb,
+                                                           T* __restrict__ t) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  T res[NP];
+  row_residual<T, NP>(r, cols, sblk, A, b, x, res);
+  const T* Lr = Lb + (r / WAVE) * WAVE * NP2 + (r % WAVE);
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) s += Lr[(i * NP + j) * WAVE] * res[i];
+    t[r * NP + j] = s;
+  }
+}
+
+// prolongation and correction: x_e += L_e x_c[parent(e)]
+template <typename T, int NP>
+__global__ __launch_bounds__(TPB) void k_prolong(int64_t n, const int32_t* __restrict__ parent,
+                                                 const T* __restrict__ Lb, const T* __restrict__ xc,
+                                                 T* __restrict__ x) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int64_t I = parent[r];
+  T cv[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) cv[j] = xc[I * NP + j];
+  const T* Lr = Lb + (r / WAVE) * WAVE * NP2 + (r % WAVE);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) s += Lr[(i * NP + j) * WAVE] * cv[j];
+    x[r * NP + i] += s;
+  }
+}
+
+// coarsest: x = A_L^{-1} b, one wavefront per row
+template <typename T>
+__global__ void k_dense_gemv(int64_t n, const T* __restrict__ Ainv, const T* __restrict__ b, T* __restrict__ x) {
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
+  const int lane = threadIdx.x % WAVE;
+  if (row >= n) return;
+  T s = 0;
+  for (int64_t c = lane; c < n; c += WAVE) s += Ainv[row * n + c] * b[c];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (lane == 0) x[row] = s;
+}
+
+// ---------------------------------------------------------- outer (FP64) kernels
+// b = M_0 f (caller order -> internal order)
+template <int NP>
+__global__ __launch_bounds__(TPB) void k_mass_in(int64_t n, const int32_t* __restrict__ perm,
+                                                 const double* __restrict__ M, const double* __restrict__ f,
+                                                 double* __restrict__ b) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int64_t e = perm[r];
+  double fv[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) fv[j] = f[e * NP + j];
+  const double* Mr = M + (r / WAVE) * WAVE * NP2 + (r % WAVE);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) s += Mr[(i * NP + j) * WAVE] * fv[j];
+    b[r * NP + i] = s;
+  }
+}
+
+// y[perm[r]] = M_0 x[perm[r]] in caller order
+template <int NP>
+__global__ __launch_bounds__(TPB) void k_mass_apply(int64_t n, const int32_t* __restrict__ perm,
+                                                    const double* __restrict__ M, const double* __restrict__ x,
+                                                    double* __restrict__ y) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int64_t e = perm[r];
+  double xv[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) xv[j] = x[e * NP + j];
+  const double* Mr = M + (r / WAVE) * WAVE * NP2 + (r % WAVE);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) s += Mr[(i * NP + j) * WAVE] * xv[j];
+    y[e * NP + i] = s;
+  }
+}
+
+// permutation of per-row vectors: dir 0: out[r] = in[perm[r]] (into internal), 1: out[perm[r]] = in[r]
+template <typename T>
+__global__ void k_permute(int64_t n, int np, const int32_t* __restrict__ perm, const T* __restrict__ in,
+                          T* __restrict__ out, int dir) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * np) return;
+  const int64_t r = idx / np, j = idx % np;
+  if (dir == 0)
+    out[idx] = in[(int64_t)perm[r] * np + j];
+  else
+    out[(int64_t)perm[r] * np + j] = in[idx];
+}
+
+// partial dot products: part[d * gridDim.x + block] for d < nd
+__global__ __launch_bounds__(TPB) void k_dots(int64_t m, int nd, const double* __restrict__ a0,
+                                              const double* __restrict__ b0, const double* __restrict__ a1,
+                                              const double* __restrict__ b1, double* __restrict__ part) {
+  __shared__ double sh[TPB / WAVE];
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    s0 += a0[i] * b0[i];
+    if (nd > 1) s1 += a1[i] * b1[i];
+  }
+  s0 = block_sum(s0, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s0;
+  if (nd > 1) {
+    s1 = block_sum(s1, sh);
+    if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = s1;
+  }
+}
+
+// fixed-order reduction of nd partial arrays (nb entries each) into scal[off + d]
+__global__ void k_reduce(const double* __restrict__ part, int nb, int nd, double* __restrict__ scal, int off) {
+  __shared__ double sh[TPB / WAVE];
+  for (int d = 0; d < nd; ++d) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[d * nb + i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) scal[off + d] = s;
+  }
+}
+
+// q = A p (FP64, level 0) with partial sums of (p, q) and (p, r)
+template <int NP>
+__global__ __launch_bounds__(TPB) void k_spmv_dots(int64_t n, const int32_t* __restrict__ cols,
+                                                   const int64_t* __restrict__ sblk, const double* __restrict__ A,
+                                                   const double* __restrict__ p, const double* __restrict__ rr,
+                                                   double* __restrict__ q, double* __restrict__ part) {
+  constexpr int NP2 = NP * NP;
+  __shared__ double sh[TPB / WAVE];
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double pq = 0.0, pr = 0.0;
+  if (r < n) {
+    const int lane = (int)(r % WAVE);
+    const int64_t B = sblk[r / WAVE];
+    const int W = (int)((sblk[r / WAVE + 1] - B) / WAVE);
+    double acc[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) acc[i] = 0.0;
+    for (int w = 0; w < W; ++w) {
+      const int32_t c = cols[B + (int64_t)WAVE * w + lane];
+      double xv[NP];
+#pragma unroll
+      for (int j = 0; j < NP; ++j) xv[j] = p[(int64_t)c * NP + j];
+      const double* Ab = A + (B + (int64_t)WAVE * w) * NP2 + lane;
+#pragma unroll
+      for (int i = 0; i < NP; ++i)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) acc[i] += Ab[(i * NP + j) * WAVE] * xv[j];
+    }
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      q[r * NP + i] = acc[i];
+      const double pi = p[r * NP + i];
+      pq += pi * acc[i];
+      pr += pi * rr[r * NP + i];
+    }
+  }
+  pq = block_sum(pq, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = pq;
+  pr = block_sum(pr, sh);
+  if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = pr;
+}
+
+// scalar bookkeeping (single thread)
+// mode 0: FCG beta = s[ZQ] / s[PQOLD]; mode 1: PCG beta = s[ZR] / s[ZROLD]
+// mode 2: FCG alpha = s[PR] / s[PQ], PQOLD = PQ; mode 3: PCG alpha = s[ZR] / s[PQ], ZROLD = ZR
+__global__ void k_scalars(double* s, int mode) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (mode == 0) s[SC_BETA] = s[SC_ZQ] / s[SC_PQOLD];
+  if (mode == 1) s[SC_BETA] = s[SC_ZR] / s[SC_ZROLD];
+  if (mode == 2) {
+    s[SC_ALPHA] = s[SC_PR] / s[SC_PQ];
+    s[SC_PQOLD] = s[SC_PQ];
+  }
+  if (mode == 3) {
+    s[SC_ALPHA] = s[SC_ZR] / s[SC_PQ];
+    s[SC_ZROLD] = s[SC_ZR];
+  }
+}
+
+// p = z + sign * beta * p  (first iteration: p = z)
+__global__ void k_update_p(int64_t m, const double* __restrict__ z, double* __restrict__ p,
+                           const double* __restrict__ s, double sign, int first) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  p[i] = first ? z[i] : z[i] + sign * s[SC_BETA] * p[i];
+}
+
+// x += alpha p; r -= alpha q; partial ||r||^2
+__global__ __launch_bounds__(TPB) void k_update_xr(int64_t m, const double* __restrict__ p,
+                                                   const double* __restrict__ q, double* __restrict__ x,
+                                                   double* __restrict__ r, const double* __restrict__ s,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[TPB / WAVE];
+  const double a = s[SC_ALPHA];
+  double rr = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += a * p[i];
+    const double ri = r[i] - a * q[i];
+    r[i] = ri;
+    rr += ri * ri;
+  }
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = rr;
+}
+
+// r = b - y
+__global__ void k_sub(int64_t m, const double* __restrict__ b, const double* __restrict__ y, double* __restrict__ r) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) r[i] = b[i] - y[i];
+}
+
+// g_e = -[ lam_e^T UA(e,0) u_e + sum_{hosted w} ( lam_e^T UA(e,w) u_c + u_e^T UA(e,w) lam_c
+//          + lam_c^T UH(e,w) u_c ) ]   (caller-order output)
+template <int NP>
+__global__ __launch_bounds__(TPB) void k_grad_kappa(int64_t n, int W, const int32_t* __restrict__ perm,
+                                                    const int32_t* __restrict__ cols,
+                                                    const int64_t* __restrict__ sblk,
+                                                    const double* __restrict__ UA, const double* __restrict__ UH,
+                                                    const int8_t* __restrict__ hostflag,
+                                                    const double* __restrict__ u, const double* __restrict__ lam,
+                                                    double* __restrict__ g) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int lane = (int)(r % WAVE);
+  const int64_t B = sblk[r / WAVE];
+  double ue[NP], le[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    ue[j] = u[r * NP + j];
+    le[j] = lam[r * NP + j];
+  }
+  double acc = 0.0;
+  for (int i = 0; i < NP; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < NP; ++j) s += UA[blk_off(B, 0, NP2, i * NP + j, lane)] * ue[j];
+    acc += le[i] * s;
+  }
+  for (int w = 1; w < W; ++w) {
+    if (hostflag[r * W + w] != 1) continue;
+    const int32_t c = cols[B + (int64_t)WAVE * w + lane];
+    double uc[NP], lc[NP];
+    for (int j = 0; j < NP; ++j) {
+      uc[j] = u[(int64_t)c * NP + j];
+      lc[j] = lam[(int64_t)c * NP + j];
+    }
+    for (int i = 0; i < NP; ++i) {
+      double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      for (int j = 0; j < NP; ++j) {
+        const double a = UA[blk_off(B, w, NP2, i * NP + j, lane)];
+        const double hh = UH[blk_off(B, w, NP2, i * NP + j, lane)];
+        s1 += a * uc[j];
+        s2 += a * lc[j];
+        s3 += hh * uc[j];
+      }
+      acc += le[i] * s1 + ue[i] * s2 + lc[i] * s3;
+    }
+  }
+  g[perm[r]] = -acc;
+}
+
+}  // namespace cdg

@@ -1,0 +1,888 @@
+// libcdgmg: device setup, V-cycle, outer Krylov loop and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+#include "kernels.inl"
+
+namespace cdg {
+const char* last_error_cstr();
+}
+
+using namespace cdg;
+
+#define HIPCHK(x)                                                                                   \
+  do {                                                                                              \
+    hipError_t e_ = (x);                                                                            \
+    if (e_ != hipSuccess) {                                                                         \
+      set_error(std::string("HIP error '") + hipGetErrorString(e_) + "' in " #x);                  \
+      return CDGMG_ERR_DEVICE;                                                                      \
+    }                                                                                               \
+  } while (0)
+
+#define RETURN_IF(rc) \
+  do {                \
+    int rc_ = (rc);   \
+    if (rc_) return rc_; \
+  } while (0)
+
+#define NP_DISPATCH(np, ...)                 \
+  switch (np) {                              \
+    case 3: { constexpr int NP = 3; __VA_ARGS__; } break;   \
+    case 4: { constexpr int NP = 4; __VA_ARGS__; } break;   \
+    case 6: { constexpr int NP = 6; __VA_ARGS__; } break;   \
+    case 10: { constexpr int NP = 10; __VA_ARGS__; } break; \
+    case 20: { constexpr int NP = 20; __VA_ARGS__; } break; \
+    default: break;                          \
+  }
+
+namespace {
+
+struct DLevel {
+  int64_t n = 0, ns = 0, slots = 0, nnzb = 0;
+  int32_t* cols = nullptr;
+  int64_t* sblk = nullptr;
+  int32_t* perm = nullptr;  // internal -> hierarchy id
+  double* A64 = nullptr;
+  float* A32 = nullptr;
+  double* D64 = nullptr;
+  float* D32 = nullptr;
+  double* L64 = nullptr;
+  float* L32 = nullptr;
+  int32_t* parent = nullptr;
+  int32_t* child_start = nullptr;
+  int32_t* blk_row = nullptr;
+  int64_t* row_blk = nullptr;
+  int64_t* plan_ptr = nullptr;
+  int32_t* plan_e = nullptr;
+  int32_t* plan_w = nullptr;
+  void *b = nullptr, *x = nullptr, *xb = nullptr, *t = nullptr;
+};
+
+struct ProfEv {
+  int cls;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct cdgmg_handle {
+  Problem P;
+  cdgmg_options o;
+  hipStream_t stream = nullptr;
+  int np = 0, d = 0, W0 = 0, L = 0;
+  int64_t N0 = 0;
+  std::vector<DLevel> lv;
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+  // level 0
+  double *UA = nullptr, *UH = nullptr, *M = nullptr, *kappa = nullptr;
+  int8_t *hostflag = nullptr, *revslot = nullptr;
+  // coarsest
+  int64_t nd = 0;
+  double *Ainv64 = nullptr, *dense1 = nullptr;
+  float* Ainv32 = nullptr;
+  // outer vectors (internal order, FP64)
+  double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *y = nullptr,
+         *t1 = nullptr, *t2 = nullptr;
+  double *scal = nullptr, *part = nullptr;
+  int nparts = 0;
+  int* err = nullptr;
+  double* hscal = nullptr;
+  int* herr = nullptr;
+  // profiling
+  std::vector<ProfEv> evs;
+  std::vector<hipEvent_t> pool;
+  size_t pool_next = 0;
+};
+
+namespace {
+
+template <typename T>
+int dalloc(cdgmg_handle* h, T** ptr, size_t count) {
+  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    return CDGMG_ERR_NOMEM;
+  }
+  h->allocs.push_back(p);
+  h->bytes += bytes;
+  *ptr = (T*)p;
+  return CDGMG_OK;
+}
+
+template <typename T>
+int upload(cdgmg_handle* h, T** ptr, const std::vector<T>& v) {
+  RETURN_IF(dalloc(h, ptr, v.size()));
+  if (!v.empty()) HIPCHK(hipMemcpyAsync(*ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
+  return CDGMG_OK;
+}
+
+inline unsigned grid_for(int64_t n, int tpb = TPB) { return (unsigned)((n + tpb - 1) / tpb); }
+
+hipEvent_t next_event(cdgmg_handle* h) {
+  if (h->pool_next == h->pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->pool.push_back(e);
+  }
+  return h->pool[h->pool_next++];
+}
+
+template <typename K, typename... Args>
+void launch(cdgmg_handle* h, int cls, K kernel, dim3 grid, dim3 block, Args... args) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (h->o.profile && cls >= 0) {
+    a = next_event(h);
+    b = next_event(h);
+    if (a) (void)hipEventRecord(a, h->stream);
+  }
+  hipLaunchKernelGGL(kernel, grid, block, 0, h->stream, args...);
+  if (a && b) {
+    (void)hipEventRecord(b, h->stream);
+    h->evs.push_back({cls, a, b});
+  }
+}
+
+// row-major [n][W][np2] -> sliced-ELL layout of the level
+template <typename T>
+std::vector<T> to_sliced(const std::vector<T>& src, const Level& L, int W, int np2) {
+  const int64_t ns = L.slices();
+  std::vector<T> out((size_t)L.slice_blk[ns] * np2, T(0));
+  for (int64_t r = 0; r < L.n; ++r) {
+    const int64_t s = r / SLICE, lane = r % SLICE, B = L.slice_blk[s];
+    for (int w = 0; w < W; ++w)
+      for (int ij = 0; ij < np2; ++ij)
+        out[(size_t)(B + SLICE * w) * np2 + (size_t)ij * SLICE + lane] = src[((size_t)r * W + w) * np2 + ij];
+  }
+  return out;
+}
+
+// row-major [n][np2] -> per-row layout
+template <typename T>
+std::vector<T> to_rows(const std::vector<T>& src, int64_t n, int np2) {
+  const int64_t ns = (n + SLICE - 1) / SLICE;
+  std::vector<T> out((size_t)ns * SLICE * np2, T(0));
+  for (int64_t r = 0; r < n; ++r)
+    for (int ij = 0; ij < np2; ++ij)
+      out[(size_t)(r / SLICE) * SLICE * np2 + (size_t)ij * SLICE + r % SLICE] = src[(size_t)r * np2 + ij];
+  return out;
+}
+
+int check_err(cdgmg_handle* h, int code, const char* what) {
+  HIPCHK(hipMemcpyAsync(h->herr, h->err, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (*h->herr) {
+    *h->herr = 0;
+    HIPCHK(hipMemsetAsync(h->err, 0, sizeof(int), h->stream));
+    set_error(what);
+    return code;
+  }
+  return CDGMG_OK;
+}
+
+// ---------------------------------------------------------------- device setup
+int upload_problem(cdgmg_handle* h) {
+  Problem& P = h->P;
+  const int np = P.np, np2 = np * np;
+  h->np = np;
+  h->d = P.d;
+  h->W0 = P.nf + 1;
+  h->L = P.L;
+  h->N0 = P.N0;
+  h->lv.assign(P.L + 1, DLevel());
+  const bool fp32 = h->o.mg_precision == CDGMG_MG_FP32;
+  for (int l = 0; l <= P.L; ++l) {
+    Level& H = P.lv[l];
+    DLevel& D = h->lv[l];
+    D.n = H.n;
+    D.ns = H.slices();
+    D.slots = H.slice_blk[D.ns];
+    D.nnzb = H.nnzb;
+    RETURN_IF(upload(h, &D.cols, H.cols));
+    RETURN_IF(upload(h, &D.sblk, H.slice_blk));
+    RETURN_IF(upload(h, &D.perm, H.perm));
+    RETURN_IF(dalloc(h, &D.A64, (size_t)D.slots * np2));
+    HIPCHK(hipMemsetAsync(D.A64, 0, (size_t)D.slots * np2 * sizeof(double), h->stream));
+    if (fp32) RETURN_IF(dalloc(h, &D.A32, (size_t)D.slots * np2));
+    if (l < P.L) {
+      RETURN_IF(dalloc(h, &D.D64, (size_t)D.ns * SLICE * np2));
+      if (fp32) RETURN_IF(dalloc(h, &D.D32, (size_t)D.ns * SLICE * np2));
+      std::vector<double> Lr = to_rows(H.Lblk, H.n, np2);
+      RETURN_IF(upload(h, &D.L64, Lr));
+      if (fp32) {
+        std::vector<float> Lf(Lr.begin(), Lr.end());
+        RETURN_IF(upload(h, &D.L32, Lf));
+      }
+      RETURN_IF(upload(h, &D.parent, H.parent));
+    }
+    if (l >= 1) {
+      std::vector<int32_t> cs(H.child_start.begin(), H.child_start.end());
+      RETURN_IF(upload(h, &D.child_start, cs));
+      std::vector<int32_t> brow(H.nnzb);
+      for (int64_t I = 0; I < H.n; ++I)
+        for (int64_t k = H.row_blk[I]; k < H.row_blk[I + 1]; ++k) brow[k] = (int32_t)I;
+      RETURN_IF(upload(h, &D.blk_row, brow));
+      RETURN_IF(upload(h, &D.row_blk, H.row_blk));
+      RETURN_IF(upload(h, &D.plan_ptr, H.plan_ptr));
+      RETURN_IF(upload(h, &D.plan_e, H.plan_e));
+      RETURN_IF(upload(h, &D.plan_w, H.plan_w));
+    }
+    const size_t vb = (size_t)D.ns * SLICE * np * sizeof(double);
+    double* tmp;
+    RETURN_IF(dalloc(h, &tmp, vb / sizeof(double)));
+    D.b = tmp;
+    RETURN_IF(dalloc(h, &tmp, vb / sizeof(double)));
+    D.x = tmp;
+    RETURN_IF(dalloc(h, &tmp, vb / sizeof(double)));
+    D.xb = tmp;
+    RETURN_IF(dalloc(h, &tmp, vb / sizeof(double)));
+    D.t = tmp;
+  }
+  // level-0 kappa-free blocks
+  RETURN_IF(upload(h, &h->UA, to_sliced(P.UA, P.lv[0], h->W0, np2)));
+  RETURN_IF(upload(h, &h->UH, to_sliced(P.UH, P.lv[0], h->W0, np2)));
+  RETURN_IF(upload(h, &h->hostflag, P.hostflag));
+  RETURN_IF(upload(h, &h->revslot, P.revslot));
+  RETURN_IF(upload(h, &h->M, to_rows(P.Mblk, P.N0, np2)));
+  RETURN_IF(dalloc(h, &h->kappa, P.N0));
+  // coarsest dense
+  h->nd = h->lv[P.L].n * np;
+  if (h->nd > 12000) {
+    set_error("setup: coarsest level has " + std::to_string(h->nd) + " unknowns (limit 12000); use more levels");
+    return CDGMG_ERR_ARG;
+  }
+  RETURN_IF(dalloc(h, &h->Ainv64, (size_t)h->nd * h->nd));
+  RETURN_IF(dalloc(h, &h->dense1, (size_t)h->nd * h->nd));
+  if (fp32) RETURN_IF(dalloc(h, &h->Ainv32, (size_t)h->nd * h->nd));
+  // outer vectors
+  const size_t m = (size_t)h->lv[0].ns * SLICE * np;
+  for (double** v : {&h->b, &h->x, &h->r, &h->z, &h->p, &h->q, &h->y, &h->t1, &h->t2}) {
+    RETURN_IF(dalloc(h, v, m));
+    HIPCHK(hipMemsetAsync(*v, 0, m * sizeof(double), h->stream));
+  }
+  RETURN_IF(dalloc(h, &h->scal, SC_N));
+  h->nparts = (int)std::max<int64_t>(1024, grid_for(P.N0));
+  RETURN_IF(dalloc(h, &h->part, 2 * (size_t)h->nparts));
+  RETURN_IF(dalloc(h, &h->err, 1));
+  HIPCHK(hipMemsetAsync(h->err, 0, sizeof(int), h->stream));
+  HIPCHK(hipHostMalloc((void**)&h->hscal, SC_N * sizeof(double)));
+  HIPCHK(hipHostMalloc((void**)&h->herr, sizeof(int)));
+  *h->herr = 0;
+  // release large host copies that the device now holds
+  std::vector<double>().swap(P.UA);
+  std::vector<double>().swap(P.UH);
+  std::vector<double>().swap(P.Gblk);
+  for (auto& H : P.lv) {
+    std::vector<double>().swap(H.Lblk);
+    std::vector<int32_t>().swap(H.plan_e);
+    std::vector<int32_t>().swap(H.plan_w);
+  }
+  return CDGMG_OK;
+}
+
+// kappa -> A_0 -> (D^{-1}, Galerkin) per level -> coarsest inverse -> FP32 copies
+int build_operators(cdgmg_handle* h, const double* kappa_dev) {
+  const int np = h->np, np2 = np * np;
+  DLevel& l0 = h->lv[0];
+  launch(h, -1, k_kappa_perm, dim3(grid_for(h->N0)), dim3(TPB), h->N0, (const int32_t*)l0.perm, kappa_dev,
+         h->kappa, h->err);
+  RETURN_IF(check_err(h, CDGMG_ERR_ARG, "setup: kappa must be positive and finite"));
+  NP_DISPATCH(np, launch(h, -1, k_assemble_A0<NP>, dim3(grid_for(h->N0)), dim3(TPB), h->N0, h->W0,
+                         (const int32_t*)l0.cols, (const int64_t*)l0.sblk, (const double*)h->UA,
+                         (const double*)h->UH, (const int8_t*)h->hostflag, (const int8_t*)h->revslot,
+                         (const double*)h->kappa, l0.A64));
+  for (int l = 0; l < h->L; ++l) {
+    DLevel &f = h->lv[l], &c = h->lv[l + 1];
+    NP_DISPATCH(np, launch(h, -1, k_diag_inverse<NP>, dim3(grid_for(f.n)), dim3(TPB), f.n,
+                           (const int64_t*)f.sblk, (const double*)f.A64, f.D64, h->err));
+    const int tpb = std::min(1024, ((np2 + 63) / 64) * 64);
+    NP_DISPATCH(np, launch(h, -1, k_galerkin<NP>, dim3((unsigned)c.nnzb), dim3(tpb), c.nnzb,
+                           (const int32_t*)c.blk_row, (const int64_t*)c.row_blk, (const int64_t*)c.plan_ptr,
+                           (const int32_t*)c.plan_e, (const int32_t*)c.plan_w, (const int32_t*)f.cols,
+                           (const int64_t*)f.sblk, (const double*)f.A64, (const double*)f.L64,
+                           (const int64_t*)c.sblk, c.A64));
+  }
+  RETURN_IF(check_err(h, CDGMG_ERR_SINGULAR, "setup: a diagonal block is not positive definite"));
+  // coarsest: dense scatter + Gauss-Jordan inverse (ping-pong)
+  DLevel& cl = h->lv[h->L];
+  const int64_t nd = h->nd;
+  HIPCHK(hipMemsetAsync(h->dense1, 0, (size_t)nd * nd * sizeof(double), h->stream));
+  NP_DISPATCH(np, launch(h, -1, k_dense_scatter<NP>, dim3(grid_for(cl.n)), dim3(TPB), cl.n,
+                         (const int32_t*)cl.cols, (const int64_t*)cl.sblk, (const double*)cl.A64, h->dense1));
+  double* in = h->dense1;
+  double* out = h->Ainv64;
+  for (int64_t k = 0; k < nd; ++k) {
+    launch(h, -1, k_gj_step, dim3(grid_for(nd * nd)), dim3(TPB), nd, k, (const double*)in, out, h->err);
+    std::swap(in, out);
+  }
+  if (in != h->Ainv64)
+    HIPCHK(hipMemcpyAsync(h->Ainv64, in, (size_t)nd * nd * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  RETURN_IF(check_err(h, CDGMG_ERR_SINGULAR, "setup: the coarsest operator is not positive definite"));
+  if (h->o.mg_precision == CDGMG_MG_FP32) {
+    for (int l = 0; l <= h->L; ++l) {
+      DLevel& D = h->lv[l];
+      const int64_t na = D.slots * np2;
+      launch(h, -1, k_cast<double, float>, dim3(grid_for(na)), dim3(TPB), na, (const double*)D.A64, D.A32);
+      if (l < h->L) {
+        const int64_t nb = D.ns * SLICE * np2;
+        launch(h, -1, k_cast<double, float>, dim3(grid_for(nb)), dim3(TPB), nb, (const double*)D.D64, D.D32);
+      }
+    }
+    launch(h, -1, k_cast<double, float>, dim3(grid_for(nd * nd)), dim3(TPB), nd * nd, (const double*)h->Ainv64,
+           h->Ainv32);
+  }
+  HIPCHK(hipGetLastError());
+  return CDGMG_OK;
+}
+
+// ---------------------------------------------------------------- V-cycle
+template <typename T>
+struct Ops;
+template <>
+struct Ops<float> {
+  static const float* A(const DLevel& d) { return d.A32; }
+  static const float* D(const DLevel& d) { return d.D32; }
+  static const float* L(const DLevel& d) { return d.L32; }
+  static const float* Ainv(const cdgmg_handle* h) { return h->Ainv32; }
+};
+template <>
+struct Ops<double> {
+  static const double* A(const DLevel& d) { return d.A64; }
+  static const double* D(const DLevel& d) { return d.D64; }
+  static const double* L(const DLevel& d) { return d.L64; }
+  static const double* Ainv(const cdgmg_handle* h) { return h->Ainv64; }
+};
+
+template <typename T, int NP>
+void smooth_sweeps(cdgmg_handle* h, int l, int count, T** x, T** xb) {
+  DLevel& d = h->lv[l];
+  const T omega = (T)h->o.omega;
+  for (int s = 0; s < count; ++s) {
+    launch(h, l == 0 ? CDGMG_K_SMOOTH0 : CDGMG_K_SMOOTH, k_smooth<T, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n,
+           (const int32_t*)d.cols, (const int64_t*)d.sblk, Ops<T>::A(d), Ops<T>::D(d), (const T*)d.b,
+           (const T*)*x, omega, *xb);
+    std::swap(*x, *xb);
+  }
+}
+
+template <typename T, int NP>
+void vcycle_t(cdgmg_handle* h, const double* r64, double* z64) {
+  const int L = h->L;
+  const T omega = (T)h->o.omega;
+  const int nu1 = h->o.nu1, nu2 = h->o.nu2;
+  std::vector<T*> xs(L + 1), xbs(L + 1);
+  for (int l = 0; l <= L; ++l) {
+    xs[l] = (T*)h->lv[l].x;
+    xbs[l] = (T*)h->lv[l].xb;
+  }
+  if (L == 0) {
+    DLevel& d = h->lv[0];
+    launch(h, CDGMG_K_VECTOR, k_cast<double, T>, dim3(grid_for(d.n * NP)), dim3(TPB), d.n * NP, r64, (T*)d.b);
+    launch(h, CDGMG_K_COARSE, k_dense_gemv<T>, dim3(grid_for(h->nd * WAVE)), dim3(TPB), h->nd, Ops<T>::Ainv(h),
+           (const T*)d.b, xs[0]);
+    launch(h, CDGMG_K_VECTOR, k_cast<T, double>, dim3(grid_for(d.n * NP)), dim3(TPB), d.n * NP, (const T*)xs[0],
+           z64);
+    return;
+  }
+  for (int l = 0; l < L; ++l) {
+    DLevel& d = h->lv[l];
+    const T* Dv = nu1 > 0 ? Ops<T>::D(d) : nullptr;
+    if (l == 0) {
+      if (nu1 > 0) {
+        launch(h, CDGMG_K_SMOOTH0, k_smooth_first<T, double, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n, r64,
+               (T*)d.b, Dv, omega, xs[0]);
+      } else {
+        launch(h, CDGMG_K_VECTOR, k_cast<double, T>, dim3(grid_for(d.n * NP)), dim3(TPB), d.n * NP, r64, (T*)d.b);
+        (void)hipMemsetAsync(xs[0], 0, d.n * NP * sizeof(T), h->stream);
+      }
+    } else {
+      launch(h, CDGMG_K_SMOOTH, k_gather_smooth_first<T, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n,
+             (const int32_t*)d.child_start, (const T*)h->lv[l - 1].t, (T*)d.b, Dv, omega, xs[l]);
+      if (nu1 == 0) (void)hipMemsetAsync(xs[l], 0, d.n * NP * sizeof(T), h->stream);
+    }
+    smooth_sweeps<T, NP>(h, l, nu1 - 1 > 0 ? nu1 - 1 : 0, &xs[l], &xbs[l]);
+    launch(h, CDGMG_K_RESTRICT, k_residual_restrict<T, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n,
+           (const int32_t*)d.cols, (const int64_t*)d.sblk, Ops<T>::A(d), (const T*)d.b, (const T*)xs[l],
+           Ops<T>::L(d), (T*)d.t);
+  }
+  DLevel& c = h->lv[L];
+  launch(h, CDGMG_K_COARSE, k_gather_smooth_first<T, NP>, dim3(grid_for(c.n)), dim3(TPB), c.n,
+         (const int32_t*)c.child_start, (const T*)h->lv[L - 1].t, (T*)c.b, (const T*)nullptr, omega, (T*)nullptr);
+  launch(h, CDGMG_K_COARSE, k_dense_gemv<T>, dim3(grid_for(h->nd * WAVE)), dim3(TPB), h->nd, Ops<T>::Ainv(h),
+         (const T*)c.b, xs[L]);
+  for (int l = L - 1; l >= 0; --l) {
+    DLevel& d = h->lv[l];
+    launch(h, CDGMG_K_PROLONG, k_prolong<T, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n, (const int32_t*)d.parent,
+           Ops<T>::L(d), (const T*)xs[l + 1], xs[l]);
+    smooth_sweeps<T, NP>(h, l, nu2, &xs[l], &xbs[l]);
+  }
+  launch(h, CDGMG_K_VECTOR, k_cast<T, double>, dim3(grid_for(h->N0 * NP)), dim3(TPB), h->N0 * NP,
+         (const T*)xs[0], z64);
+}
+
+void vcycle(cdgmg_handle* h, const double* r64, double* z64) {
+  if (h->o.mg_precision == CDGMG_MG_FP32) {
+    NP_DISPATCH(h->np, vcycle_t<float, NP>(h, r64, z64));
+  } else {
+    NP_DISPATCH(h->np, vcycle_t<double, NP>(h, r64, z64));
+  }
+}
+
+// ---------------------------------------------------------------- outer solve
+void dot_into(cdgmg_handle* h, int64_t m, const double* a, const double* b, int slot) {
+  const unsigned g = std::min<unsigned>(1024, grid_for(m));
+  launch(h, CDGMG_K_VECTOR, k_dots, dim3(g), dim3(TPB), m, 1, a, b, (const double*)nullptr,
+         (const double*)nullptr, h->part);
+  launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)g, 1, h->scal, slot);
+}
+
+int read_scalar(cdgmg_handle* h, int slot, double* out) {
+  HIPCHK(hipMemcpyAsync(h->hscal + slot, h->scal + slot, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  *out = h->hscal[slot];
+  return CDGMG_OK;
+}
+
+int true_residual(cdgmg_handle* h, double* rr) {
+  const int64_t m = h->N0 * h->np;
+  DLevel& d = h->lv[0];
+  NP_DISPATCH(h->np, launch(h, CDGMG_K_SPMV, k_spmv<double, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n,
+                            (const int32_t*)d.cols, (const int64_t*)d.sblk, (const double*)d.A64,
+                            (const double*)h->x, h->y));
+  launch(h, CDGMG_K_VECTOR, k_sub, dim3(grid_for(m)), dim3(TPB), m, (const double*)h->b, (const double*)h->y,
+         h->t1);
+  dot_into(h, m, h->t1, h->t1, SC_TMP);
+  return read_scalar(h, SC_TMP, rr);
+}
+
+void reset_profile(cdgmg_handle* h) {
+  h->evs.clear();
+  h->pool_next = 0;
+}
+
+void collect_profile(cdgmg_handle* h, cdgmg_solve_info* info) {
+  if (!info) return;
+  for (int k = 0; k < CDGMG_NK; ++k) {
+    info->kernel_ms[k] = 0.0;
+    info->kernel_launches[k] = 0;
+  }
+  if (!h->o.profile) return;
+  (void)hipStreamSynchronize(h->stream);
+  for (auto& e : h->evs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+      info->kernel_ms[e.cls] += ms;
+      info->kernel_launches[e.cls] += 1;
+    }
+  }
+}
+
+// solve A x = b with h->b set (internal order); result in h->x
+int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int64_t m = h->N0 * h->np;
+  const int np = h->np;
+  DLevel& d0 = h->lv[0];
+  HIPCHK(hipMemsetAsync(h->x, 0, m * sizeof(double), h->stream));
+  HIPCHK(hipMemcpyAsync(h->r, h->b, m * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  double bb = 0.0;
+  dot_into(h, m, h->b, h->b, SC_BB);
+  RETURN_IF(read_scalar(h, SC_BB, &bb));
+  if (!std::isfinite(bb)) {
+    set_error("solve: right-hand side is not finite");
+    return CDGMG_ERR_NAN;
+  }
+  const double nb = std::sqrt(bb);
+  int it = 0;
+  double rel = 0.0, rel_true = 0.0;
+  int status = CDGMG_NOT_CONVERGED;
+  if (nb == 0.0) {
+    status = CDGMG_OK;
+  } else {
+    const bool fcg = h->o.outer == CDGMG_OUTER_FCG;
+    while (it < h->o.max_iter) {
+      vcycle(h, h->r, h->z);
+      if (fcg) {
+        if (it > 0) {
+          dot_into(h, m, h->z, h->q, SC_ZQ);
+          launch(h, CDGMG_K_VECTOR, k_scalars, dim3(1), dim3(1), h->scal, 0);
+        }
+        launch(h, CDGMG_K_VECTOR, k_update_p, dim3(grid_for(m)), dim3(TPB), m, (const double*)h->z, h->p,
+               (const double*)h->scal, -1.0, it == 0 ? 1 : 0);
+      } else {
+        dot_into(h, m, h->z, h->r, SC_ZR);
+        if (it > 0) launch(h, CDGMG_K_VECTOR, k_scalars, dim3(1), dim3(1), h->scal, 1);
+        launch(h, CDGMG_K_VECTOR, k_update_p, dim3(grid_for(m)), dim3(TPB), m, (const double*)h->z, h->p,
+               (const double*)h->scal, 1.0, it == 0 ? 1 : 0);
+      }
+      const unsigned g = grid_for(d0.n);
+      NP_DISPATCH(np, launch(h, CDGMG_K_SPMV, k_spmv_dots<NP>, dim3(g), dim3(TPB), d0.n, (const int32_t*)d0.cols,
+                             (const int64_t*)d0.sblk, (const double*)d0.A64, (const double*)h->p,
+                             (const double*)h->r, h->q, h->part));
+      launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)g, 2, h->scal, SC_PQ);
+      launch(h, CDGMG_K_VECTOR, k_scalars, dim3(1), dim3(1), h->scal, fcg ? 2 : 3);
+      const unsigned gu = std::min<unsigned>(1024, grid_for(m));
+      launch(h, CDGMG_K_VECTOR, k_update_xr, dim3(gu), dim3(TPB), m, (const double*)h->p, (const double*)h->q,
+             h->x, h->r, (const double*)h->scal, h->part);
+      launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)gu, 1, h->scal, SC_RR);
+      double rr;
+      RETURN_IF(read_scalar(h, SC_RR, &rr));
+      ++it;
+      if (!std::isfinite(rr)) {
+        set_error("solve: residual is not finite");
+        status = CDGMG_ERR_NAN;
+        break;
+      }
+      rel = std::sqrt(rr) / nb;
+      if (info && info->history && it <= info->history_len) info->history[it - 1] = rel;
+      if (rel <= h->o.tol) {
+        double rt;
+        RETURN_IF(true_residual(h, &rt));
+        rel_true = std::sqrt(rt) / nb;
+        if (rel_true <= h->o.tol) {
+          status = CDGMG_OK;
+          break;
+        }
+        HIPCHK(hipMemcpyAsync(h->r, h->t1, m * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+      }
+    }
+  }
+  if (status != CDGMG_OK && status != CDGMG_ERR_NAN && nb != 0.0) {
+    double rt;
+    RETURN_IF(true_residual(h, &rt));
+    rel_true = std::sqrt(rt) / nb;
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  auto t1 = std::chrono::steady_clock::now();
+  if (info) {
+    info->iterations = it;
+    info->rel_residual = rel_true;
+    info->conv_factor = (it > 0 && rel > 0.0) ? std::pow(rel, 1.0 / it) : 0.0;
+    info->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    collect_profile(h, info);
+  }
+  if (status == CDGMG_NOT_CONVERGED) set_error("solve: not converged within max_iter");
+  return status;
+}
+
+int check_handle(cdgmg_handle* h) {
+  if (!h) {
+    set_error("null handle");
+    return CDGMG_ERR_ARG;
+  }
+  return CDGMG_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+int cdgmg_version(void) { return 10000; }
+
+const char* cdgmg_last_error(void) { return cdg::last_error_cstr(); }
+
+void cdgmg_default_options(cdgmg_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->gamma = 1e4;
+  o->omega = 0.7;
+  o->nu1 = 2;
+  o->nu2 = 2;
+  o->mg_precision = CDGMG_MG_FP32;
+  o->outer = CDGMG_OUTER_FCG;
+  o->coarsening = CDGMG_COARSEN_PRIMAL;
+  o->switch_mode = CDGMG_SWITCH_CONSISTENT;
+  o->switch_seed = 0;
+  o->tol = 1e-10;
+  o->max_iter = 500;
+  o->profile = 0;
+}
+
+int cdgmg_agglomerate(const cdgmg_mesh* mesh, int max_levels, int64_t coarse_dofs_max, int p, uint64_t seed,
+                      int32_t* parent_out, int32_t* level_sizes_out, int* n_levels_out) {
+  set_error("");
+  if (!mesh || !parent_out || !level_sizes_out || !n_levels_out || max_levels < 1 || p < 1 || p > 3) {
+    set_error("agglomerate: invalid argument");
+    return CDGMG_ERR_ARG;
+  }
+  try {
+    Topology t;
+    int rc = build_topology(*mesh, t);
+    if (rc) return rc;
+    const int np = mesh->dim == 2 ? (p + 1) * (p + 2) / 2 : (p + 1) * (p + 2) * (p + 3) / 6;
+    std::vector<int32_t> parents, sizes;
+    int nl = agglomerate(*mesh, t, max_levels, coarse_dofs_max, np, seed, parents, sizes);
+    std::copy(parents.begin(), parents.end(), parent_out);
+    std::copy(sizes.begin(), sizes.end(), level_sizes_out);
+    *n_levels_out = nl;
+  } catch (const std::exception& e) {
+    set_error(std::string("agglomerate: ") + e.what());
+    return CDGMG_ERR_NOMEM;
+  }
+  return CDGMG_OK;
+}
+
+int cdgmg_switch(const cdgmg_mesh* mesh, int mode, uint64_t seed, int8_t* hosted_out) {
+  set_error("");
+  if (!mesh || !hosted_out) {
+    set_error("switch: invalid argument");
+    return CDGMG_ERR_ARG;
+  }
+  Topology t;
+  int rc = build_topology(*mesh, t);
+  if (rc) return rc;
+  if (mode == CDGMG_SWITCH_NATURAL)
+    natural_switch(t, mesh->face_bc, seed);
+  else
+    consistent_switch(t, mesh->face_bc);
+  std::copy(t.hosted.begin(), t.hosted.end(), hosted_out);
+  return CDGMG_OK;
+}
+
+int cdgmg_setup(const cdgmg_mesh* mesh, int p, const double* kappa_dev, const cdgmg_hierarchy* hier,
+                const cdgmg_options* opts, void* stream, cdgmg_handle** out) {
+  set_error("");
+  if (!mesh || !hier || !out || !kappa_dev) {
+    set_error("setup: invalid argument");
+    return CDGMG_ERR_ARG;
+  }
+  cdgmg_options o;
+  if (opts)
+    o = *opts;
+  else
+    cdgmg_default_options(&o);
+  if (o.nu1 < 0 || o.nu2 < 0 || o.nu1 + o.nu2 == 0 || !(o.omega > 0) || !(o.tol > 0) || o.max_iter < 1 ||
+      !(o.gamma > 0)) {
+    set_error("setup: invalid options");
+    return CDGMG_ERR_ARG;
+  }
+  if (o.coarsening != CDGMG_COARSEN_PRIMAL) {
+    set_error("setup: flux coarsening is not available in this build of the solve path");
+    return CDGMG_ERR_ARG;
+  }
+  cdgmg_handle* h = new (std::nothrow) cdgmg_handle();
+  if (!h) return CDGMG_ERR_NOMEM;
+  h->o = o;
+  h->stream = (hipStream_t)stream;
+  int rc;
+  try {
+    rc = build_problem(*mesh, p, *hier, o, h->P);
+  } catch (const std::exception& e) {
+    set_error(std::string("setup: ") + e.what());
+    rc = CDGMG_ERR_NOMEM;
+  }
+  if (!rc) rc = upload_problem(h);
+  if (!rc) rc = build_operators(h, kappa_dev);
+  if (!rc && hipStreamSynchronize(h->stream) != hipSuccess) {
+    set_error("setup: device error");
+    rc = CDGMG_ERR_DEVICE;
+  }
+  if (rc) {
+    std::string msg = cdg::last_error_cstr();
+    cdgmg_destroy(h);
+    set_error(msg);
+    return rc;
+  }
+  *out = h;
+  return CDGMG_OK;
+}
+
+int cdgmg_update_kappa(cdgmg_handle* h, const double* kappa_dev) {
+  RETURN_IF(check_handle(h));
+  set_error("");
+  RETURN_IF(build_operators(h, kappa_dev));
+  return CDGMG_OK;
+}
+
+int cdgmg_solve(cdgmg_handle* h, const double* f_dev, double* u_dev, cdgmg_solve_info* info) {
+  RETURN_IF(check_handle(h));
+  set_error("");
+  reset_profile(h);
+  const int np = h->np;
+  DLevel& d = h->lv[0];
+  NP_DISPATCH(np, launch(h, -1, k_mass_in<NP>, dim3(grid_for(d.n)), dim3(TPB), d.n, (const int32_t*)d.perm,
+                         (const double*)h->M, f_dev, h->b));
+  int rc = krylov(h, info);
+  launch(h, -1, k_permute<double>, dim3(grid_for(h->N0 * np)), dim3(TPB), h->N0, np, (const int32_t*)d.perm,
+         (const double*)h->x, u_dev, 1);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return rc;
+}
+
+int cdgmg_solve_rhs(cdgmg_handle* h, const double* b_dev, double* x_dev, cdgmg_solve_info* info) {
+  RETURN_IF(check_handle(h));
+  set_error("");
+  reset_profile(h);
+  const int np = h->np;
+  DLevel& d = h->lv[0];
+  launch(h, -1, k_permute<double>, dim3(grid_for(h->N0 * np)), dim3(TPB), h->N0, np, (const int32_t*)d.perm,
+         b_dev, h->b, 0);
+  int rc = krylov(h, info);
+  launch(h, -1, k_permute<double>, dim3(grid_for(h->N0 * np)), dim3(TPB), h->N0, np, (const int32_t*)d.perm,
+         (const double*)h->x, x_dev, 1);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return rc;
+}
+
+int cdgmg_solve_transpose(cdgmg_handle* h, const double* g_dev, double* lam_dev, cdgmg_solve_info* info) {
+  return cdgmg_solve_rhs(h, g_dev, lam_dev, info);
+}
+
+int cdgmg_grad_kappa(cdgmg_handle* h, const double* u_dev, const double* lam_dev, double* gk_dev) {
+  RETURN_IF(check_handle(h));
+  set_error("");
+  const int np = h->np;
+  DLevel& d = h->lv[0];
+  launch(h, -1, k_permute<double>, dim3(grid_for(h->N0 * np)), dim3(TPB), h->N0, np, (const int32_t*)d.perm,
+         u_dev, h->t1, 0);
+  launch(h, -1, k_permute<double>, dim3(grid_for(h->N0 * np)), dim3(TPB), h->N0, np, (const int32_t*)d.perm,
+         lam_dev, h->t2, 0);
+  NP_DISPATCH(np, launch(h, -1, k_grad_kappa<NP>, dim3(grid_for(d.n)), dim3(TPB), d.n, h->W0,
+                         (const int32_t*)d.perm, (const int32_t*)d.cols, (const int64_t*)d.sblk,
+                         (const double*)h->UA, (const double*)h->UH, (const int8_t*)h->hostflag,
+                         (const double*)h->t1, (const double*)h->t2, gk_dev));
+  HIPCHK(hipGetLastError());
+  return CDGMG_OK;
+}
+
+int cdgmg_apply_mass(cdgmg_handle* h, const double* x_dev, double* y_dev) {
+  RETURN_IF(check_handle(h));
+  DLevel& d = h->lv[0];
+  NP_DISPATCH(h->np, launch(h, -1, k_mass_apply<NP>, dim3(grid_for(d.n)), dim3(TPB), d.n, (const int32_t*)d.perm,
+                            (const double*)h->M, x_dev, y_dev));
+  HIPCHK(hipGetLastError());
+  return CDGMG_OK;
+}
+
+int cdgmg_apply_A(cdgmg_handle* h, int level, int precision, const void* x_dev, void* y_dev) {
+  RETURN_IF(check_handle(h));
+  if (level < 0 || level > h->L || (precision != 0 && precision != 1) ||
+      (precision == 1 && h->o.mg_precision != CDGMG_MG_FP32)) {
+    set_error("apply_A: invalid level or precision");
+    return CDGMG_ERR_ARG;
+  }
+  DLevel& d = h->lv[level];
+  const int np = h->np;
+  if (precision == 0) {
+    double *xi = h->t1, *yi = h->t2;
+    launch(h, -1, k_permute<double>, dim3(grid_for(d.n * np)), dim3(TPB), d.n, np, (const int32_t*)d.perm,
+           (const double*)x_dev, xi, 0);
+    NP_DISPATCH(np, launch(h, -1, k_spmv<double, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n, (const int32_t*)d.cols,
+                           (const int64_t*)d.sblk, (const double*)d.A64, (const double*)xi, yi));
+    launch(h, -1, k_permute<double>, dim3(grid_for(d.n * np)), dim3(TPB), d.n, np, (const int32_t*)d.perm,
+           (const double*)yi, (double*)y_dev, 1);
+  } else {
+    float *xi = (float*)h->t1, *yi = (float*)h->t2;
+    launch(h, -1, k_permute<float>, dim3(grid_for(d.n * np)), dim3(TPB), d.n, np, (const int32_t*)d.perm,
+           (const float*)x_dev, xi, 0);
+    NP_DISPATCH(np, launch(h, -1, k_spmv<float, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n, (const int32_t*)d.cols,
+                           (const int64_t*)d.sblk, (const float*)d.A32, (const float*)xi, yi));
+    launch(h, -1, k_permute<float>, dim3(grid_for(d.n * np)), dim3(TPB), d.n, np, (const int32_t*)d.perm,
+           (const float*)yi, (float*)y_dev, 1);
+  }
+  HIPCHK(hipGetLastError());
+  return CDGMG_OK;
+}
+
+int cdgmg_vcycle(cdgmg_handle* h, const double* r_dev, double* z_dev) {
+  RETURN_IF(check_handle(h));
+  DLevel& d = h->lv[0];
+  const int np = h->np;
+  launch(h, -1, k_permute<double>, dim3(grid_for(h->N0 * np)), dim3(TPB), h->N0, np, (const int32_t*)d.perm,
+         r_dev, h->t1, 0);
+  vcycle(h, h->t1, h->t2);
+  launch(h, -1, k_permute<double>, dim3(grid_for(h->N0 * np)), dim3(TPB), h->N0, np, (const int32_t*)d.perm,
+         (const double*)h->t2, z_dev, 1);
+  HIPCHK(hipGetLastError());
+  return CDGMG_OK;
+}
+
+int cdgmg_level_info(cdgmg_handle* h, int* n_levels, int64_t* n_elem, int64_t* nnzb) {
+  RETURN_IF(check_handle(h));
+  if (n_levels) *n_levels = h->L + 1;
+  for (int l = 0; l <= h->L; ++l) {
+    if (n_elem) n_elem[l] = h->lv[l].n;
+    if (nnzb) nnzb[l] = h->lv[l].nnzb;
+  }
+  return CDGMG_OK;
+}
+
+int cdgmg_export_operator(cdgmg_handle* h, int level, int64_t* nnzb, int64_t* row_ptr, int32_t* cols,
+                          double* blocks) {
+  RETURN_IF(check_handle(h));
+  if (level < 0 || level > h->L || !nnzb) {
+    set_error("export_operator: invalid argument");
+    return CDGMG_ERR_ARG;
+  }
+  const Level& H = h->P.lv[level];
+  const DLevel& D = h->lv[level];
+  const int np = h->np, np2 = np * np, nf = h->P.nf;
+  // valid slots per internal row
+  auto valid = [&](int64_t r, int w) {
+    if (level == 0) return w == 0 || h->P.topo.nbr[(int64_t)H.perm[r] * nf + w - 1] >= 0;
+    return w < H.row_len[r];
+  };
+  *nnzb = H.nnzb;
+  if (!row_ptr || !cols || !blocks) return CDGMG_OK;
+  std::vector<double> A((size_t)D.slots * np2);
+  HIPCHK(hipMemcpyAsync(A.data(), D.A64, A.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  std::vector<int64_t> cnt(H.n + 1, 0);
+  for (int64_t r = 0; r < H.n; ++r) {
+    int c = 0;
+    for (int w = 0; w < H.row_len[r]; ++w) c += valid(r, w);
+    cnt[H.perm[r] + 1] = c;
+  }
+  for (int64_t i = 0; i < H.n; ++i) cnt[i + 1] += cnt[i];
+  for (int64_t i = 0; i <= H.n; ++i) row_ptr[i] = cnt[i];
+  for (int64_t r = 0; r < H.n; ++r) {
+    const int64_t s = r / SLICE, lane = r % SLICE, B = H.slice_blk[s];
+    std::vector<std::pair<int32_t, int>> ent;
+    for (int w = 0; w < H.row_len[r]; ++w)
+      if (valid(r, w)) ent.push_back({H.perm[H.cols[B + SLICE * w + lane]], w});
+    std::sort(ent.begin(), ent.end());
+    int64_t k = row_ptr[H.perm[r]];
+    for (auto& e : ent) {
+      cols[k] = e.first;
+      for (int ij = 0; ij < np2; ++ij)
+        blocks[k * np2 + ij] = A[(size_t)(B + SLICE * e.second) * np2 + (size_t)ij * SLICE + lane];
+      ++k;
+    }
+  }
+  return CDGMG_OK;
+}
+
+int cdgmg_node_coords(cdgmg_handle* h, double* xyz) {
+  RETURN_IF(check_handle(h));
+  std::copy(h->P.nodes.begin(), h->P.nodes.end(), xyz);
+  return CDGMG_OK;
+}
+
+int cdgmg_device_bytes(cdgmg_handle* h, size_t* bytes) {
+  RETURN_IF(check_handle(h));
+  *bytes = h->bytes;
+  return CDGMG_OK;
+}
+
+int cdgmg_destroy(cdgmg_handle* h) {
+  if (!h) return CDGMG_OK;
+  if (h->stream || !h->allocs.empty()) (void)hipStreamSynchronize(h->stream);
+  for (void* p : h->allocs) (void)hipFree(p);
+  for (auto e : h->pool) (void)hipEventDestroy(e);
+  if (h->hscal) (void)hipHostFree(h->hscal);
+  if (h->herr) (void)hipHostFree(h->herr);
+  delete h;
+  return CDGMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,172 @@
+"""GPU parity of the HIP path against the FP64 oracle (call through the C ABI)."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2012_08024_amd as cm  # noqa: E402
+from oracle.adjoint import grad_kappa as oracle_grad_kappa  # noqa: E402
+from oracle.agglomerate import build_hierarchy  # noqa: E402
+from oracle.cdg import CDG  # noqa: E402
+from oracle.krylov import fcg, pcg  # noqa: E402
+from oracle.multigrid import Hierarchy  # noqa: E402
+from workloads import mesh2d_jittered_delaunay, mesh3d_kuhn, source_sine  # noqa: E402
+
+CASES = {
+    # name: (dim, n, p, levels, seed); sizes span several 64-row slices and a ragged tail
+    "2d_p2": (2, 14, 2, 3, 11),
+    "2d_p3": (2, 12, 3, 4, 12),
+    "2d_p1": (2, 11, 1, 3, 5),
+    "3d_p2": (3, 4, 2, 3, 13),
+    "3d_p1": (3, 5, 1, 3, 7),
+}
+
+
+def _build(name, mg=cm.MG_FP64, kappa_kind="random", **opts):
+    d, n, p, levels, seed = CASES[name]
+    mesh = mesh2d_jittered_delaunay(n, 1) if d == 2 else mesh3d_kuhn(n, 1)
+    parents, sizes = cm.agglomerate(mesh, levels, seed, p=p)
+    rng = np.random.default_rng(seed)
+    kappa = rng.uniform(0.5, 2.0, mesh.n_elem) if kappa_kind == "random" else np.ones(mesh.n_elem)
+    print("case", name, "n_elem", mesh.n_elem, "sizes", list(sizes), flush=True)
+    solver = cm.Solver(mesh, p, kappa, parents, sizes, mg_precision=mg, **opts)
+    cdg = CDG(mesh.coords, mesh.e2v, mesh.face_bc, p)
+    H = Hierarchy(cdg, parents, kappa=kappa, coarsening="primal")
+    return mesh, solver, cdg, H, kappa, parents, sizes
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_level_operators_match_oracle(name):
+    mesh, solver, cdg, H, kappa, parents, sizes = _build(name)
+    for l in range(len(sizes)):
+        A = cm.bsr_to_scipy(*solver.export_operator(l))
+        R = H.A[l]
+        err = abs(A - R).max() / abs(R).max()
+        assert err <= 1e-12, (name, l, err)
+    ne, nz = solver.level_info()
+    assert list(ne) == list(sizes)
+    solver.close()
+
+
+@pytest.mark.parametrize("name", ["2d_p2", "3d_p2"])
+def test_apply_A_fp64_and_fp32(name):
+    mesh, solver, cdg, H, kappa, parents, sizes = _build(name, mg=cm.MG_FP32)
+    rng = np.random.default_rng(1)
+    for l in range(len(sizes)):
+        x = rng.standard_normal(H.A[l].shape[0])
+        ref = H.A[l] @ x
+        y = solver.apply_A(l, x, 0).cpu().numpy()
+        assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max() * 10
+        y32 = solver.apply_A(l, x.astype(np.float32), 1).cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(y32 - ref) <= 1e-5 * np.linalg.norm(ref)
+    solver.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_vcycle_fp64_matches_oracle(name):
+    mesh, solver, cdg, H, kappa, parents, sizes = _build(name)
+    r = np.random.default_rng(2).standard_normal(H.A[0].shape[0])
+    z = solver.vcycle(r).cpu().numpy()
+    ref = H.vcycle(r, 2, 2, 0.7)
+    assert np.linalg.norm(z - ref) <= 1e-11 * np.linalg.norm(ref)
+    solver.close()
+
+
+def test_vcycle_fp32_close_to_oracle():
+    mesh, solver, cdg, H, kappa, parents, sizes = _build("2d_p3", mg=cm.MG_FP32)
+    r = np.random.default_rng(2).standard_normal(H.A[0].shape[0])
+    z = solver.vcycle(r).cpu().numpy()
+    ref = H.vcycle(r, 2, 2, 0.7)
+    assert np.linalg.norm(z - ref) <= 1e-4 * np.linalg.norm(ref)
+    solver.close()
+
+
+@pytest.mark.parametrize("name,mg", [("2d_p2", cm.MG_FP64), ("2d_p3", cm.MG_FP32), ("3d_p2", cm.MG_FP32),
+                                     ("3d_p1", cm.MG_FP64)])
+def test_solve_matches_direct_solve(name, mg):
+    mesh, solver, cdg, H, kappa, parents, sizes = _build(name, mg=mg, tol=1e-12)
+    x = solver.node_coords().reshape(-1, mesh.dim)
+    assert np.allclose(x, cdg.nodes_phys().reshape(-1, mesh.dim), atol=1e-14)
+    f = source_sine(x)
+    u, info = solver.solve(f)
+    ref = spl.spsolve(H.A[0].tocsc(), cdg.M0() @ f)
+    err = np.linalg.norm(u.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert info.rel_residual <= 1e-12
+    assert err <= (1e-10 if mg == cm.MG_FP64 else 1e-9), err
+    solver.close()
+
+
+def test_pcg_fp64_iterations_match_oracle():
+    # C1 shape: 2D p=2, 3 levels, PCG, all FP64; iteration counts within +-1
+    mesh = mesh2d_jittered_delaunay(16, 1)
+    parents, sizes = cm.agglomerate(mesh, 3, 11, p=2)
+    kappa = np.ones(mesh.n_elem)
+    solver = cm.Solver(mesh, 2, kappa, parents, sizes, mg_precision=cm.MG_FP64, outer=cm.OUTER_PCG, tol=1e-10)
+    cdg = CDG(mesh.coords, mesh.e2v, mesh.face_bc, 2)
+    H = Hierarchy(cdg, parents, coarsening="primal")
+    f = source_sine(cdg.nodes_phys().reshape(-1, 2))
+    b = cdg.M0() @ f
+    xo, ito, reso = pcg(H.A[0], b, H.vcycle, tol=1e-10)
+    u, info = solver.solve(f)
+    assert abs(info.iterations - ito) <= 1
+    assert np.linalg.norm(u.cpu().numpy() - xo) <= 1e-8 * np.linalg.norm(xo)
+    solver.close()
+
+
+def test_fcg_history_matches_oracle_fp64():
+    mesh, solver, cdg, H, kappa, parents, sizes = _build("2d_p2", tol=1e-11)
+    f = source_sine(cdg.nodes_phys().reshape(-1, 2))
+    b = cdg.M0() @ f
+    hist = []
+    xo, ito, reso = fcg(H.A[0], b, H.vcycle, tol=1e-11, history=hist)
+    u, info = solver.solve(f, history=True)
+    assert abs(info.iterations - ito) <= 1
+    oracle_rel = [np.linalg.norm(b - H.A[0] @ x) / np.linalg.norm(b) for x in hist[:5]]
+    assert np.allclose(info.history[:5], oracle_rel, rtol=1e-6)
+    solver.close()
+
+
+@pytest.mark.parametrize("name", ["2d_p2", "3d_p2"])
+def test_mass_and_grad_kappa_match_oracle(name):
+    mesh, solver, cdg, H, kappa, parents, sizes = _build(name)
+    rng = np.random.default_rng(5)
+    n = H.A[0].shape[0]
+    x = rng.standard_normal(n)
+    assert np.allclose(solver.apply_mass(x).cpu().numpy(), cdg.M0() @ x, rtol=0, atol=1e-15 * np.abs(x).max())
+    u, lam = rng.standard_normal(n), rng.standard_normal(n)
+    g = solver.grad_kappa(u, lam).cpu().numpy()
+    ref = oracle_grad_kappa(cdg, u, lam)
+    assert np.abs(g - ref).max() <= 1e-12 * np.abs(ref).max()
+    solver.close()
+
+
+def test_update_kappa_rebuilds_operators():
+    mesh, solver, cdg, H, kappa, parents, sizes = _build("2d_p2")
+    k2 = np.random.default_rng(9).uniform(0.1, 10.0, mesh.n_elem)
+    solver.update_kappa(k2)
+    H2 = Hierarchy(cdg, parents, kappa=k2, coarsening="primal")
+    for l in range(len(sizes)):
+        A = cm.bsr_to_scipy(*solver.export_operator(l))
+        assert abs(A - H2.A[l]).max() <= 1e-12 * abs(H2.A[l]).max()
+    solver.close()
+
+
+def test_error_paths():
+    mesh = mesh2d_jittered_delaunay(6, 1)
+    parents, sizes = cm.agglomerate(mesh, 2, 1, p=1)
+    with pytest.raises(cm.CdgmgError) as ei:
+        cm.Solver(mesh, 1, -np.ones(mesh.n_elem), parents, sizes)
+    assert ei.value.code == -1
+    solver = cm.Solver(mesh, 1, np.ones(mesh.n_elem), parents, sizes, max_iter=1, tol=1e-14)
+    f = np.ones(mesh.n_elem * 3)
+    u, info = solver.solve(f)  # NOT_CONVERGED is a warning; info is filled
+    assert info.iterations == 1 and info.rel_residual > 1e-14
+    with pytest.raises(cm.CdgmgError) as ei:
+        solver.solve(np.full(mesh.n_elem * 3, np.nan))
+    assert ei.value.code == -7
+    solver.close()
