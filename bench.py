@@ -1,0 +1,279 @@
+#!/usr/bin/env python3
+"""Throughput of the CDG Poisson solve on one MI355X.
+
+One step = one solve A u = M_0 f from u = 0 to a true FP64 relative residual
+<= 1e-10 with FCG(1) preconditioned by the FP32 V(2,2) block-Jacobi cycle on
+the agglomerated hierarchy (inputs resident in HBM, setup excluded).  The
+same solve with an FP64 V-cycle, the GPU rebuild of all level operators for
+a new kappa, the adjoint solve + dL/dkappa, per-kernel HIP-event timings with
+the level-0 smoother's roofline, and the CPU oracle on a bounded sample are
+reported alongside.  Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOFs/s to 1e-10 rel residual: FP32-MG-in-FP64-FCG vs FP64-MG; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernels_hash():
+    h = hashlib.sha256()
+    for name in ("kernels.inl", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2012_08024_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def cpu_baseline(cfg, n_sample):
+    """The FP64 oracle (same generator, smaller n; same p, levels, cycle and
+    outer solver) timed around the solve only, on one thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.agglomerate import build_hierarchy
+    from oracle.cdg import CDG
+    from oracle.krylov import fcg
+    from oracle.multigrid import Hierarchy
+    from workloads import mesh2d_jittered_delaunay, mesh3d_kuhn, source_sine
+
+    with threadpool_limits(1):
+        if cfg["dim"] == 2:
+            m = mesh2d_jittered_delaunay(n_sample, cfg["mesh_seed"])
+        else:
+            m = mesh3d_kuhn(n_sample, cfg["mesh_seed"])
+        t0 = time.perf_counter()
+        cdg = CDG(m.coords, m.e2v, m.face_bc, cfg["p"])
+        par = build_hierarchy(m.e2v, cdg.topo.neighbor_pairs(), cfg["levels"], cfg["agg_seed"])
+        H = Hierarchy(cdg, par, coarsening="primal")
+        t_setup = time.perf_counter() - t0
+        b = cdg.M0() @ source_sine(cdg.nodes_phys().reshape(-1, cfg["dim"]))
+        t0 = time.perf_counter()
+        x, it, res = fcg(H.A[0], b, H.vcycle, tol=cfg["tol"])
+        t_solve = time.perf_counter() - t0
+    dofs = cdg.N * cdg.np
+    return {
+        "value": dofs / t_solve, "unit": "DOFs/s", "cores": 1, "kind": "oracle",
+        "sample": "same generator at n=%d (%d elements, %d DOFs), p=%d, %d levels, FP64 V(2,2) "
+                  "block Jacobi in FCG(1) to %.0e; solve only, setup %.1f s excluded"
+                  % (n_sample, cdg.N, dofs, cfg["p"], len(H.sizes), cfg["tol"], t_setup),
+        "iterations": it, "solve_s": t_solve, "cpu": cpu_model(),
+        "threads": "1 (threadpool_limits(1); SciPy sparse products are single-threaded)",
+    }
+
+
+def smoother_bytes(nnzb0, n0, npb, s):
+    """Algorithmic HBM bytes of one level-0 block-Jacobi sweep: the stored
+    blocks of A_0 and their column indices, D^{-1}, and b, x read, x written."""
+    return nnzb0 * npb * npb * s + 4 * nnzb0 + n0 * npb * npb * s + 3 * n0 * npb * s
+
+
+def spmv_bytes(nnzb0, n0, npb):
+    """Outer FP64 q = A_0 p with (p,q), (p,r): A_0 blocks + cols, p, r read, q written."""
+    return nnzb0 * npb * npb * 8 + 4 * nnzb0 + 3 * n0 * npb * 8
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--cpu-sample-n", type=int, default=112)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--kernel-variant", type=int, default=0, help="0 auto, 1 thread per row, 2 row-split")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the solve is single-GPU; "
+              "multi-GPU domain decomposition is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2012_08024_amd as cm
+    from workloads import CONFIGS, config_mesh, source_sine
+
+    cfg = CONFIGS[args.config]
+    torch.cuda.set_device(0)
+    log("config %s: building mesh" % args.config)
+    mesh, kappa = config_mesh(cfg)
+    parents, sizes = cm.agglomerate(mesh, cfg["levels"] or 50, cfg["agg_seed"], p=cfg["p"],
+                                    coarse_dofs=cfg.get("coarse_dofs", 0))
+    log("levels %s" % list(sizes))
+    kappa_t = torch.tensor(kappa, dtype=torch.float64, device="cuda")
+
+    t0 = time.perf_counter()
+    s32 = cm.Solver(mesh, cfg["p"], kappa_t, parents, sizes, mg_precision=cm.MG_FP32, tol=cfg["tol"],
+                    kernel_variant=args.kernel_variant)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    npb = s32.np
+    dofs = mesh.n_elem * npb
+    ne, nnzb = s32.level_info()
+    f = torch.tensor(source_sine(s32.node_coords().reshape(-1, mesh.dim)), device="cuda")
+    log("setup %.1f s, %d DOFs, nnzb %s" % (setup_s, dofs, list(nnzb)))
+
+    # GPU rebuild of the operators (kappa assembly, Galerkin coarsening, block inverses, coarsest inverse)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s32.update_kappa(kappa_t)
+    torch.cuda.synchronize()
+    rebuild_ms = (time.perf_counter() - t0) * 1e3
+
+    u32, hinfo = s32.solve(f, history=True)
+    log("FP32-MG residual history: " + " ".join("%.1e" % v for v in hinfo.history[::10]))
+    for _ in range(args.warmup):
+        u32, info = s32.solve(f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        u32, info = s32.solve(f)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = dofs * args.steps / elapsed
+    log("FP32-MG: %.2f ms/solve, %d iterations, rel res %.2e, %.3g DOFs/s"
+        % (ms_per_step, info.iterations, info.rel_residual, value))
+
+    # the same timed loop with HIP events around every kernel launch
+    s32.set_profile(True)
+    kms = {k: 0.0 for k in cm.K_NAMES}
+    kcnt = {k: 0 for k in cm.K_NAMES}
+    for _ in range(args.steps):
+        _, pinfo = s32.solve(f)
+        for k in cm.K_NAMES:
+            kms[k] += pinfo.kernel_ms[k]
+            kcnt[k] += pinfo.kernel_launches[k]
+    s32.set_profile(False)
+    avg_smooth_ms = kms["smooth0"] / max(kcnt["smooth0"], 1)
+    avg_spmv_ms = kms["spmv"] / max(kcnt["spmv"], 1)
+    sb = smoother_bytes(int(nnzb[0]), mesh.n_elem, npb, 4)
+    achieved = sb / (avg_smooth_ms * 1e-3) / 1e9
+    spb = spmv_bytes(int(nnzb[0]), mesh.n_elem, npb)
+    spmv_gbs = spb / (avg_spmv_ms * 1e-3) / 1e9
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic_%s.json" % args.config)
+    if os.path.exists(tpath):
+        with open(tpath) as fh:
+            tj = json.load(fh)
+        ent = tj.get("k_smooth_level0")
+        if ent and ent.get("kernels_hash") == kernels_hash():
+            traffic = ent["hbm_bytes_per_launch"]
+
+    # adjoint: lambda = A^{-1} M_0 u, then dL/dkappa
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = s32.apply_mass(u32)
+    lam, ainfo = s32.solve_transpose(g)
+    gk = s32.grad_kappa(u32, lam)
+    torch.cuda.synchronize()
+    adjoint_ms = (time.perf_counter() - t0) * 1e3
+
+    out64 = None
+    err_vs_64 = None
+    if not args.no_fp64:
+        s32_bytes = s32.device_bytes()
+        s64 = cm.Solver(mesh, cfg["p"], kappa_t, parents, sizes, mg_precision=cm.MG_FP64, tol=cfg["tol"],
+                        kernel_variant=args.kernel_variant)
+        for _ in range(max(1, args.warmup)):
+            u64, info64 = s64.solve(f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            u64, info64 = s64.solve(f)
+        torch.cuda.synchronize()
+        el64 = time.perf_counter() - t0
+        err_vs_64 = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
+        out64 = {"value": dofs * args.steps / el64, "ms_per_step": el64 * 1e3 / args.steps,
+                 "iterations": info64.iterations, "rel_residual": info64.rel_residual,
+                 "conv_factor": info64.conv_factor}
+        log("FP64-MG: %.2f ms/solve, %d iterations" % (out64["ms_per_step"], info64.iterations))
+        s64.close()
+    else:
+        s32_bytes = s32.device_bytes()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("CPU oracle sample n=%d" % args.cpu_sample_n)
+        cpu = cpu_baseline(cfg, args.cpu_sample_n)
+        log("CPU oracle: %.3g DOFs/s (%d iterations)" % (cpu["value"], cpu["iterations"]))
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOFs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (V-cycle) / f64 (outer FCG, residual)",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: %dD jittered %s mesh n=%d, %d elements, CDG p=%d, %d DOFs, kappa=%s, %d-level "
+                        "greedy agglomeration (seed %d), V(%d,%d) damped block Jacobi omega=%.1f, "
+                        "Galerkin coarse operators, FCG(1), tol %.0e"
+                        % (args.config, cfg["dim"], "Delaunay" if cfg["dim"] == 2 else "Kuhn-tet", cfg["n"],
+                           mesh.n_elem, cfg["p"], dofs, cfg["kappa"], len(sizes), cfg["agg_seed"], 2, 2, 0.7,
+                           cfg["tol"]),
+            "elements": int(mesh.n_elem), "dofs": int(dofs), "p": cfg["p"], "levels": [int(x) for x in sizes],
+            "nnzb": [int(x) for x in nnzb],
+            "operator_complexity": float(sum(nnzb) / nnzb[0]),
+            "parallelism": "single GPU",
+        },
+        "iterations": info.iterations,
+        "residual_history_every_10": [float(v) for v in hinfo.history[::10]],
+        "rel_residual": info.rel_residual,
+        "conv_factor": info.conv_factor,
+        "error_vs_fp64_mg": err_vs_64,
+        "fp64_mg": out64,
+        "speedup_fp32_mg_vs_fp64_mg": (value / out64["value"]) if out64 else None,
+        "setup_s_total": setup_s,
+        "operator_rebuild_ms_gpu": rebuild_ms,
+        "adjoint_ms": adjoint_ms,
+        "adjoint_iterations": ainfo.iterations,
+        "device_bytes": s32_bytes,
+        "kernel_ms_per_solve": {k: kms[k] / args.steps for k in cm.K_NAMES if kcnt[k]},
+        "kernel_launches_per_solve": {k: kcnt[k] / args.steps for k in cm.K_NAMES if kcnt[k]},
+        "roofline": {
+            "kernel": "k_smooth<float,%d> (level-0 damped block-Jacobi sweep)" % npb,
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "algorithmic_bytes_per_launch": sb, "avg_launch_ms": avg_smooth_ms,
+        },
+        "outer_spmv_roofline": {"kernel": "k_spmv_dots<%d> (FP64)" % npb, "achieved": spmv_gbs,
+                                "frac": spmv_gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": spb,
+                                "avg_launch_ms": avg_spmv_ms},
+        "cpu_baseline": cpu,
+    }
+    s32.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -60,13 +60,13 @@ extern "C" {
 #define CDGMG_SWITCH_NATURAL 1
 
 /* kernel classes timed when cdgmg_options.profile != 0 */
-#define CDGMG_K_SPMV 0           /* outer FP64 y = A_0 x (+ fused dots) */
-#define CDGMG_K_SMOOTH0 1        /* level-0 damped block-Jacobi sweep */
-#define CDGMG_K_SMOOTH 2         /* coarse-level sweeps */
+#define CDGMG_K_SPMV 0           /* outer FP64 q = A_0 p with fused (p,q), (p,r) partial sums */
+#define CDGMG_K_SMOOTH0 1        /* level-0 damped block-Jacobi sweep (one kernel) */
+#define CDGMG_K_SMOOTH 2         /* first sweeps from zero and coarse-level sweeps */
 #define CDGMG_K_RESTRICT 3       /* residual + restriction, all levels */
 #define CDGMG_K_PROLONG 4        /* prolongation + correction, all levels */
 #define CDGMG_K_COARSE 5         /* coarsest solve */
-#define CDGMG_K_VECTOR 6         /* FCG vector updates and reductions */
+#define CDGMG_K_VECTOR 6         /* FCG vector updates, reductions, casts, true residual */
 #define CDGMG_NK 8
 
 typedef struct cdgmg_mesh {
@@ -96,6 +96,8 @@ typedef struct cdgmg_options {
   double tol;          /* relative true residual ||b - A x|| / ||b||; default 1e-10 */
   int max_iter;        /* default 500 */
   int profile;         /* nonzero: time kernel classes with HIP events */
+  int kernel_variant;  /* V-cycle sweep/restriction kernels: 0 auto (slot-split below 1e5 rows),
+                          1 thread per row, 2 slot-split (4 wavefronts share a 64-row slice's slots) */
 } cdgmg_options;
 
 typedef struct cdgmg_solve_info {
@@ -199,6 +201,9 @@ int cdgmg_export_operator(cdgmg_handle* h, int level, int64_t* nnzb, int64_t* ro
 
 /* Level-0 nodal points (host [n_elem][n_p][dim], caller order). */
 int cdgmg_node_coords(cdgmg_handle* h, double* xyz);
+
+/* Switch HIP-event timing of kernel classes on or off for later solves. */
+int cdgmg_set_profile(cdgmg_handle* h, int on);
 
 /* Device memory held by the handle, in bytes. */
 int cdgmg_device_bytes(cdgmg_handle* h, size_t* bytes);

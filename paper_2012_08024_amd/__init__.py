@@ -47,7 +47,7 @@ class _Opts(ctypes.Structure):
                 ("nu2", ctypes.c_int), ("mg_precision", ctypes.c_int), ("outer", ctypes.c_int),
                 ("coarsening", ctypes.c_int), ("switch_mode", ctypes.c_int),
                 ("switch_seed", ctypes.c_uint64), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("profile", ctypes.c_int)]
+                ("profile", ctypes.c_int), ("kernel_variant", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -77,6 +77,7 @@ _SIGS = {
     "cdgmg_export_operator": ([_vp, _i, _vp, _vp, _vp, _vp], _i),
     "cdgmg_node_coords": ([_vp, _vp], _i),
     "cdgmg_device_bytes": ([_vp, _vp], _i),
+    "cdgmg_set_profile": ([_vp, _i], _i),
     "cdgmg_destroy": ([_vp], _i),
     "cdgmg_debug_host_operator": ([_vp, _i, _vp, _vp, _vp, _i, _vp, _vp, _vp, _vp], _i),
 }
@@ -313,6 +314,9 @@ class Solver:
         out = np.zeros((self.n_elem, self.np, self.hm.dim))
         _check(lib.cdgmg_node_coords(self.handle, _ptr(out)))
         return out
+
+    def set_profile(self, on):
+        _check(lib.cdgmg_set_profile(self.handle, 1 if on else 0))
 
     def device_bytes(self):
         b = ctypes.c_size_t(0)

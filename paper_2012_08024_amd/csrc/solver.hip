@@ -89,8 +89,8 @@ struct cdgmg_handle {
   double *Ainv64 = nullptr, *dense1 = nullptr;
   float* Ainv32 = nullptr;
   // outer vectors (internal order, FP64)
-  double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *y = nullptr,
-         *t1 = nullptr, *t2 = nullptr;
+  double *b = nullptr, *x = nullptr, *xl = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr,
+         *y = nullptr, *t1 = nullptr, *t2 = nullptr;
   double *scal = nullptr, *part = nullptr;
   int nparts = 0;
   int* err = nullptr;
@@ -265,7 +265,7 @@ int upload_problem(cdgmg_handle* h) {
   if (fp32) RETURN_IF(dalloc(h, &h->Ainv32, (size_t)h->nd * h->nd));
   // outer vectors
   const size_t m = (size_t)h->lv[0].ns * SLICE * np;
-  for (double** v : {&h->b, &h->x, &h->r, &h->z, &h->p, &h->q, &h->y, &h->t1, &h->t2}) {
+  for (double** v : {&h->b, &h->x, &h->xl, &h->r, &h->z, &h->p, &h->q, &h->y, &h->t1, &h->t2}) {
     RETURN_IF(dalloc(h, v, m));
     HIPCHK(hipMemsetAsync(*v, 0, m * sizeof(double), h->stream));
   }
@@ -362,14 +362,29 @@ struct Ops<double> {
   static const double* Ainv(const cdgmg_handle* h) { return h->Ainv64; }
 };
 
+// slot-split kernels on levels too small to fill the GPU with one thread per row
+bool use_rs(const cdgmg_handle* h, int l) {
+  if (h->o.kernel_variant == 1) return false;
+  if (h->o.kernel_variant == 2) return true;
+  return h->lv[l].n < 100000;
+}
+
+// thread-per-row kernels: one-wavefront workgroups on small levels spread the
+// few wavefronts over the compute units
+inline int row_tpb(const cdgmg_handle* h, int l) { return h->lv[l].n < 100000 ? WAVE : TPB; }
+
 template <typename T, int NP>
 void smooth_sweeps(cdgmg_handle* h, int l, int count, T** x, T** xb) {
   DLevel& d = h->lv[l];
   const T omega = (T)h->o.omega;
+  const int cls = l == 0 ? CDGMG_K_SMOOTH0 : CDGMG_K_SMOOTH;
   for (int s = 0; s < count; ++s) {
-    launch(h, l == 0 ? CDGMG_K_SMOOTH0 : CDGMG_K_SMOOTH, k_smooth<T, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n,
-           (const int32_t*)d.cols, (const int64_t*)d.sblk, Ops<T>::A(d), Ops<T>::D(d), (const T*)d.b,
-           (const T*)*x, omega, *xb);
+    if (use_rs(h, l))
+      launch(h, cls, k_smooth_ss<T, NP>, dim3((unsigned)d.ns), dim3(WAVE * NW), d.n, (const int32_t*)d.cols,
+             (const int64_t*)d.sblk, Ops<T>::A(d), Ops<T>::D(d), (const T*)d.b, (const T*)*x, omega, *xb);
+    else
+      launch(h, cls, k_smooth<T, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n, (const int32_t*)d.cols,
+             (const int64_t*)d.sblk, Ops<T>::A(d), Ops<T>::D(d), (const T*)d.b, (const T*)*x, omega, *xb);
     std::swap(*x, *xb);
   }
 }
@@ -379,6 +394,7 @@ void vcycle_t(cdgmg_handle* h, const double* r64, double* z64) {
   const int L = h->L;
   const T omega = (T)h->o.omega;
   const int nu1 = h->o.nu1, nu2 = h->o.nu2;
+  const dim3 ssb(WAVE * NW);
   std::vector<T*> xs(L + 1), xbs(L + 1);
   for (int l = 0; l <= L; ++l) {
     xs[l] = (T*)h->lv[l].x;
@@ -395,33 +411,41 @@ void vcycle_t(cdgmg_handle* h, const double* r64, double* z64) {
   }
   for (int l = 0; l < L; ++l) {
     DLevel& d = h->lv[l];
+    const bool rs = use_rs(h, l);
     const T* Dv = nu1 > 0 ? Ops<T>::D(d) : nullptr;
+    const int tpb = row_tpb(h, l);
     if (l == 0) {
       if (nu1 > 0) {
-        launch(h, CDGMG_K_SMOOTH0, k_smooth_first<T, double, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n, r64,
+        launch(h, CDGMG_K_SMOOTH, k_smooth_first<T, double, NP>, dim3(grid_for(d.n, tpb)), dim3(tpb), d.n, r64,
                (T*)d.b, Dv, omega, xs[0]);
       } else {
         launch(h, CDGMG_K_VECTOR, k_cast<double, T>, dim3(grid_for(d.n * NP)), dim3(TPB), d.n * NP, r64, (T*)d.b);
         (void)hipMemsetAsync(xs[0], 0, d.n * NP * sizeof(T), h->stream);
       }
     } else {
-      launch(h, CDGMG_K_SMOOTH, k_gather_smooth_first<T, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n,
+      launch(h, CDGMG_K_SMOOTH, k_gather_smooth_first<T, NP>, dim3(grid_for(d.n, tpb)), dim3(tpb), d.n,
              (const int32_t*)d.child_start, (const T*)h->lv[l - 1].t, (T*)d.b, Dv, omega, xs[l]);
       if (nu1 == 0) (void)hipMemsetAsync(xs[l], 0, d.n * NP * sizeof(T), h->stream);
     }
     smooth_sweeps<T, NP>(h, l, nu1 - 1 > 0 ? nu1 - 1 : 0, &xs[l], &xbs[l]);
-    launch(h, CDGMG_K_RESTRICT, k_residual_restrict<T, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n,
-           (const int32_t*)d.cols, (const int64_t*)d.sblk, Ops<T>::A(d), (const T*)d.b, (const T*)xs[l],
-           Ops<T>::L(d), (T*)d.t);
+    if (rs)
+      launch(h, CDGMG_K_RESTRICT, k_residual_restrict_ss<T, NP>, dim3((unsigned)d.ns), ssb, d.n,
+             (const int32_t*)d.cols, (const int64_t*)d.sblk, Ops<T>::A(d), (const T*)d.b, (const T*)xs[l],
+             Ops<T>::L(d), (T*)d.t);
+    else
+      launch(h, CDGMG_K_RESTRICT, k_residual_restrict<T, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n,
+             (const int32_t*)d.cols, (const int64_t*)d.sblk, Ops<T>::A(d), (const T*)d.b, (const T*)xs[l],
+             Ops<T>::L(d), (T*)d.t);
   }
   DLevel& c = h->lv[L];
-  launch(h, CDGMG_K_COARSE, k_gather_smooth_first<T, NP>, dim3(grid_for(c.n)), dim3(TPB), c.n,
+  launch(h, CDGMG_K_COARSE, k_gather_smooth_first<T, NP>, dim3(grid_for(c.n, WAVE)), dim3(WAVE), c.n,
          (const int32_t*)c.child_start, (const T*)h->lv[L - 1].t, (T*)c.b, (const T*)nullptr, omega, (T*)nullptr);
   launch(h, CDGMG_K_COARSE, k_dense_gemv<T>, dim3(grid_for(h->nd * WAVE)), dim3(TPB), h->nd, Ops<T>::Ainv(h),
          (const T*)c.b, xs[L]);
   for (int l = L - 1; l >= 0; --l) {
     DLevel& d = h->lv[l];
-    launch(h, CDGMG_K_PROLONG, k_prolong<T, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n, (const int32_t*)d.parent,
+    const int tpb = row_tpb(h, l);
+    launch(h, CDGMG_K_PROLONG, k_prolong<T, NP>, dim3(grid_for(d.n, tpb)), dim3(tpb), d.n, (const int32_t*)d.parent,
            Ops<T>::L(d), (const T*)xs[l + 1], xs[l]);
     smooth_sweeps<T, NP>(h, l, nu2, &xs[l], &xbs[l]);
   }
@@ -452,15 +476,15 @@ int read_scalar(cdgmg_handle* h, int slot, double* out) {
   return CDGMG_OK;
 }
 
+// compensated true residual r = b - A (x_hi + x_lo), written into h->r (the
+// recursive residual is replaced by it); returns ||r||^2
 int true_residual(cdgmg_handle* h, double* rr) {
-  const int64_t m = h->N0 * h->np;
   DLevel& d = h->lv[0];
-  NP_DISPATCH(h->np, launch(h, CDGMG_K_SPMV, k_spmv<double, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n,
-                            (const int32_t*)d.cols, (const int64_t*)d.sblk, (const double*)d.A64,
-                            (const double*)h->x, h->y));
-  launch(h, CDGMG_K_VECTOR, k_sub, dim3(grid_for(m)), dim3(TPB), m, (const double*)h->b, (const double*)h->y,
-         h->t1);
-  dot_into(h, m, h->t1, h->t1, SC_TMP);
+  const unsigned g = grid_for(d.n);
+  NP_DISPATCH(h->np, launch(h, CDGMG_K_VECTOR, k_residual2<NP>, dim3(g), dim3(TPB), d.n, (const int32_t*)d.cols,
+                            (const int64_t*)d.sblk, (const double*)d.A64, (const double*)h->b,
+                            (const double*)h->x, (const double*)h->xl, h->r, h->part));
+  launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)g, 1, h->scal, SC_TMP);
   return read_scalar(h, SC_TMP, rr);
 }
 
@@ -493,6 +517,7 @@ int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
   const int np = h->np;
   DLevel& d0 = h->lv[0];
   HIPCHK(hipMemsetAsync(h->x, 0, m * sizeof(double), h->stream));
+  HIPCHK(hipMemsetAsync(h->xl, 0, m * sizeof(double), h->stream));
   HIPCHK(hipMemcpyAsync(h->r, h->b, m * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
   double bb = 0.0;
   dot_into(h, m, h->b, h->b, SC_BB);
@@ -505,6 +530,7 @@ int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
   int it = 0;
   double rel = 0.0, rel_true = 0.0;
   int status = CDGMG_NOT_CONVERGED;
+  double rho_last = nb;
   if (nb == 0.0) {
     status = CDGMG_OK;
   } else {
@@ -531,8 +557,8 @@ int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
       launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)g, 2, h->scal, SC_PQ);
       launch(h, CDGMG_K_VECTOR, k_scalars, dim3(1), dim3(1), h->scal, fcg ? 2 : 3);
       const unsigned gu = std::min<unsigned>(1024, grid_for(m));
-      launch(h, CDGMG_K_VECTOR, k_update_xr, dim3(gu), dim3(TPB), m, (const double*)h->p, (const double*)h->q,
-             h->x, h->r, (const double*)h->scal, h->part);
+      launch(h, CDGMG_K_VECTOR, k_update_xr2, dim3(gu), dim3(TPB), m, (const double*)h->p, (const double*)h->q,
+             h->x, h->xl, h->r, (const double*)h->scal, h->part);
       launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)gu, 1, h->scal, SC_RR);
       double rr;
       RETURN_IF(read_scalar(h, SC_RR, &rr));
@@ -544,15 +570,18 @@ int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
       }
       rel = std::sqrt(rr) / nb;
       if (info && info->history && it <= info->history_len) info->history[it - 1] = rel;
-      if (rel <= h->o.tol) {
+      // reliable updates: the recursive residual is replaced by the compensated
+      // true residual whenever it has dropped 100x since the last replacement,
+      // and before convergence is accepted
+      if (rel <= h->o.tol || std::sqrt(rr) <= 1e-2 * rho_last) {
         double rt;
         RETURN_IF(true_residual(h, &rt));
         rel_true = std::sqrt(rt) / nb;
+        rho_last = std::sqrt(rt);
         if (rel_true <= h->o.tol) {
           status = CDGMG_OK;
           break;
         }
-        HIPCHK(hipMemcpyAsync(h->r, h->t1, m * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
       }
     }
   }
@@ -606,6 +635,7 @@ void cdgmg_default_options(cdgmg_options* o) {
   o->tol = 1e-10;
   o->max_iter = 500;
   o->profile = 0;
+  o->kernel_variant = 0;
 }
 
 int cdgmg_agglomerate(const cdgmg_mesh* mesh, int max_levels, int64_t coarse_dofs_max, int p, uint64_t seed,
@@ -713,8 +743,8 @@ int cdgmg_solve(cdgmg_handle* h, const double* f_dev, double* u_dev, cdgmg_solve
   NP_DISPATCH(np, launch(h, -1, k_mass_in<NP>, dim3(grid_for(d.n)), dim3(TPB), d.n, (const int32_t*)d.perm,
                          (const double*)h->M, f_dev, h->b));
   int rc = krylov(h, info);
-  launch(h, -1, k_permute<double>, dim3(grid_for(h->N0 * np)), dim3(TPB), h->N0, np, (const int32_t*)d.perm,
-         (const double*)h->x, u_dev, 1);
+  launch(h, -1, k_out_dd, dim3(grid_for(h->N0 * np)), dim3(TPB), h->N0, np, (const int32_t*)d.perm,
+         (const double*)h->x, (const double*)h->xl, u_dev);
   HIPCHK(hipStreamSynchronize(h->stream));
   return rc;
 }
@@ -728,8 +758,8 @@ int cdgmg_solve_rhs(cdgmg_handle* h, const double* b_dev, double* x_dev, cdgmg_s
   launch(h, -1, k_permute<double>, dim3(grid_for(h->N0 * np)), dim3(TPB), h->N0, np, (const int32_t*)d.perm,
          b_dev, h->b, 0);
   int rc = krylov(h, info);
-  launch(h, -1, k_permute<double>, dim3(grid_for(h->N0 * np)), dim3(TPB), h->N0, np, (const int32_t*)d.perm,
-         (const double*)h->x, x_dev, 1);
+  launch(h, -1, k_out_dd, dim3(grid_for(h->N0 * np)), dim3(TPB), h->N0, np, (const int32_t*)d.perm,
+         (const double*)h->x, (const double*)h->xl, x_dev);
   HIPCHK(hipStreamSynchronize(h->stream));
   return rc;
 }
@@ -865,6 +895,12 @@ int cdgmg_export_operator(cdgmg_handle* h, int level, int64_t* nnzb, int64_t* ro
 int cdgmg_node_coords(cdgmg_handle* h, double* xyz) {
   RETURN_IF(check_handle(h));
   std::copy(h->P.nodes.begin(), h->P.nodes.end(), xyz);
+  return CDGMG_OK;
+}
+
+int cdgmg_set_profile(cdgmg_handle* h, int on) {
+  RETURN_IF(check_handle(h));
+  h->o.profile = on ? 1 : 0;
   return CDGMG_OK;
 }
 

@@ -67,9 +67,10 @@ def test_apply_A_fp64_and_fp32(name):
     solver.close()
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("name", list(CASES))
-def test_vcycle_fp64_matches_oracle(name):
-    mesh, solver, cdg, H, kappa, parents, sizes = _build(name)
+def test_vcycle_fp64_matches_oracle(name, variant):
+    mesh, solver, cdg, H, kappa, parents, sizes = _build(name, kernel_variant=variant)
     r = np.random.default_rng(2).standard_normal(H.A[0].shape[0])
     z = solver.vcycle(r).cpu().numpy()
     ref = H.vcycle(r, 2, 2, 0.7)
@@ -77,8 +78,9 @@ def test_vcycle_fp64_matches_oracle(name):
     solver.close()
 
 
-def test_vcycle_fp32_close_to_oracle():
-    mesh, solver, cdg, H, kappa, parents, sizes = _build("2d_p3", mg=cm.MG_FP32)
+@pytest.mark.parametrize("variant", [1, 2])
+def test_vcycle_fp32_close_to_oracle(variant):
+    mesh, solver, cdg, H, kappa, parents, sizes = _build("2d_p3", mg=cm.MG_FP32, kernel_variant=variant)
     r = np.random.default_rng(2).standard_normal(H.A[0].shape[0])
     z = solver.vcycle(r).cpu().numpy()
     ref = H.vcycle(r, 2, 2, 0.7)
