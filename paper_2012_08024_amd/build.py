@@ -9,7 +9,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcdgmg.so")
 ARCH = os.environ.get("CDGMG_ARCH", "gfx950")
 
-HOST_SRC = ["host_mesh.cpp", "host_fem.cpp", "host_debug.cpp"]
+HOST_SRC = ["host_mesh.cpp", "host_fem.cpp", "host_flux.cpp", "host_debug.cpp"]
 DEV_SRC = ["solver.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed FP32 instructions are disabled for all device code

@@ -8,6 +8,47 @@
 
 using namespace cdg;
 
+namespace {
+// dense helpers on row-major n x n blocks
+void invert_spd_like(int n, double* a) {
+  // Gauss-Jordan without pivoting (blocks are symmetric positive definite)
+  for (int k = 0; k < n; ++k) {
+    const double p = a[k * n + k];
+    a[k * n + k] = 1.0;
+    for (int j = 0; j < n; ++j) a[k * n + j] /= p;
+    for (int i = 0; i < n; ++i) {
+      if (i == k) continue;
+      const double f = a[i * n + k];
+      a[i * n + k] = 0.0;
+      for (int j = 0; j < n; ++j) a[i * n + j] -= f * a[k * n + j];
+    }
+  }
+}
+
+// out += sign * P^T Q R with P, R possibly identity (nullptr)
+void tp_acc(int n, const double* P, const double* Q, const double* R, double sign, double* out) {
+  std::vector<double> T(n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      if (R)
+        for (int m = 0; m < n; ++m) s += Q[i * n + m] * R[m * n + j];
+      else
+        s = Q[i * n + j];
+      T[i * n + j] = s;
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      if (P)
+        for (int m = 0; m < n; ++m) s += P[m * n + i] * T[m * n + j];
+      else
+        s = T[i * n + j];
+      out[i * n + j] += sign * s;
+    }
+}
+}  // namespace
+
 extern "C" int cdgmg_debug_host_operator(const cdgmg_mesh* mesh, int p, const double* kappa,
                                          const cdgmg_hierarchy* hier, const cdgmg_options* opts, int level,
                                          int64_t* nnzb, int64_t* row_ptr, int32_t* cols, double* blocks) {
@@ -56,6 +97,14 @@ extern "C" int cdgmg_debug_host_operator(const cdgmg_mesh* mesh, int p, const do
   // Galerkin products level by level, blocks stored row-major per (row, slot)
   std::vector<double> cur = A;
   std::vector<int> width(1, W0);
+  // flux-form state: M_l blocks and G_l blocks (component-major)
+  std::vector<double> Ml, Gl;
+  if (P.flux) {
+    Ml.assign((size_t)P.N0 * np2, 0.0);
+    for (int64_t r = 0; r < P.N0; ++r)
+      for (int ij = 0; ij < np2; ++ij) Ml[(size_t)r * np2 + ij] = P.Mblk[(size_t)r * np2 + ij] / k[r];
+    Gl = P.G0;
+  }
   for (int l = 1; l <= level; ++l) {
     const Level &f = P.lv[l - 1], &c = P.lv[l];
     const int Wf = width.back();
@@ -83,6 +132,45 @@ extern "C" int cdgmg_debug_host_operator(const cdgmg_mesh* mesh, int p, const do
             dst[i * np + j] += s;
           }
       }
+    }
+    if (P.flux) {
+      const FluxPlan& F = P.fp[l - 1];
+      const int d = P.d;
+      const int64_t nX = (int64_t)F.x_col.size(), nY = (int64_t)F.y_col.size();
+      std::vector<double> Minv(Ml), X((size_t)d * nX * np2, 0.0), Y((size_t)d * nY * np2, 0.0),
+          Mc((size_t)c.n * np2, 0.0);
+      for (int64_t r = 0; r < f.n; ++r) invert_spd_like(np, &Minv[(size_t)r * np2]);
+      auto blk = [&](const OpRef& o) -> const double* {
+        switch (o.kind) {
+          case OP_L: return &f.Lblk[(size_t)o.idx * np2];
+          case OP_G: return &Gl[((size_t)o.comp * F.g_col.size() + o.idx) * np2];
+          case OP_X: return &X[((size_t)o.comp * nX + o.idx) * np2];
+          case OP_Y: return &Y[((size_t)o.comp * nY + o.idx) * np2];
+          case OP_MINV: return &Minv[(size_t)o.idx * np2];
+          case OP_M: return &Ml[(size_t)o.idx * np2];
+          default: return nullptr;
+        }
+      };
+      for (int64_t o = 0; o < d * nX; ++o)
+        for (int64_t q = F.xp_ptr[o]; q < F.xp_ptr[o + 1]; ++q)
+          tp_acc(np, blk(F.xp[q].P), blk(F.xp[q].Q), blk(F.xp[q].R), F.xp[q].sign, &X[(size_t)o * np2]);
+      for (int64_t o = 0; o < d * nY; ++o)
+        for (int64_t q = F.yp_ptr[o]; q < F.yp_ptr[o + 1]; ++q)
+          tp_acc(np, blk(F.yp[q].P), blk(F.yp[q].Q), blk(F.yp[q].R), F.yp[q].sign, &Y[(size_t)o * np2]);
+      for (int64_t J = 0; J < c.n; ++J)
+        for (int64_t q = F.mp_ptr[J]; q < F.mp_ptr[J + 1]; ++q)
+          tp_acc(np, blk(F.mp[q].P), blk(F.mp[q].Q), blk(F.mp[q].R), F.mp[q].sign, &Mc[(size_t)J * np2]);
+      std::vector<double> Minvc(Mc);
+      for (int64_t J = 0; J < c.n; ++J) invert_spd_like(np, &Minvc[(size_t)J * np2]);
+      auto blk2 = [&](const OpRef& o) -> const double* {
+        if (o.kind == OP_MINVC) return &Minvc[(size_t)o.idx * np2];
+        return blk(o);
+      };
+      for (int64_t kb = 0; kb < c.nnzb; ++kb)
+        for (int64_t q = F.sp_ptr[kb]; q < F.sp_ptr[kb + 1]; ++q)
+          tp_acc(np, blk2(F.sp[q].P), blk2(F.sp[q].Q), blk2(F.sp[q].R), F.sp[q].sign, &nxt[(size_t)kb * np2]);
+      Ml.swap(Mc);
+      Gl.swap(Y);
     }
     cur.swap(nxt);
     width.push_back(0);

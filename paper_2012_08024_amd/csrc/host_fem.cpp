@@ -776,7 +776,14 @@ int build_problem(const cdgmg_mesh& m, int p, const cdgmg_hierarchy& h, const cd
     });
   }
 
-  // ---- coarse patterns (Galerkin: distance-1 on the coarse graph) and K7 plans
+  // ---- coarse patterns (Galerkin: distance-1 on the coarse graph; flux form:
+  //      plus the Schur-complement couplings) and K7 plans
+  P.flux = (o.coarsening == CDGMG_COARSEN_FLUX);
+  if (P.flux && L > 0) {
+    P.fp.assign(L, FluxPlan());
+    flux_g0(P);
+  }
+  std::vector<std::pair<std::pair<int32_t, int32_t>, TPTerm>> sterms;
   for (int l = 1; l <= L; ++l) {
     Level &f = P.lv[l - 1], &c = P.lv[l];
     std::vector<std::vector<int32_t>> rows(c.n);
@@ -791,6 +798,10 @@ int build_problem(const cdgmg_mesh& m, int p, const cdgmg_hierarchy& h, const cd
       for (int64_t e = c.child_start[I]; e < c.child_start[I + 1]; ++e)
         for (int w = 0; w < f.row_len[e]; ++w)
           if (fvalid(e, w)) row.push_back(f.parent[fcol(e, w)]);
+    }
+    if (P.flux) flux_level_symbolic(P, l - 1, rows, sterms);
+    for (int64_t I = 0; I < c.n; ++I) {
+      auto& row = rows[I];
       std::sort(row.begin() + 1, row.end());
       row.erase(std::unique(row.begin() + 1, row.end()), row.end());
       row.erase(std::remove(row.begin() + 1, row.end(), (int32_t)I), row.end());
@@ -805,6 +816,7 @@ int build_problem(const cdgmg_mesh& m, int p, const cdgmg_hierarchy& h, const cd
       c.row_blk[I + 1] = c.row_blk[I] + c.row_len[I];
     }
     c.nnzb = c.row_blk[c.n];
+    if (P.flux) flux_level_schur(P, l - 1, rows, sterms);
     c.slice_blk.assign(ns + 1, 0);
     for (int64_t s = 0; s < ns; ++s) c.slice_blk[s + 1] = c.slice_blk[s] + (int64_t)c.slice_w[s] * SLICE;
     c.cols.assign(c.slice_blk[ns], 0);

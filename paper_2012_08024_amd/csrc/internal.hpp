@@ -89,6 +89,31 @@ struct Level {
   int64_t slices() const { return (n + SLICE - 1) / SLICE; }
 };
 
+// Flux-form coarsening plans (Sec. 4.1) for level l -> l+1, in block indices.
+// Operand references: kind + index; blocks of G_l, X and Y are stored
+// component-major (component c at offset c * count).
+enum OpKind : int8_t { OP_NONE = 0, OP_L = 1, OP_A = 2, OP_G = 3, OP_X = 4, OP_Y = 5, OP_MINV = 6, OP_MINVC = 7,
+                       OP_M = 8 };
+struct OpRef {
+  int8_t kind;
+  int8_t comp;   // component for G/X/Y, else 0
+  int64_t idx;   // L: level-l row; A: (row, slot) packed as row * 64 + slot; G/X/Y: block; MINV: level-l row;
+                 // MINVC: level-(l+1) row; M: level-l row
+};
+struct TPTerm {
+  OpRef P, Q, R;  // contributes sign * P^T Q R (P or R may be OP_NONE = identity)
+  double sign;
+};
+struct FluxPlan {
+  // G_l pattern (level-l rows), X = G_l L pattern (level-l rows, level-(l+1) cols), Y = L^T X (= G_{l+1})
+  std::vector<int64_t> g_ptr, x_ptr, y_ptr;        // row pointers
+  std::vector<int32_t> g_col, x_col, y_col;        // columns
+  std::vector<int64_t> xp_ptr, yp_ptr, mp_ptr;     // per-output term ranges
+  std::vector<TPTerm> xp, yp, mp;                  // X blocks, Y blocks, M_{l+1} rows
+  std::vector<int64_t> sp_ptr;                     // per A_{l+1} block (row_blk numbering)
+  std::vector<TPTerm> sp;                          // Schur terms -X^T M_l^-1 X + Y^T M_{l+1}^-1 Y
+};
+
 struct Problem {
   int d = 0, p = 0, np = 0, nf = 0;
   int64_t N0 = 0;
@@ -105,9 +130,17 @@ struct Problem {
   std::vector<double> Mblk;           // [N0][np][np] element mass matrices
   std::vector<double> Gblk;           // [d][N0][nf+1][np][np] flux-form gradient (kappa-free)
   std::vector<double> nodes;          // [N0 caller order][np][d]
+  bool flux = false;
+  std::vector<FluxPlan> fp;           // [L]: plan building level l+1 from level l
+  std::vector<double> G0;             // [d][nG0][np][np] block-major G_0 in the FluxPlan[0] pattern
 };
 
 int build_problem(const cdgmg_mesh& m, int p, const cdgmg_hierarchy& h, const cdgmg_options& o,
                   Problem& P);
+void flux_g0(Problem& P);
+void flux_level_symbolic(Problem& P, int l, std::vector<std::vector<int32_t>>& rows,
+                         std::vector<std::pair<std::pair<int32_t, int32_t>, TPTerm>>& sterms);
+void flux_level_schur(Problem& P, int l, const std::vector<std::vector<int32_t>>& rows,
+                      std::vector<std::pair<std::pair<int32_t, int32_t>, TPTerm>>& sterms);
 
 }  // namespace cdg

@@ -22,6 +22,20 @@ enum {
   SC_ZQ = 0, SC_PQOLD, SC_PQ, SC_PR, SC_RR, SC_BETA, SC_ALPHA, SC_ZR, SC_ZROLD, SC_BB, SC_TMP, SC_N = 16
 };
 
+// one term sign * P^T Q R of a plan-driven block product; element (i, j) of an
+// operand X with stride s is X[(i n_p + j) s]; P or R null means identity
+struct TPDev {
+  const double* P;
+  const double* Q;
+  const double* R;
+  int32_t sp, sq, sr, pad;
+  double sign;
+};
+struct TPOut {
+  double* O;
+  int64_t so;
+};
+
 struct DevEll {
   int64_t n;              // rows
   const int32_t* cols;    // [sum W_s * 64]

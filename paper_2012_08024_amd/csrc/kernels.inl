@@ -55,7 +55,7 @@ __global__ void k_kappa_perm(int64_t n, const int32_t* __restrict__ perm, const 
 // positive Schur-complement diagonal).  err is set on a non-positive pivot.
 template <int NP>
 __global__ void k_diag_inverse(int64_t n, const int64_t* __restrict__ sblk, const double* __restrict__ A,
-                               double* __restrict__ Dinv, int* __restrict__ err) {
+                               double* __restrict__ Dinv, int* __restrict__ err, int definite) {
   constexpr int NP2 = NP * NP;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
@@ -65,7 +65,7 @@ __global__ void k_diag_inverse(int64_t n, const int64_t* __restrict__ sblk, cons
   for (int ij = 0; ij < NP2; ++ij) D[ij * WAVE] = A[blk_off(B, 0, NP2, ij, lane)];
   for (int k = 0; k < NP; ++k) {
     const double p = D[(k * NP + k) * WAVE];
-    if (!(p > 0.0)) {
+    if (definite ? !(p > 0.0) : !(p != 0.0)) {
       *err = 1;
       return;
     }
@@ -129,6 +129,90 @@ __global__ void k_galerkin(int64_t nblk, const int32_t* __restrict__ blk_row, co
   }
 }
 
+// K7 (flux form): out_o (+)= sum over its plan terms of sign * P^T Q R, in
+// fixed order.  One workgroup per output block, one thread per entry.
+template <int NP>
+__global__ void k_triple(int64_t nout, const TPOut* __restrict__ outs, const int64_t* __restrict__ ptr,
+                         const TPDev* __restrict__ ent, int accumulate) {
+  constexpr int NP2 = NP * NP;
+  __shared__ double sP[NP2], sQ[NP2], sR[NP2], sT[NP2];
+  const int64_t o = blockIdx.x;
+  if (o >= nout) return;
+  const int tid = threadIdx.x;
+  const int i = tid / NP, j = tid % NP;
+  const TPOut out = outs[o];
+  double acc = 0.0;
+  if (accumulate && tid < NP2) acc = out.O[(int64_t)tid * out.so];
+  for (int64_t q = ptr[o]; q < ptr[o + 1]; ++q) {
+    const TPDev e = ent[q];
+    if (tid < NP2) {
+      sQ[tid] = e.Q[(int64_t)tid * e.sq];
+      if (e.P) sP[tid] = e.P[(int64_t)tid * e.sp];
+      if (e.R) sR[tid] = e.R[(int64_t)tid * e.sr];
+    }
+    __syncthreads();
+    if (tid < NP2) {
+      double s = 0.0;
+      if (e.R) {
+        for (int m = 0; m < NP; ++m) s += sQ[i * NP + m] * sR[m * NP + j];
+      } else {
+        s = sQ[tid];
+      }
+      sT[tid] = s;
+    }
+    __syncthreads();
+    if (tid < NP2) {
+      double s = 0.0;
+      if (e.P) {
+        for (int m = 0; m < NP; ++m) s += sP[m * NP + i] * sT[m * NP + j];
+      } else {
+        s = sT[tid];
+      }
+      acc += e.sign * s;
+    }
+    __syncthreads();
+  }
+  if (tid < NP2) out.O[(int64_t)tid * out.so] = acc;
+}
+
+// flux-form mass of level 0: M(e) = kappa_e^{-1} M_e (block-major output)
+template <int NP>
+__global__ void k_mass_kappa(int64_t n, const double* __restrict__ Mrow, const double* __restrict__ kappa,
+                             double* __restrict__ Mbm) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const double ik = 1.0 / kappa[r];
+  for (int ij = 0; ij < NP2; ++ij) Mbm[r * NP2 + ij] = Mrow[row_off(r, NP2, ij)] * ik;
+}
+
+// inverse of block-major n_p x n_p blocks (Gauss-Jordan, no pivoting; blocks are SPD)
+template <int NP>
+__global__ void k_block_inverse_bm(int64_t n, const double* __restrict__ src, double* __restrict__ dst,
+                                   int* __restrict__ err) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double* D = dst + r * NP2;
+  for (int ij = 0; ij < NP2; ++ij) D[ij] = src[r * NP2 + ij];
+  for (int k = 0; k < NP; ++k) {
+    const double p = D[k * NP + k];
+    if (!(p > 0.0)) {
+      *err = 1;
+      return;
+    }
+    const double ip = 1.0 / p;
+    D[k * NP + k] = 1.0;
+    for (int j = 0; j < NP; ++j) D[k * NP + j] *= ip;
+    for (int i = 0; i < NP; ++i) {
+      if (i == k) continue;
+      const double f = D[i * NP + k];
+      D[i * NP + k] = 0.0;
+      for (int j = 0; j < NP; ++j) D[i * NP + j] -= f * D[k * NP + j];
+    }
+  }
+}
+
 // coarsest level: scatter the sliced blocks into a dense row-major matrix
 template <int NP>
 __global__ void k_dense_scatter(int64_t n, const int32_t* __restrict__ cols, const int64_t* __restrict__ sblk,
@@ -150,12 +234,12 @@ __global__ void k_dense_scatter(int64_t n, const int32_t* __restrict__ cols, con
 
 // one Gauss-Jordan step of the in-place inverse (out-of-place between two buffers)
 __global__ void k_gj_step(int64_t n, int64_t k, const double* __restrict__ in, double* __restrict__ out,
-                          int* __restrict__ err) {
+                          int* __restrict__ err, int definite) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n * n) return;
   const int64_t i = idx / n, j = idx % n;
   const double p = in[k * n + k];
-  if (idx == 0 && !(p > 0.0)) *err = 1;
+  if (idx == 0 && (definite ? !(p > 0.0) : !(p != 0.0))) *err = 1;
   const double rk = (j == k) ? 1.0 : in[k * n + j];
   if (i == k) {
     out[idx] = rk / p;

@@ -63,6 +63,13 @@ struct DLevel {
   int32_t* plan_e = nullptr;
   int32_t* plan_w = nullptr;
   void *b = nullptr, *x = nullptr, *xb = nullptr, *t = nullptr;
+  // flux-form coarsening (building level l+1 from this level l)
+  double *Mbm = nullptr, *Minv = nullptr, *G = nullptr, *X = nullptr, *Y = nullptr;
+  int64_t nX = 0, nY = 0;
+  TPDev *xp = nullptr, *yp = nullptr, *mp = nullptr, *sp = nullptr;
+  TPOut *xo = nullptr, *yo = nullptr, *mo = nullptr, *so = nullptr;
+  int64_t *xpp = nullptr, *ypp = nullptr, *mpp = nullptr, *spp = nullptr;
+  int64_t nxo = 0, nyo = 0, nmo = 0, nso = 0;
 };
 
 struct ProfEv {
@@ -190,6 +197,93 @@ int check_err(cdgmg_handle* h, int code, const char* what) {
 }
 
 // ---------------------------------------------------------------- device setup
+// Flux-form coarsening: device arrays for M_l, M_l^{-1}, G_l, X, Y per level and
+// the host plans translated into (pointer, stride) terms.
+int upload_flux(cdgmg_handle* h) {
+  Problem& P = h->P;
+  const int np = P.np, np2 = np * np, d = P.d;
+  for (int l = 0; l <= P.L; ++l) {
+    DLevel& D = h->lv[l];
+    RETURN_IF(dalloc(h, &D.Mbm, (size_t)D.n * np2));
+    RETURN_IF(dalloc(h, &D.Minv, (size_t)D.n * np2));
+  }
+  RETURN_IF(upload(h, &h->lv[0].G, P.G0));
+  for (int l = 0; l < P.L; ++l) {
+    const FluxPlan& F = P.fp[l];
+    DLevel &D = h->lv[l], &C = h->lv[l + 1];
+    D.nX = (int64_t)F.x_col.size();
+    D.nY = (int64_t)F.y_col.size();
+    RETURN_IF(dalloc(h, &D.X, (size_t)d * D.nX * np2));
+    RETURN_IF(dalloc(h, &D.Y, (size_t)d * D.nY * np2));
+    C.G = D.Y;
+  }
+  for (int l = 0; l < P.L; ++l) {
+    const FluxPlan& F = P.fp[l];
+    DLevel &D = h->lv[l], &C = h->lv[l + 1];
+    const int64_t nG = (int64_t)F.g_col.size();
+    auto ref = [&](const OpRef& o, const double** ptr, int32_t* stride) {
+      *stride = 1;
+      switch (o.kind) {
+        case OP_L:
+          *ptr = D.L64 + (o.idx / SLICE) * SLICE * np2 + (o.idx % SLICE);
+          *stride = SLICE;
+          break;
+        case OP_G: *ptr = D.G + ((size_t)o.comp * nG + o.idx) * np2; break;
+        case OP_X: *ptr = D.X + ((size_t)o.comp * D.nX + o.idx) * np2; break;
+        case OP_Y: *ptr = D.Y + ((size_t)o.comp * D.nY + o.idx) * np2; break;
+        case OP_MINV: *ptr = D.Minv + (size_t)o.idx * np2; break;
+        case OP_MINVC: *ptr = C.Minv + (size_t)o.idx * np2; break;
+        case OP_M: *ptr = D.Mbm + (size_t)o.idx * np2; break;
+        default: *ptr = nullptr; break;
+      }
+    };
+    auto terms = [&](const std::vector<TPTerm>& src, TPDev** dst) {
+      std::vector<TPDev> v(src.size());
+      for (size_t q = 0; q < src.size(); ++q) {
+        ref(src[q].P, &v[q].P, &v[q].sp);
+        ref(src[q].Q, &v[q].Q, &v[q].sq);
+        ref(src[q].R, &v[q].R, &v[q].sr);
+        v[q].pad = 0;
+        v[q].sign = src[q].sign;
+      }
+      return upload(h, dst, v);
+    };
+    std::vector<TPOut> outs;
+    // X outputs (component-major), Y outputs, M_{l+1} rows, A_{l+1} blocks
+    outs.resize((size_t)d * D.nX);
+    for (size_t o = 0; o < outs.size(); ++o) outs[o] = TPOut{D.X + o * np2, 1};
+    RETURN_IF(upload(h, &D.xo, outs));
+    RETURN_IF(upload(h, &D.xpp, F.xp_ptr));
+    RETURN_IF(terms(F.xp, &D.xp));
+    D.nxo = (int64_t)outs.size();
+    outs.resize((size_t)d * D.nY);
+    for (size_t o = 0; o < outs.size(); ++o) outs[o] = TPOut{D.Y + o * np2, 1};
+    RETURN_IF(upload(h, &D.yo, outs));
+    RETURN_IF(upload(h, &D.ypp, F.yp_ptr));
+    RETURN_IF(terms(F.yp, &D.yp));
+    D.nyo = (int64_t)outs.size();
+    outs.resize((size_t)C.n);
+    for (size_t o = 0; o < outs.size(); ++o) outs[o] = TPOut{C.Mbm + o * np2, 1};
+    RETURN_IF(upload(h, &D.mo, outs));
+    RETURN_IF(upload(h, &D.mpp, F.mp_ptr));
+    RETURN_IF(terms(F.mp, &D.mp));
+    D.nmo = (int64_t)outs.size();
+    const Level& H = P.lv[l + 1];
+    outs.resize((size_t)H.nnzb);
+    for (int64_t I = 0; I < H.n; ++I)
+      for (int64_t t = 0; t < H.row_len[I]; ++t)
+        outs[H.row_blk[I] + t] =
+            TPOut{C.A64 + (H.slice_blk[I / SLICE] + (int64_t)SLICE * t) * np2 + (I % SLICE), SLICE};
+    RETURN_IF(upload(h, &D.so, outs));
+    RETURN_IF(upload(h, &D.spp, F.sp_ptr));
+    RETURN_IF(terms(F.sp, &D.sp));
+    D.nso = (int64_t)outs.size();
+  }
+  std::vector<FluxPlan>().swap(P.fp);
+  std::vector<double>().swap(P.G0);
+  return CDGMG_OK;
+}
+
 int upload_problem(cdgmg_handle* h) {
   Problem& P = h->P;
   const int np = P.np, np2 = np * np;
@@ -277,6 +371,7 @@ int upload_problem(cdgmg_handle* h) {
   HIPCHK(hipHostMalloc((void**)&h->hscal, SC_N * sizeof(double)));
   HIPCHK(hipHostMalloc((void**)&h->herr, sizeof(int)));
   *h->herr = 0;
+  if (P.flux) RETURN_IF(upload_flux(h));
   // release large host copies that the device now holds
   std::vector<double>().swap(P.UA);
   std::vector<double>().swap(P.UH);
@@ -300,18 +395,40 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev) {
                          (const int32_t*)l0.cols, (const int64_t*)l0.sblk, (const double*)h->UA,
                          (const double*)h->UH, (const int8_t*)h->hostflag, (const int8_t*)h->revslot,
                          (const double*)h->kappa, l0.A64));
+  const bool flux = h->P.flux;
+  const int definite = flux ? 0 : 1;
+  const int tpb = std::min(1024, ((np2 + 63) / 64) * 64);
+  if (flux)
+    NP_DISPATCH(np, launch(h, -1, k_mass_kappa<NP>, dim3(grid_for(h->N0)), dim3(TPB), h->N0, (const double*)h->M,
+                           (const double*)h->kappa, l0.Mbm));
   for (int l = 0; l < h->L; ++l) {
     DLevel &f = h->lv[l], &c = h->lv[l + 1];
     NP_DISPATCH(np, launch(h, -1, k_diag_inverse<NP>, dim3(grid_for(f.n)), dim3(TPB), f.n,
-                           (const int64_t*)f.sblk, (const double*)f.A64, f.D64, h->err));
-    const int tpb = std::min(1024, ((np2 + 63) / 64) * 64);
+                           (const int64_t*)f.sblk, (const double*)f.A64, f.D64, h->err, definite));
+    if (flux) {
+      // M_l^{-1}, X = G_l L, Y = L^T X (= G_{l+1}), M_{l+1} = L^T M_l L, M_{l+1}^{-1}
+      NP_DISPATCH(np, launch(h, -1, k_block_inverse_bm<NP>, dim3(grid_for(f.n)), dim3(TPB), f.n,
+                             (const double*)f.Mbm, f.Minv, h->err));
+      NP_DISPATCH(np, launch(h, -1, k_triple<NP>, dim3((unsigned)f.nxo), dim3(tpb), f.nxo, (const TPOut*)f.xo,
+                             (const int64_t*)f.xpp, (const TPDev*)f.xp, 0));
+      NP_DISPATCH(np, launch(h, -1, k_triple<NP>, dim3((unsigned)f.nyo), dim3(tpb), f.nyo, (const TPOut*)f.yo,
+                             (const int64_t*)f.ypp, (const TPDev*)f.yp, 0));
+      NP_DISPATCH(np, launch(h, -1, k_triple<NP>, dim3((unsigned)f.nmo), dim3(tpb), f.nmo, (const TPOut*)f.mo,
+                             (const int64_t*)f.mpp, (const TPDev*)f.mp, 0));
+      NP_DISPATCH(np, launch(h, -1, k_block_inverse_bm<NP>, dim3(grid_for(c.n)), dim3(TPB), c.n,
+                             (const double*)c.Mbm, c.Minv, h->err));
+    }
     NP_DISPATCH(np, launch(h, -1, k_galerkin<NP>, dim3((unsigned)c.nnzb), dim3(tpb), c.nnzb,
                            (const int32_t*)c.blk_row, (const int64_t*)c.row_blk, (const int64_t*)c.plan_ptr,
                            (const int32_t*)c.plan_e, (const int32_t*)c.plan_w, (const int32_t*)f.cols,
                            (const int64_t*)f.sblk, (const double*)f.A64, (const double*)f.L64,
                            (const int64_t*)c.sblk, c.A64));
+    if (flux)  // A_{l+1} += -X^T M_l^{-1} X + Y^T M_{l+1}^{-1} Y
+      NP_DISPATCH(np, launch(h, -1, k_triple<NP>, dim3((unsigned)f.nso), dim3(tpb), f.nso, (const TPOut*)f.so,
+                             (const int64_t*)f.spp, (const TPDev*)f.sp, 1));
   }
-  RETURN_IF(check_err(h, CDGMG_ERR_SINGULAR, "setup: a diagonal block is not positive definite"));
+  RETURN_IF(check_err(h, CDGMG_ERR_SINGULAR, flux ? "setup: a diagonal or mass block is singular"
+                                                  : "setup: a diagonal block is not positive definite"));
   // coarsest: dense scatter + Gauss-Jordan inverse (ping-pong)
   DLevel& cl = h->lv[h->L];
   const int64_t nd = h->nd;
@@ -321,12 +438,13 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev) {
   double* in = h->dense1;
   double* out = h->Ainv64;
   for (int64_t k = 0; k < nd; ++k) {
-    launch(h, -1, k_gj_step, dim3(grid_for(nd * nd)), dim3(TPB), nd, k, (const double*)in, out, h->err);
+    launch(h, -1, k_gj_step, dim3(grid_for(nd * nd)), dim3(TPB), nd, k, (const double*)in, out, h->err, definite);
     std::swap(in, out);
   }
   if (in != h->Ainv64)
     HIPCHK(hipMemcpyAsync(h->Ainv64, in, (size_t)nd * nd * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
-  RETURN_IF(check_err(h, CDGMG_ERR_SINGULAR, "setup: the coarsest operator is not positive definite"));
+  RETURN_IF(check_err(h, CDGMG_ERR_SINGULAR, flux ? "setup: the coarsest operator is singular"
+                                                  : "setup: the coarsest operator is not positive definite"));
   if (h->o.mg_precision == CDGMG_MG_FP32) {
     for (int l = 0; l <= h->L; ++l) {
       DLevel& D = h->lv[l];
@@ -696,8 +814,8 @@ int cdgmg_setup(const cdgmg_mesh* mesh, int p, const double* kappa_dev, const cd
     set_error("setup: invalid options");
     return CDGMG_ERR_ARG;
   }
-  if (o.coarsening != CDGMG_COARSEN_PRIMAL) {
-    set_error("setup: flux coarsening is not available in this build of the solve path");
+  if (o.coarsening != CDGMG_COARSEN_PRIMAL && o.coarsening != CDGMG_COARSEN_FLUX) {
+    set_error("setup: unknown coarsening");
     return CDGMG_ERR_ARG;
   }
   cdgmg_handle* h = new (std::nothrow) cdgmg_handle();

@@ -172,3 +172,49 @@ def test_error_paths():
         solver.solve(np.full(mesh.n_elem * 3, np.nan))
     assert ei.value.code == -7
     solver.close()
+
+
+@pytest.mark.parametrize("name", ["2d_p2", "2d_p3", "3d_p2", "3d_p1"])
+def test_flux_coarse_operators_match_oracle(name):
+    # GPU flux-form coarsening (Sec. 4.1) against the oracle, which coarsens
+    # M, G, C separately and takes the Schur complement
+    d, n, p, levels, seed = CASES[name]
+    mesh = mesh2d_jittered_delaunay(n, 1) if d == 2 else mesh3d_kuhn(n, 1)
+    parents, sizes = cm.agglomerate(mesh, levels, seed, p=p)
+    kappa = np.random.default_rng(seed).uniform(0.5, 2.0, mesh.n_elem)
+    print("case", name, "flux", list(sizes), flush=True)
+    try:
+        solver = cm.Solver(mesh, p, kappa, parents, sizes, mg_precision=cm.MG_FP64, coarsening=cm.COARSEN_FLUX)
+    except cm.CdgmgError as e:  # an indefinite coarse diagonal block can be singular
+        pytest.skip("flux setup refused: %s" % e)
+    cdg = CDG(mesh.coords, mesh.e2v, mesh.face_bc, p)
+    H = Hierarchy(cdg, parents, kappa=kappa, coarsening="flux")
+    for l in range(len(sizes)):
+        A = cm.bsr_to_scipy(*solver.export_operator(l))
+        R = H.A[l]
+        err = abs(A - R).max() / abs(R).max()
+        assert err <= 1e-11, (name, l, err)
+    k2 = np.random.default_rng(3).uniform(0.2, 5.0, mesh.n_elem)
+    solver.update_kappa(k2)
+    H2 = Hierarchy(cdg, parents, kappa=k2, coarsening="flux")
+    for l in range(len(sizes)):
+        A = cm.bsr_to_scipy(*solver.export_operator(l))
+        assert abs(A - H2.A[l]).max() <= 1e-11 * abs(H2.A[l]).max()
+    solver.close()
+
+
+def test_flux_solve_small_mesh():
+    # on a small mesh the flux-coarsened levels are still definite and the
+    # flux-preconditioned FCG converges to the direct solution
+    mesh = mesh2d_jittered_delaunay(8, 1)
+    parents, sizes = cm.agglomerate(mesh, 3, 11, p=2)
+    kappa = np.ones(mesh.n_elem)
+    solver = cm.Solver(mesh, 2, kappa, parents, sizes, mg_precision=cm.MG_FP32, coarsening=cm.COARSEN_FLUX,
+                       tol=1e-11)
+    cdg = CDG(mesh.coords, mesh.e2v, mesh.face_bc, 2)
+    f = source_sine(cdg.nodes_phys().reshape(-1, 2))
+    u, info = solver.solve(f)
+    ref = spl.spsolve(cdg.A().tocsc(), cdg.M0() @ f)
+    assert info.rel_residual <= 1e-11
+    assert np.linalg.norm(u.cpu().numpy() - ref) <= 1e-9 * np.linalg.norm(ref)
+    solver.close()
