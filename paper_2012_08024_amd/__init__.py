@@ -221,6 +221,7 @@ class Solver:
         stream = torch.cuda.current_stream().cuda_stream
         _check(lib.cdgmg_setup(ctypes.byref(self.hm.c), p, kappa.data_ptr(), ctypes.byref(hier),
                                ctypes.byref(self.opts), ctypes.c_void_p(stream), ctypes.byref(self.handle)))
+        self._kappa = kappa.detach().clone()
 
     def _dev(self, a, dtype=None):
         torch = self.torch
@@ -274,6 +275,13 @@ class Solver:
     def update_kappa(self, kappa):
         kappa = self._dev(kappa)
         _check(lib.cdgmg_update_kappa(self.handle, kappa.data_ptr()))
+        self._kappa = kappa.detach().clone()
+
+    def ensure_kappa(self, kappa):
+        """Rebuild the operators only if kappa differs from the current one."""
+        kappa = self._dev(kappa)
+        if kappa.shape != self._kappa.shape or not bool(self.torch.equal(kappa, self._kappa)):
+            self.update_kappa(kappa)
 
     def level_info(self):
         nl = ctypes.c_int(0)

@@ -12,8 +12,9 @@ ARCH = os.environ.get("CDGMG_ARCH", "gfx950")
 HOST_SRC = ["host_mesh.cpp", "host_fem.cpp", "host_flux.cpp", "host_debug.cpp"]
 DEV_SRC = ["solver.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-# packed FP32 instructions are disabled for all device code
-HIP_FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=" + ARCH,
+# packed FP32 instructions are disabled for all device code; FMA contraction
+# honours the local "fp contract(off)" of the compensated (error-free) sums
+HIP_FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=" + ARCH, "-ffp-contract=fast-honor-pragmas",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-command-line-argument"]
 

@@ -667,17 +667,21 @@ __global__ __launch_bounds__(TPB) void k_spmv_dots(int64_t n, const int32_t* __r
 // double-double sums (Ogita, Rump & Oishi, "Accurate sum and dot product",
 // 2005, algorithm Dot2) and the iterate is kept as x_hi + x_lo.  These
 // kernels are bound by HBM bytes, so the extra FP64 operations are free.
+// FMA contraction must stay off in these routines: fusing the rounded product
+// p = a x into the following sum would make the error terms double-count.
 __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
-  s = __dadd_rn(a, b);
-  const double bb = __dsub_rn(s, a);
-  e = __dadd_rn(__dsub_rn(a, __dsub_rn(s, bb)), __dsub_rn(b, bb));
+#pragma clang fp contract(off)
+  s = (a + b);
+  const double bb = (s - a);
+  e = (a - (s - bb)) + (b - bb);
 }
 __device__ __forceinline__ void dot2_acc(double a, double x, double& s, double& c) {
-  const double p = __dmul_rn(a, x);
-  const double ep = __fma_rn(a, x, -p);
+#pragma clang fp contract(off)
+  const double p = (a * x);
+  const double ep = __builtin_fma(a, x, -p);
   double t;
   two_sum(s, p, s, t);
-  c = __dadd_rn(c, __dadd_rn(t, ep));
+  c = (c + (t + ep));
 }
 
 // q = A p (compensated) with partial sums of (p, q) and (p, r)
@@ -686,6 +690,7 @@ __global__ __launch_bounds__(TPB) void k_spmv2_dots(int64_t n, const int32_t* __
                                                     const int64_t* __restrict__ sblk, const double* __restrict__ A,
                                                     const double* __restrict__ p, const double* __restrict__ rr,
                                                     double* __restrict__ q, double* __restrict__ part) {
+#pragma clang fp contract(off)
   constexpr int NP2 = NP * NP;
   __shared__ double sh[TPB / WAVE];
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -710,7 +715,7 @@ __global__ __launch_bounds__(TPB) void k_spmv2_dots(int64_t n, const int32_t* __
     }
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
-      const double qi = __dadd_rn(s[i], c[i]);
+      const double qi = (s[i] + c[i]);
       q[r * NP + i] = qi;
       const double pi = p[r * NP + i];
       pq += pi * qi;
@@ -730,6 +735,7 @@ __global__ __launch_bounds__(TPB) void k_residual2(int64_t n, const int32_t* __r
                                                    const double* __restrict__ b, const double* __restrict__ xh,
                                                    const double* __restrict__ xl, double* __restrict__ rt,
                                                    double* __restrict__ part) {
+#pragma clang fp contract(off)
   constexpr int NP2 = NP * NP;
   __shared__ double sh[TPB / WAVE];
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -759,12 +765,12 @@ __global__ __launch_bounds__(TPB) void k_residual2(int64_t n, const int32_t* __r
         for (int j = 0; j < NP; ++j) {
           const double a = Ab[(i * NP + j) * WAVE];
           dot2_acc(-a, hv[j], s[i], c[i]);
-          c[i] = __fma_rn(-a, lv[j], c[i]);
+          c[i] = __builtin_fma(-a, lv[j], c[i]);
         }
     }
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
-      const double v = __dadd_rn(s[i], c[i]);
+      const double v = (s[i] + c[i]);
       rt[r * NP + i] = v;
       rr += v * v;
     }
@@ -778,18 +784,19 @@ __global__ __launch_bounds__(TPB) void k_update_xr2(int64_t m, const double* __r
                                                     const double* __restrict__ q, double* __restrict__ xh,
                                                     double* __restrict__ xl, double* __restrict__ r,
                                                     const double* __restrict__ s, double* __restrict__ part) {
+#pragma clang fp contract(off)
   __shared__ double sh[TPB / WAVE];
   const double a = s[SC_ALPHA];
   double rr = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-    const double y = __dmul_rn(a, p[i]);
-    const double ey = __fma_rn(a, p[i], -y);
+    const double y = (a * p[i]);
+    const double ey = __builtin_fma(a, p[i], -y);
     double hi, e;
     two_sum(xh[i], y, hi, e);
-    const double lo = __dadd_rn(xl[i], __dadd_rn(e, ey));
-    const double nh = __dadd_rn(hi, lo);
+    const double lo = (xl[i] + (e + ey));
+    const double nh = (hi + lo);
     xh[i] = nh;
-    xl[i] = __dsub_rn(lo, __dsub_rn(nh, hi));
+    xl[i] = (lo - (nh - hi));
     const double ri = r[i] - a * q[i];
     r[i] = ri;
     rr += ri * ri;
@@ -801,10 +808,11 @@ __global__ __launch_bounds__(TPB) void k_update_xr2(int64_t m, const double* __r
 // out[perm[r]] = xh[r] + xl[r]
 __global__ void k_out_dd(int64_t n, int np, const int32_t* __restrict__ perm, const double* __restrict__ xh,
                          const double* __restrict__ xl, double* __restrict__ out) {
+#pragma clang fp contract(off)
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n * np) return;
   const int64_t r = idx / np, j = idx % np;
-  out[(int64_t)perm[r] * np + j] = __dadd_rn(xh[idx], xl[idx]);
+  out[(int64_t)perm[r] * np + j] = xh[idx] + xl[idx];
 }
 
 // scalar bookkeeping (single thread)

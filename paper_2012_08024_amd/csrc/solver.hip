@@ -649,6 +649,10 @@ int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
   double rel = 0.0, rel_true = 0.0;
   int status = CDGMG_NOT_CONVERGED;
   double rho_last = nb;
+  // near the tolerance the rounding of a plain FP64 q = A p (about
+  // eps |A| |alpha p| per step) would make the recursive residual drift from
+  // the true one; from rel <= 1e4 tol on, q is accumulated compensated
+  bool accurate = false;
   if (nb == 0.0) {
     status = CDGMG_OK;
   } else {
@@ -669,9 +673,15 @@ int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
                (const double*)h->scal, 1.0, it == 0 ? 1 : 0);
       }
       const unsigned g = grid_for(d0.n);
-      NP_DISPATCH(np, launch(h, CDGMG_K_SPMV, k_spmv_dots<NP>, dim3(g), dim3(TPB), d0.n, (const int32_t*)d0.cols,
-                             (const int64_t*)d0.sblk, (const double*)d0.A64, (const double*)h->p,
-                             (const double*)h->r, h->q, h->part));
+      if (accurate) {
+        NP_DISPATCH(np, launch(h, CDGMG_K_SPMV, k_spmv2_dots<NP>, dim3(g), dim3(TPB), d0.n,
+                               (const int32_t*)d0.cols, (const int64_t*)d0.sblk, (const double*)d0.A64,
+                               (const double*)h->p, (const double*)h->r, h->q, h->part));
+      } else {
+        NP_DISPATCH(np, launch(h, CDGMG_K_SPMV, k_spmv_dots<NP>, dim3(g), dim3(TPB), d0.n,
+                               (const int32_t*)d0.cols, (const int64_t*)d0.sblk, (const double*)d0.A64,
+                               (const double*)h->p, (const double*)h->r, h->q, h->part));
+      }
       launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)g, 2, h->scal, SC_PQ);
       launch(h, CDGMG_K_VECTOR, k_scalars, dim3(1), dim3(1), h->scal, fcg ? 2 : 3);
       const unsigned gu = std::min<unsigned>(1024, grid_for(m));
@@ -687,6 +697,7 @@ int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
         break;
       }
       rel = std::sqrt(rr) / nb;
+      if (rel <= 1e4 * h->o.tol) accurate = true;
       if (info && info->history && it <= info->history_len) info->history[it - 1] = rel;
       // reliable updates: the recursive residual is replaced by the compensated
       // true residual whenever it has dropped 100x since the last replacement,

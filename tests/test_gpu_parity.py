@@ -218,3 +218,24 @@ def test_flux_solve_small_mesh():
     assert info.rel_residual <= 1e-11
     assert np.linalg.norm(u.cpu().numpy() - ref) <= 1e-9 * np.linalg.norm(ref)
     solver.close()
+
+
+def test_compensated_outer_loop_reaches_below_fp64_floor():
+    # 2D p=3 at n=72: the FP64 rounding noise of one residual is ~3e-11 of
+    # ||b|| (eps || |A||u| || / ||b||); the compensated outer loop (Dot2 q and
+    # true residual, double-double iterate) still reaches 1e-13
+    mesh = mesh2d_jittered_delaunay(72, 2)
+    parents, sizes = cm.agglomerate(mesh, 5, 12, p=3)
+    solver = cm.Solver(mesh, 3, np.ones(mesh.n_elem), parents, sizes, tol=1e-13, max_iter=400)
+    f = source_sine(solver.node_coords().reshape(-1, 2))
+    u, info = solver.solve(f, history=True)
+    print("iterations", info.iterations, "true residual", info.rel_residual, flush=True)
+    assert info.rel_residual <= 1e-13
+    cdg = CDG(mesh.coords, mesh.e2v, mesh.face_bc, 3)
+    A = cdg.A()
+    b = cdg.M0() @ f
+    floor = 2.2e-16 * np.linalg.norm(abs(A) @ np.abs(u.cpu().numpy())) / np.linalg.norm(b)
+    assert floor > 1e-12  # the target is below what a plain FP64 residual can resolve
+    ref = spl.spsolve(A.tocsc(), b)
+    assert np.linalg.norm(u.cpu().numpy() - ref) <= 1e-9 * np.linalg.norm(ref)
+    solver.close()

@@ -105,7 +105,10 @@ def test_cost_is_near_linear():
     for n in (24, 48):
         m = mesh2d_jittered_delaunay(n, 1)
         pairs = Topology(m.e2v, m.coords).neighbor_pairs()
-        t0 = time.perf_counter()
-        build_hierarchy(m.e2v, pairs, 2, 3)
-        ts.append(time.perf_counter() - t0)
+        best = float("inf")
+        for _ in range(3):  # best of three against scheduling noise
+            t0 = time.perf_counter()
+            build_hierarchy(m.e2v, pairs, 2, 3)
+            best = min(best, time.perf_counter() - t0)
+        ts.append(best)
     assert ts[1] / ts[0] < 8.0
