@@ -103,7 +103,10 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=112)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--kernel-variant", type=int, default=0, help="0 auto, 1 thread per row, 2 row-split")
+    ap.add_argument("--kernel-variant", type=int, default=0,
+                    help="V-cycle kernel family (see cdgmg_options.kernel_variant); 0 = auto")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the solve is single-GPU; "
@@ -261,17 +264,24 @@ def main():
         "kernel_ms_per_solve": {k: kms[k] / args.steps for k in cm.K_NAMES if kcnt[k]},
         "kernel_launches_per_solve": {k: kcnt[k] / args.steps for k in cm.K_NAMES if kcnt[k]},
         "roofline": {
-            "kernel": "k_smooth<float,%d> (level-0 damped block-Jacobi sweep)" % npb,
+            "kernel": "level-0 damped block-Jacobi sweep (k_smooth_hs<float,%d,H>, FP32)" % npb,
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "algorithmic_bytes_per_launch": sb, "avg_launch_ms": avg_smooth_ms,
         },
-        "outer_spmv_roofline": {"kernel": "k_spmv_dots<%d> (FP64)" % npb, "achieved": spmv_gbs,
+        "outer_spmv_roofline": {"kernel": "outer q = A_0 p with dots (k_spmv_dots_hs<%d,H>, FP64)" % npb, "achieved": spmv_gbs,
                                 "frac": spmv_gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": spb,
                                 "avg_launch_ms": avg_spmv_ms},
         "cpu_baseline": cpu,
     }
     s32.close()
+    if args.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_probe_bytes"] = int(src.numel() * 4)
     print(json.dumps(result), flush=True)
 
 

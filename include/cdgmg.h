@@ -96,8 +96,11 @@ typedef struct cdgmg_options {
   double tol;          /* relative true residual ||b - A x|| / ||b||; default 1e-10 */
   int max_iter;        /* default 500 */
   int profile;         /* nonzero: time kernel classes with HIP events */
-  int kernel_variant;  /* V-cycle sweep/restriction kernels: 0 auto (slot-split below 1e5 rows),
-                          1 thread per row, 2 slot-split (4 wavefronts share a 64-row slice's slots) */
+  int kernel_variant;  /* V-cycle sweep/restriction kernels: 0 auto (level 0 thread per row, or
+                          slot-split for n_p >= 20; coarse levels wave per row), 1 thread per row
+                          everywhere, 2 slot-split everywhere (4 wavefronts share a 64-row slice's
+                          slots), 3 thread per row on level 0 + wave per row on coarse levels,
+                          4 slot-split on level 0 + wave per row on coarse levels */
 } cdgmg_options;
 
 typedef struct cdgmg_solve_info {

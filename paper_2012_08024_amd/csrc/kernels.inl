@@ -529,6 +529,179 @@ __global__ __launch_bounds__(WAVE * NW) void k_residual_restrict_ss(
   }
 }
 
+// ------------------------------------------------------------------
+// Component-split kernels for wide blocks (n_p = 20 on level 0): H wavefronts
+// per 64-row slice, wavefront h owns output components [h n_p/H, (h+1) n_p/H)
+// of the slice's rows; each keeps n_p/H accumulators and the row's gathered x
+// block, so less state per thread and more loads in flight.  The residual is
+// exchanged through LDS for the D^{-1} and L_e^T products.
+template <typename T, int NP, int H>
+__device__ __forceinline__ void hs_residual(int64_t r, int lane, int h, bool valid, const int32_t* __restrict__ cols,
+                                            const int64_t* __restrict__ sblk, const T* __restrict__ A,
+                                            const T* __restrict__ b, const T* __restrict__ x, T (*sres)[WAVE]) {
+  constexpr int NP2 = NP * NP, NI = NP / H;
+  if (valid) {
+    T acc[NI];
+#pragma unroll
+    for (int t = 0; t < NI; ++t) acc[t] = b[r * NP + h * NI + t];
+    const int64_t B = sblk[r / WAVE];
+    const int W = (int)((sblk[r / WAVE + 1] - B) / WAVE);
+    for (int w = 0; w < W; ++w) {
+      const int32_t c = cols[B + (int64_t)WAVE * w + lane];
+      T xv[NP];
+#pragma unroll
+      for (int j = 0; j < NP; ++j) xv[j] = x[(int64_t)c * NP + j];
+      const T* Ab = A + (B + (int64_t)WAVE * w) * NP2 + (int64_t)h * NI * NP * WAVE + lane;
+#pragma unroll
+      for (int t = 0; t < NI; ++t)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) acc[t] -= Ab[(t * NP + j) * WAVE] * xv[j];
+    }
+#pragma unroll
+    for (int t = 0; t < NI; ++t) sres[h * NI + t][lane] = acc[t];
+  }
+  __syncthreads();
+}
+
+template <typename T, int NP, int H>
+__global__ __launch_bounds__(WAVE * H) void k_smooth_hs(int64_t n, const int32_t* __restrict__ cols,
+                                                        const int64_t* __restrict__ sblk, const T* __restrict__ A,
+                                                        const T* __restrict__ Dinv, const T* __restrict__ b,
+                                                        const T* __restrict__ xin, T omega, T* __restrict__ xout) {
+  constexpr int NP2 = NP * NP, NI = NP / H;
+  __shared__ T sres[NP][WAVE];
+  const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
+  const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
+  const bool valid = r < n;
+  hs_residual<T, NP, H>(r, lane, h, valid, cols, sblk, A, b, xin, sres);
+  if (!valid) return;
+  const T* D = Dinv + (int64_t)blockIdx.x * WAVE * NP2 + lane;
+#pragma unroll
+  for (int t = 0; t < NI; ++t) {
+    const int i = h * NI + t;
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) s += D[(i * NP + j) * WAVE] * sres[j][lane];
+    xout[r * NP + i] = xin[r * NP + i] + omega * s;
+  }
+}
+
+template <typename T, int NP, int H>
+__global__ __launch_bounds__(WAVE * H) void k_residual_restrict_hs(
+    int64_t n, const int32_t* __restrict__ cols, const int64_t* __restrict__ sblk, const T* __restrict__ A,
+    const T* __restrict__ b, const T* __restrict__ x, const T* __restrict__ Lb, T* __restrict__ t_out) {
+  constexpr int NP2 = NP * NP, NI = NP / H;
+  __shared__ T sres[NP][WAVE];
+  const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
+  const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
+  const bool valid = r < n;
+  hs_residual<T, NP, H>(r, lane, h, valid, cols, sblk, A, b, x, sres);
+  if (!valid) return;
+  const T* Lr = Lb + (int64_t)blockIdx.x * WAVE * NP2 + lane;
+#pragma unroll
+  for (int t = 0; t < NI; ++t) {
+    const int j = h * NI + t;
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) s += Lr[(i * NP + j) * WAVE] * sres[i][lane];
+    t_out[r * NP + j] = s;
+  }
+}
+
+// ------------------------------------------------------------------
+// Wave-per-row kernels for the coarse levels.  Row r's blocks are stored as a
+// dense n_p x (len_r n_p) strip, component-major (unpadded):
+//     R[(off_r n_p + i) (len_r n_p) ... ] -> element (i, k) at base_r + i * len_r n_p + k,
+// with k = w n_p + j for slot w, column j.  One wavefront per row: lane l
+// handles k = l, l + 64, ... for every i (coalesced strip loads, a short chain
+// per lane); the n_p partial sums are reduced with xor-shuffles so every lane
+// holds the row residual.
+template <typename T>
+__device__ __forceinline__ T wave_allsum(T v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T, int NP>
+__device__ __forceinline__ void wpr_residual(int64_t r, int lane, const int32_t* __restrict__ cols,
+                                             const int64_t* __restrict__ roff, const T* __restrict__ R,
+                                             const T* __restrict__ b, const T* __restrict__ x, T* res) {
+  const int64_t o = roff[r];
+  const int len = (int)(roff[r + 1] - o);
+  const int K = len * NP;
+  const T* Rr = R + o * NP * NP;
+  T acc[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) acc[i] = 0;
+  for (int k = lane; k < K; k += WAVE) {
+    const int w = k / NP, j = k - w * NP;
+    const T xv = x[(int64_t)cols[o + w] * NP + j];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) acc[i] += Rr[(int64_t)i * K + k] * xv;
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) res[i] = b[r * NP + i] - wave_allsum(acc[i]);
+}
+
+template <typename T, int NP>
+__global__ __launch_bounds__(TPB) void k_smooth_wpr(int64_t n, const int32_t* __restrict__ cols,
+                                                    const int64_t* __restrict__ roff, const T* __restrict__ R,
+                                                    const T* __restrict__ Dinv, const T* __restrict__ b,
+                                                    const T* __restrict__ xin, T omega, T* __restrict__ xout) {
+  constexpr int NP2 = NP * NP;
+  const int lane = threadIdx.x % WAVE;
+  const int64_t r = (int64_t)blockIdx.x * (TPB / WAVE) + threadIdx.x / WAVE;
+  if (r >= n) return;
+  T res[NP];
+  wpr_residual<T, NP>(r, lane, cols, roff, R, b, xin, res);
+  if (lane < NP) {
+    const T* D = Dinv + (r / WAVE) * WAVE * NP2 + (r % WAVE);
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) s += D[(lane * NP + j) * WAVE] * res[j];
+    xout[r * NP + lane] = xin[r * NP + lane] + omega * s;
+  }
+}
+
+template <typename T, int NP>
+__global__ __launch_bounds__(TPB) void k_residual_restrict_wpr(int64_t n, const int32_t* __restrict__ cols,
+                                                               const int64_t* __restrict__ roff,
+                                                               const T* __restrict__ R, const T* __restrict__ b,
+                                                               const T* __restrict__ x, const T* __restrict__ Lb,
+                                                               T* __restrict__ t) {
+  constexpr int NP2 = NP * NP;
+  const int lane = threadIdx.x % WAVE;
+  const int64_t r = (int64_t)blockIdx.x * (TPB / WAVE) + threadIdx.x / WAVE;
+  if (r >= n) return;
+  T res[NP];
+  wpr_residual<T, NP>(r, lane, cols, roff, R, b, x, res);
+  if (lane < NP) {
+    const T* Lr = Lb + (r / WAVE) * WAVE * NP2 + (r % WAVE);
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) s += Lr[(i * NP + lane) * WAVE] * res[i];
+    t[r * NP + lane] = s;
+  }
+}
+
+// sliced-ELL (FP64) -> wave-per-row strips (type T), setup
+template <typename T, int NP>
+__global__ void k_to_wpr(int64_t n, const int64_t* __restrict__ sblk, const int64_t* __restrict__ roff,
+                         const double* __restrict__ A, T* __restrict__ R) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int64_t B = sblk[r / WAVE];
+  const int lane = (int)(r % WAVE);
+  const int64_t o = roff[r];
+  const int len = (int)(roff[r + 1] - o);
+  const int K = len * NP;
+  T* Rr = R + o * NP2;
+  for (int w = 0; w < len; ++w)
+    for (int i = 0; i < NP; ++i)
+      for (int j = 0; j < NP; ++j) Rr[(int64_t)i * K + w * NP + j] = (T)A[blk_off(B, w, NP2, i * NP + j, lane)];
+}
+
 // ---------------------------------------------------------- outer (FP64) kernels
 // b = M_0 f (caller order -> internal order)
 template <int NP>
@@ -800,6 +973,111 @@ __global__ __launch_bounds__(TPB) void k_update_xr2(int64_t m, const double* __r
     const double ri = r[i] - a * q[i];
     r[i] = ri;
     rr += ri * ri;
+  }
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = rr;
+}
+
+// Component-split outer kernels (H wavefronts per slice, as k_smooth_hs):
+// q = A p with partial sums of (p, q), (p, r); COMP selects the compensated
+// (Dot2) accumulation.  One partial per slice.
+template <int NP, int H, bool COMP>
+__global__ __launch_bounds__(WAVE * H) void k_spmv_dots_hs(int64_t n, const int32_t* __restrict__ cols,
+                                                           const int64_t* __restrict__ sblk,
+                                                           const double* __restrict__ A, const double* __restrict__ p,
+                                                           const double* __restrict__ rr, double* __restrict__ q,
+                                                           double* __restrict__ part) {
+#pragma clang fp contract(off)
+  constexpr int NP2 = NP * NP, NI = NP / H;
+  __shared__ double sh[TPB / WAVE];
+  const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
+  const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
+  double pq = 0.0, pr = 0.0;
+  if (r < n) {
+    const int64_t B = sblk[r / WAVE];
+    const int W = (int)((sblk[r / WAVE + 1] - B) / WAVE);
+    double s[NI], c[NI];
+#pragma unroll
+    for (int t = 0; t < NI; ++t) s[t] = c[t] = 0.0;
+    for (int w = 0; w < W; ++w) {
+      const int32_t col = cols[B + (int64_t)WAVE * w + lane];
+      double xv[NP];
+#pragma unroll
+      for (int j = 0; j < NP; ++j) xv[j] = p[(int64_t)col * NP + j];
+      const double* Ab = A + (B + (int64_t)WAVE * w) * NP2 + (int64_t)h * NI * NP * WAVE + lane;
+#pragma unroll
+      for (int t = 0; t < NI; ++t)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+          if constexpr (COMP)
+            dot2_acc(Ab[(t * NP + j) * WAVE], xv[j], s[t], c[t]);
+          else
+            s[t] = __builtin_fma(Ab[(t * NP + j) * WAVE], xv[j], s[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NI; ++t) {
+      const int i = h * NI + t;
+      const double qi = COMP ? (s[t] + c[t]) : s[t];
+      q[r * NP + i] = qi;
+      const double pi = p[r * NP + i];
+      pq = __builtin_fma(pi, qi, pq);
+      pr = __builtin_fma(pi, rr[r * NP + i], pr);
+    }
+  }
+  pq = block_sum(pq, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = pq;
+  pr = block_sum(pr, sh);
+  if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = pr;
+}
+
+// true residual rt = b - A (xh + xl), compensated, component-split; partial ||rt||^2 per slice
+template <int NP, int H>
+__global__ __launch_bounds__(WAVE * H) void k_residual2_hs(int64_t n, const int32_t* __restrict__ cols,
+                                                           const int64_t* __restrict__ sblk,
+                                                           const double* __restrict__ A, const double* __restrict__ b,
+                                                           const double* __restrict__ xh,
+                                                           const double* __restrict__ xl, double* __restrict__ rt,
+                                                           double* __restrict__ part) {
+#pragma clang fp contract(off)
+  constexpr int NP2 = NP * NP, NI = NP / H;
+  __shared__ double sh[TPB / WAVE];
+  const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
+  const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
+  double rr = 0.0;
+  if (r < n) {
+    const int64_t B = sblk[r / WAVE];
+    const int W = (int)((sblk[r / WAVE + 1] - B) / WAVE);
+    double s[NI], c[NI];
+#pragma unroll
+    for (int t = 0; t < NI; ++t) {
+      s[t] = b[r * NP + h * NI + t];
+      c[t] = 0.0;
+    }
+    for (int w = 0; w < W; ++w) {
+      const int32_t col = cols[B + (int64_t)WAVE * w + lane];
+      double hv[NP], lv[NP];
+#pragma unroll
+      for (int j = 0; j < NP; ++j) {
+        hv[j] = xh[(int64_t)col * NP + j];
+        lv[j] = xl[(int64_t)col * NP + j];
+      }
+      const double* Ab = A + (B + (int64_t)WAVE * w) * NP2 + (int64_t)h * NI * NP * WAVE + lane;
+#pragma unroll
+      for (int t = 0; t < NI; ++t)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+          const double a = Ab[(t * NP + j) * WAVE];
+          dot2_acc(-a, hv[j], s[t], c[t]);
+          c[t] = __builtin_fma(-a, lv[j], c[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NI; ++t) {
+      const double v = s[t] + c[t];
+      rt[r * NP + h * NI + t] = v;
+      rr = __builtin_fma(v, v, rr);
+    }
   }
   rr = block_sum(rr, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = rr;

@@ -70,6 +70,11 @@ struct DLevel {
   TPOut *xo = nullptr, *yo = nullptr, *mo = nullptr, *so = nullptr;
   int64_t *xpp = nullptr, *ypp = nullptr, *mpp = nullptr, *spp = nullptr;
   int64_t nxo = 0, nyo = 0, nmo = 0, nso = 0;
+  // wave-per-row strips of A_l (coarse levels): compact columns, row offsets
+  int32_t* wcols = nullptr;
+  int64_t* woff = nullptr;
+  float* R32 = nullptr;
+  double* R64 = nullptr;
 };
 
 struct ProfEv {
@@ -318,6 +323,18 @@ int upload_problem(cdgmg_handle* h) {
       }
       RETURN_IF(upload(h, &D.parent, H.parent));
     }
+    if (l >= 1 && l < P.L) {
+      std::vector<int32_t> wc(H.nnzb);
+      for (int64_t r = 0; r < H.n; ++r)
+        for (int w = 0; w < H.row_len[r]; ++w)
+          wc[H.row_blk[r] + w] = H.cols[H.slice_blk[r / SLICE] + (int64_t)SLICE * w + r % SLICE];
+      RETURN_IF(upload(h, &D.wcols, wc));
+      RETURN_IF(upload(h, &D.woff, H.row_blk));
+      if (fp32)
+        RETURN_IF(dalloc(h, &D.R32, (size_t)H.nnzb * np2));
+      else
+        RETURN_IF(dalloc(h, &D.R64, (size_t)H.nnzb * np2));
+    }
     if (l >= 1) {
       std::vector<int32_t> cs(H.child_start.begin(), H.child_start.end());
       RETURN_IF(upload(h, &D.child_start, cs));
@@ -364,7 +381,7 @@ int upload_problem(cdgmg_handle* h) {
     HIPCHK(hipMemsetAsync(*v, 0, m * sizeof(double), h->stream));
   }
   RETURN_IF(dalloc(h, &h->scal, SC_N));
-  h->nparts = (int)std::max<int64_t>(1024, grid_for(P.N0));
+  h->nparts = (int)std::max<int64_t>(1024, (P.N0 + SLICE - 1) / SLICE + 1);
   RETURN_IF(dalloc(h, &h->part, 2 * (size_t)h->nparts));
   RETURN_IF(dalloc(h, &h->err, 1));
   HIPCHK(hipMemsetAsync(h->err, 0, sizeof(int), h->stream));
@@ -429,6 +446,16 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev) {
   }
   RETURN_IF(check_err(h, CDGMG_ERR_SINGULAR, flux ? "setup: a diagonal or mass block is singular"
                                                   : "setup: a diagonal block is not positive definite"));
+  // wave-per-row strips of the coarse operators used by the V-cycle
+  for (int l = 1; l < h->L; ++l) {
+    DLevel& D = h->lv[l];
+    if (D.R32)
+      NP_DISPATCH(np, launch(h, -1, k_to_wpr<float, NP>, dim3(grid_for(D.n)), dim3(TPB), D.n,
+                             (const int64_t*)D.sblk, (const int64_t*)D.woff, (const double*)D.A64, D.R32));
+    if (D.R64)
+      NP_DISPATCH(np, launch(h, -1, k_to_wpr<double, NP>, dim3(grid_for(D.n)), dim3(TPB), D.n,
+                             (const int64_t*)D.sblk, (const int64_t*)D.woff, (const double*)D.A64, D.R64));
+  }
   // coarsest: dense scatter + Gauss-Jordan inverse (ping-pong)
   DLevel& cl = h->lv[h->L];
   const int64_t nd = h->nd;
@@ -471,6 +498,7 @@ struct Ops<float> {
   static const float* D(const DLevel& d) { return d.D32; }
   static const float* L(const DLevel& d) { return d.L32; }
   static const float* Ainv(const cdgmg_handle* h) { return h->Ainv32; }
+  static const float* R(const DLevel& d) { return d.R32; }
 };
 template <>
 struct Ops<double> {
@@ -478,14 +506,61 @@ struct Ops<double> {
   static const double* D(const DLevel& d) { return d.D64; }
   static const double* L(const DLevel& d) { return d.L64; }
   static const double* Ainv(const cdgmg_handle* h) { return h->Ainv64; }
+  static const double* R(const DLevel& d) { return d.R64; }
 };
 
-// slot-split kernels on levels too small to fill the GPU with one thread per row
-bool use_rs(const cdgmg_handle* h, int l) {
-  if (h->o.kernel_variant == 1) return false;
-  if (h->o.kernel_variant == 2) return true;
-  return h->lv[l].n < 100000;
+// V-cycle kernel family per level: thread per row, slot-split (NW wavefronts
+// share a slice's slots) or wave per row (coarse strips)
+enum { KM_ROW = 0, KM_SS = 1, KM_WPR = 2, KM_HS2 = 3, KM_HS4 = 4 };
+int kmode(const cdgmg_handle* h, int l) {
+  const int v = h->o.kernel_variant;
+  if (v == 1) return KM_ROW;
+  if (v == 2) return KM_SS;
+  if (l >= 1) return KM_WPR;
+  if (v == 3) return KM_ROW;
+  if (v == 4) return KM_SS;
+  if (v == 5) return h->np % 2 == 0 ? KM_HS2 : KM_ROW;
+  if (v == 6) return h->np % 4 == 0 ? KM_HS4 : (h->np % 2 == 0 ? KM_HS2 : KM_ROW);
+  if (h->np % 4 == 0 && h->np >= 20) return KM_HS4;  // auto
+  if (h->np % 2 == 0 && h->np >= 6) return KM_HS2;
+  return KM_ROW;
 }
+
+// launch helpers for the component-split family (H must divide n_p)
+template <typename T, int NP, int H>
+void launch_hs_smooth(cdgmg_handle* h, int cls, DLevel& d, const T* A, const T* Dv, const T* b, const T* x, T omega,
+                      T* xo) {
+  if constexpr (NP % H == 0)
+    launch(h, cls, k_smooth_hs<T, NP, H>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n, (const int32_t*)d.cols,
+           (const int64_t*)d.sblk, A, Dv, b, x, omega, xo);
+}
+template <int NP, int H>
+void launch_spmv_hs(cdgmg_handle* h, DLevel& d, bool accurate) {
+  if constexpr (NP % H == 0) {
+    if (accurate)
+      launch(h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, true>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
+             (const int32_t*)d.cols, (const int64_t*)d.sblk, (const double*)d.A64, (const double*)h->p,
+             (const double*)h->r, h->q, h->part);
+    else
+      launch(h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, false>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
+             (const int32_t*)d.cols, (const int64_t*)d.sblk, (const double*)d.A64, (const double*)h->p,
+             (const double*)h->r, h->q, h->part);
+  }
+}
+template <int NP, int H>
+void launch_residual2_hs(cdgmg_handle* h, DLevel& d) {
+  if constexpr (NP % H == 0)
+    launch(h, CDGMG_K_VECTOR, k_residual2_hs<NP, H>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
+           (const int32_t*)d.cols, (const int64_t*)d.sblk, (const double*)d.A64, (const double*)h->b,
+           (const double*)h->x, (const double*)h->xl, h->r, h->part);
+}
+template <typename T, int NP, int H>
+void launch_hs_restrict(cdgmg_handle* h, DLevel& d, const T* A, const T* b, const T* x, const T* L, T* t) {
+  if constexpr (NP % H == 0)
+    launch(h, CDGMG_K_RESTRICT, k_residual_restrict_hs<T, NP, H>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
+           (const int32_t*)d.cols, (const int64_t*)d.sblk, A, b, x, L, t);
+}
+bool use_rs(const cdgmg_handle* h, int l) { return kmode(h, l) == KM_SS; }
 
 // thread-per-row kernels: one-wavefront workgroups on small levels spread the
 // few wavefronts over the compute units
@@ -496,8 +571,16 @@ void smooth_sweeps(cdgmg_handle* h, int l, int count, T** x, T** xb) {
   DLevel& d = h->lv[l];
   const T omega = (T)h->o.omega;
   const int cls = l == 0 ? CDGMG_K_SMOOTH0 : CDGMG_K_SMOOTH;
+  const int km = kmode(h, l);
   for (int s = 0; s < count; ++s) {
-    if (use_rs(h, l))
+    if (km == KM_HS2)
+      launch_hs_smooth<T, NP, 2>(h, cls, d, Ops<T>::A(d), Ops<T>::D(d), (const T*)d.b, (const T*)*x, omega, *xb);
+    else if (km == KM_HS4)
+      launch_hs_smooth<T, NP, 4>(h, cls, d, Ops<T>::A(d), Ops<T>::D(d), (const T*)d.b, (const T*)*x, omega, *xb);
+    else if (km == KM_WPR)
+      launch(h, cls, k_smooth_wpr<T, NP>, dim3(grid_for(d.n * WAVE)), dim3(TPB), d.n, (const int32_t*)d.wcols,
+             (const int64_t*)d.woff, Ops<T>::R(d), Ops<T>::D(d), (const T*)d.b, (const T*)*x, omega, *xb);
+    else if (km == KM_SS)
       launch(h, cls, k_smooth_ss<T, NP>, dim3((unsigned)d.ns), dim3(WAVE * NW), d.n, (const int32_t*)d.cols,
              (const int64_t*)d.sblk, Ops<T>::A(d), Ops<T>::D(d), (const T*)d.b, (const T*)*x, omega, *xb);
     else
@@ -546,7 +629,15 @@ void vcycle_t(cdgmg_handle* h, const double* r64, double* z64) {
       if (nu1 == 0) (void)hipMemsetAsync(xs[l], 0, d.n * NP * sizeof(T), h->stream);
     }
     smooth_sweeps<T, NP>(h, l, nu1 - 1 > 0 ? nu1 - 1 : 0, &xs[l], &xbs[l]);
-    if (rs)
+    if (kmode(h, l) == KM_HS2)
+      launch_hs_restrict<T, NP, 2>(h, d, Ops<T>::A(d), (const T*)d.b, (const T*)xs[l], Ops<T>::L(d), (T*)d.t);
+    else if (kmode(h, l) == KM_HS4)
+      launch_hs_restrict<T, NP, 4>(h, d, Ops<T>::A(d), (const T*)d.b, (const T*)xs[l], Ops<T>::L(d), (T*)d.t);
+    else if (kmode(h, l) == KM_WPR)
+      launch(h, CDGMG_K_RESTRICT, k_residual_restrict_wpr<T, NP>, dim3(grid_for(d.n * WAVE)), dim3(TPB), d.n,
+             (const int32_t*)d.wcols, (const int64_t*)d.woff, Ops<T>::R(d), (const T*)d.b, (const T*)xs[l],
+             Ops<T>::L(d), (T*)d.t);
+    else if (rs)
       launch(h, CDGMG_K_RESTRICT, k_residual_restrict_ss<T, NP>, dim3((unsigned)d.ns), ssb, d.n,
              (const int32_t*)d.cols, (const int64_t*)d.sblk, Ops<T>::A(d), (const T*)d.b, (const T*)xs[l],
              Ops<T>::L(d), (T*)d.t);
@@ -598,10 +689,17 @@ int read_scalar(cdgmg_handle* h, int slot, double* out) {
 // recursive residual is replaced by it); returns ||r||^2
 int true_residual(cdgmg_handle* h, double* rr) {
   DLevel& d = h->lv[0];
-  const unsigned g = grid_for(d.n);
-  NP_DISPATCH(h->np, launch(h, CDGMG_K_VECTOR, k_residual2<NP>, dim3(g), dim3(TPB), d.n, (const int32_t*)d.cols,
-                            (const int64_t*)d.sblk, (const double*)d.A64, (const double*)h->b,
-                            (const double*)h->x, (const double*)h->xl, h->r, h->part));
+  const int km0 = kmode(h, 0);
+  const unsigned g = (km0 == KM_HS2 || km0 == KM_HS4) ? (unsigned)d.ns : grid_for(d.n);
+  if (km0 == KM_HS4) {
+    NP_DISPATCH(h->np, launch_residual2_hs<NP, 4>(h, d));
+  } else if (km0 == KM_HS2) {
+    NP_DISPATCH(h->np, launch_residual2_hs<NP, 2>(h, d));
+  } else {
+    NP_DISPATCH(h->np, launch(h, CDGMG_K_VECTOR, k_residual2<NP>, dim3(g), dim3(TPB), d.n, (const int32_t*)d.cols,
+                              (const int64_t*)d.sblk, (const double*)d.A64, (const double*)h->b,
+                              (const double*)h->x, (const double*)h->xl, h->r, h->part));
+  }
   launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)g, 1, h->scal, SC_TMP);
   return read_scalar(h, SC_TMP, rr);
 }
@@ -672,8 +770,13 @@ int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
         launch(h, CDGMG_K_VECTOR, k_update_p, dim3(grid_for(m)), dim3(TPB), m, (const double*)h->z, h->p,
                (const double*)h->scal, 1.0, it == 0 ? 1 : 0);
       }
-      const unsigned g = grid_for(d0.n);
-      if (accurate) {
+      const int km0 = kmode(h, 0);
+      const unsigned g = (km0 == KM_HS2 || km0 == KM_HS4) ? (unsigned)d0.ns : grid_for(d0.n);
+      if (km0 == KM_HS4) {
+        NP_DISPATCH(np, launch_spmv_hs<NP, 4>(h, d0, accurate));
+      } else if (km0 == KM_HS2) {
+        NP_DISPATCH(np, launch_spmv_hs<NP, 2>(h, d0, accurate));
+      } else if (accurate) {
         NP_DISPATCH(np, launch(h, CDGMG_K_SPMV, k_spmv2_dots<NP>, dim3(g), dim3(TPB), d0.n,
                                (const int32_t*)d0.cols, (const int64_t*)d0.sblk, (const double*)d0.A64,
                                (const double*)h->p, (const double*)h->r, h->q, h->part));
