@@ -84,9 +84,11 @@ def cpu_baseline(cfg, n_sample):
 
 
 def smoother_bytes(nnzb0, n0, npb, s):
-    """Algorithmic HBM bytes of one level-0 block-Jacobi sweep: the stored
-    blocks of A_0 and their column indices, D^{-1}, and b, x read, x written."""
-    return nnzb0 * npb * npb * s + 4 * nnzb0 + n0 * npb * npb * s + 3 * n0 * npb * s
+    """Algorithmic HBM bytes of one level-0 damped block-Jacobi sweep on the
+    D^{-1}-prescaled operator: its off-diagonal blocks and their column
+    indices, and D^{-1} b, x read, x written."""
+    off = nnzb0 - n0
+    return off * npb * npb * s + 4 * off + 3 * n0 * npb * s
 
 
 def spmv_bytes(nnzb0, n0, npb):
@@ -264,7 +266,7 @@ def main():
         "kernel_ms_per_solve": {k: kms[k] / args.steps for k in cm.K_NAMES if kcnt[k]},
         "kernel_launches_per_solve": {k: kcnt[k] / args.steps for k in cm.K_NAMES if kcnt[k]},
         "roofline": {
-            "kernel": "level-0 damped block-Jacobi sweep (k_smooth_hs<float,%d,H>, FP32)" % npb,
+            "kernel": "level-0 damped block-Jacobi sweep (k_sweep0<float,%d,H>, FP32)" % npb,
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "algorithmic_bytes_per_launch": sb, "avg_launch_ms": avg_smooth_ms,

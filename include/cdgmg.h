@@ -96,11 +96,10 @@ typedef struct cdgmg_options {
   double tol;          /* relative true residual ||b - A x|| / ||b||; default 1e-10 */
   int max_iter;        /* default 500 */
   int profile;         /* nonzero: time kernel classes with HIP events */
-  int kernel_variant;  /* V-cycle sweep/restriction kernels: 0 auto (level 0 thread per row, or
-                          slot-split for n_p >= 20; coarse levels wave per row), 1 thread per row
-                          everywhere, 2 slot-split everywhere (4 wavefronts share a 64-row slice's
-                          slots), 3 thread per row on level 0 + wave per row on coarse levels,
-                          4 slot-split on level 0 + wave per row on coarse levels */
+  int kernel_variant;  /* wavefronts per 64-row slice of the level-0 V-cycle kernels and of the
+                          outer FP64 product: 0 auto (4 for n_p >= 20 divisible by 4, 2 for even
+                          n_p >= 6, else 1), or 1, 2, 4, 5 where it divides n_p (else setup
+                          fails with CDGMG_ERR_ARG); coarse levels always run wave per row */
 } cdgmg_options;
 
 typedef struct cdgmg_solve_info {

@@ -256,10 +256,10 @@ __global__ void k_cast(int64_t n, const S* __restrict__ src, D* __restrict__ dst
 }
 
 // ============================================================ solve kernels
-// y = A x
-template <typename T, int NP>
+// y = A x, products in T with the stored operator (TA) rounded to T
+template <typename TA, typename T, int NP>
 __global__ __launch_bounds__(TPB) void k_spmv(int64_t n, const int32_t* __restrict__ cols,
-                                              const int64_t* __restrict__ sblk, const T* __restrict__ A,
+                                              const int64_t* __restrict__ sblk, const TA* __restrict__ A,
                                               const T* __restrict__ x, T* __restrict__ y) {
   constexpr int NP2 = NP * NP;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -275,133 +275,14 @@ __global__ __launch_bounds__(TPB) void k_spmv(int64_t n, const int32_t* __restri
     T xv[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) xv[j] = x[(int64_t)c * NP + j];
-    const T* Ab = A + (B + (int64_t)WAVE * w) * NP2 + lane;
+    const TA* Ab = A + (B + (int64_t)WAVE * w) * NP2 + lane;
 #pragma unroll
     for (int i = 0; i < NP; ++i)
 #pragma unroll
-      for (int j = 0; j < NP; ++j) acc[i] += Ab[(i * NP + j) * WAVE] * xv[j];
+      for (int j = 0; j < NP; ++j) acc[i] += (T)Ab[(i * NP + j) * WAVE] * xv[j];
   }
 #pragma unroll
   for (int i = 0; i < NP; ++i) y[r * NP + i] = acc[i];
-}
-
-// residual res = b - A x (registers)
-template <typename T, int NP>
-__device__ __forceinline__ void row_residual(int64_t r, const int32_t* __restrict__ cols,
-                                             const int64_t* __restrict__ sblk, const T* __restrict__ A,
-                                             const T* __restrict__ b, const T* __restrict__ x, T* res) {
-  constexpr int NP2 = NP * NP;
-  const int lane = (int)(r % WAVE);
-  const int64_t B = sblk[r / WAVE];
-  const int W = (int)((sblk[r / WAVE + 1] - B) / WAVE);
-#pragma unroll
-  for (int i = 0; i < NP; ++i) res[i] = b[r * NP + i];
-  for (int w = 0; w < W; ++w) {
-    const int32_t c = cols[B + (int64_t)WAVE * w + lane];
-    T xv[NP];
-#pragma unroll
-    for (int j = 0; j < NP; ++j) xv[j] = x[(int64_t)c * NP + j];
-    const T* Ab = A + (B + (int64_t)WAVE * w) * NP2 + lane;
-#pragma unroll
-    for (int i = 0; i < NP; ++i)
-#pragma unroll
-      for (int j = 0; j < NP; ++j) res[i] -= Ab[(i * NP + j) * WAVE] * xv[j];
-  }
-}
-
-// damped block-Jacobi sweep: xout = xin + omega D^{-1} (b - A xin)
-template <typename T, int NP>
-__global__ __launch_bounds__(TPB) void k_smooth(int64_t n, const int32_t* __restrict__ cols,
-                                                const int64_t* __restrict__ sblk, const T* __restrict__ A,
-                                                const T* __restrict__ Dinv, const T* __restrict__ b,
-                                                const T* __restrict__ xin, T omega, T* __restrict__ xout) {
-  constexpr int NP2 = NP * NP;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  T res[NP];
-  row_residual<T, NP>(r, cols, sblk, A, b, xin, res);
-  const T* D = Dinv + (r / WAVE) * WAVE * NP2 + (r % WAVE);
-#pragma unroll
-  for (int i = 0; i < NP; ++i) {
-    T s = 0;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) s += D[(i * NP + j) * WAVE] * res[j];
-    xout[r * NP + i] = xin[r * NP + i] + omega * s;
-  }
-}
-
-// first sweep from x = 0: b = (T) src, x = omega D^{-1} b
-template <typename T, typename S, int NP>
-__global__ __launch_bounds__(TPB) void k_smooth_first(int64_t n, const S* __restrict__ src, T* __restrict__ b,
-                                                      const T* __restrict__ Dinv, T omega, T* __restrict__ x) {
-  constexpr int NP2 = NP * NP;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  T bv[NP];
-#pragma unroll
-  for (int j = 0; j < NP; ++j) {
-    bv[j] = (T)src[r * NP + j];
-    if ((const void*)src != (const void*)b) b[r * NP + j] = bv[j];
-  }
-  const T* D = Dinv + (r / WAVE) * WAVE * NP2 + (r % WAVE);
-#pragma unroll
-  for (int i = 0; i < NP; ++i) {
-    T s = 0;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) s += D[(i * NP + j) * WAVE] * bv[j];
-    x[r * NP + i] = omega * s;
-  }
-}
-
-// coarse level entry: b_I = sum over children e of t_e (restricted residuals);
-// then (if Dinv) the first sweep x = omega D^{-1} b
-template <typename T, int NP>
-__global__ __launch_bounds__(TPB) void k_gather_smooth_first(int64_t n, const int32_t* __restrict__ child_start,
-                                                             const T* __restrict__ t, T* __restrict__ b,
-                                                             const T* __restrict__ Dinv, T omega,
-                                                             T* __restrict__ x) {
-  constexpr int NP2 = NP * NP;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  T bv[NP];
-#pragma unroll
-  for (int j = 0; j < NP; ++j) bv[j] = 0;
-  for (int32_t e = child_start[r]; e < child_start[r + 1]; ++e)
-#pragma unroll
-    for (int j = 0; j < NP; ++j) bv[j] += t[(int64_t)e * NP + j];
-#pragma unroll
-  for (int j = 0; j < NP; ++j) b[r * NP + j] = bv[j];
-  if (Dinv == nullptr) return;
-  const T* D = Dinv + (r / WAVE) * WAVE * NP2 + (r % WAVE);
-#pragma unroll
-  for (int i = 0; i < NP; ++i) {
-    T s = 0;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) s += D[(i * NP + j) * WAVE] * bv[j];
-    x[r * NP + i] = omega * s;
-  }
-}
-
-// restriction of the residual: t_e = L_e^T (b - A x)_e
-template <typename T, int NP>
-__global__ __launch_bounds__(TPB) void k_residual_restrict(int64_t n, const int32_t* __restrict__ cols,
-                                                           const int64_t* __restrict__ sblk,
-                                                           const T* __restrict__ A, const T* __restrict__ b,
-                                                           const T* __restrict__ x, const T* __restrict__ Lb,
-                                                           T* __restrict__ t) {
-  constexpr int NP2 = NP * NP;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  T res[NP];
-  row_residual<T, NP>(r, cols, sblk, A, b, x, res);
-  const T* Lr = Lb + (r / WAVE) * WAVE * NP2 + (r % WAVE);
-#pragma unroll
-  for (int j = 0; j < NP; ++j) {
-    T s = 0;
-#pragma unroll
-    for (int i = 0; i < NP; ++i) s += Lr[(i * NP + j) * WAVE] * res[i];
-    t[r * NP + j] = s;
-  }
 }
 
 // prolongation and correction: x_e += L_e x_c[parent(e)]
@@ -439,165 +320,81 @@ __global__ void k_dense_gemv(int64_t n, const T* __restrict__ Ainv, const T* __r
 }
 
 // ------------------------------------------------------------------
-// Slot-split variants for levels too small to fill the GPU with one thread
-// per row: a workgroup owns one 64-row slice and its NW wavefronts divide the
-// slice's block columns (slots w = iw, iw + NW, ...).  Each wavefront keeps the
-// full n_p-vector partial sum of its slots; the partials are reduced through
-// LDS in fixed order (deterministic) and the wavefronts then share the n_p
-// outputs of the D^{-1} or L_e^T product.  The serial chain per thread is
-// NW times shorter and every x gather is issued once.
-constexpr int NW = 4;
-
-template <typename T, int NP>
-__device__ __forceinline__ void ss_residual(int64_t s, int lane, int iw, const int32_t* __restrict__ cols,
-                                            const int64_t* __restrict__ sblk, const T* __restrict__ A,
-                                            const T* __restrict__ b, const T* __restrict__ x, bool valid,
-                                            T (*sp)[NP][WAVE], T (*sres)[WAVE]) {
-  constexpr int NP2 = NP * NP;
-  const int64_t r = s * WAVE + lane;
-  T acc[NP];
-#pragma unroll
-  for (int i = 0; i < NP; ++i) acc[i] = 0;
-  if (valid) {
-    const int64_t B = sblk[s];
-    const int W = (int)((sblk[s + 1] - B) / WAVE);
-    for (int w = iw; w < W; w += NW) {
-      const int32_t c = cols[B + (int64_t)WAVE * w + lane];
-      T xv[NP];
-#pragma unroll
-      for (int j = 0; j < NP; ++j) xv[j] = x[(int64_t)c * NP + j];
-      const T* Ab = A + (B + (int64_t)WAVE * w) * NP2 + lane;
-#pragma unroll
-      for (int i = 0; i < NP; ++i)
-#pragma unroll
-        for (int j = 0; j < NP; ++j) acc[i] += Ab[(i * NP + j) * WAVE] * xv[j];
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < NP; ++i) sp[iw][i][lane] = acc[i];
-  __syncthreads();
-  // residual component i = iw, iw + NW, ... : b_i - sum over the NW partials (fixed order)
-  for (int i = iw; i < NP; i += NW) {
-    T v = valid ? b[r * NP + i] : T(0);
-#pragma unroll
-    for (int q = 0; q < NW; ++q) v -= sp[q][i][lane];
-    sres[i][lane] = v;
-  }
-  __syncthreads();
-}
-
-template <typename T, int NP>
-__global__ __launch_bounds__(WAVE * NW) void k_smooth_ss(int64_t n, const int32_t* __restrict__ cols,
-                                                         const int64_t* __restrict__ sblk, const T* __restrict__ A,
-                                                         const T* __restrict__ Dinv, const T* __restrict__ b,
-                                                         const T* __restrict__ xin, T omega, T* __restrict__ xout) {
-  constexpr int NP2 = NP * NP;
-  __shared__ T sp[NW][NP][WAVE];
-  __shared__ T sres[NP][WAVE];
-  const int lane = threadIdx.x % WAVE, iw = threadIdx.x / WAVE;
-  const int64_t s = blockIdx.x, r = s * WAVE + lane;
-  const bool valid = r < n;
-  ss_residual<T, NP>(s, lane, iw, cols, sblk, A, b, xin, valid, sp, sres);
-  if (!valid) return;
-  const T* D = Dinv + s * WAVE * NP2 + lane;
-  for (int i = iw; i < NP; i += NW) {
-    T acc = 0;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) acc += D[(i * NP + j) * WAVE] * sres[j][lane];
-    xout[r * NP + i] = xin[r * NP + i] + omega * acc;
-  }
-}
-
-template <typename T, int NP>
-__global__ __launch_bounds__(WAVE * NW) void k_residual_restrict_ss(
-    int64_t n, const int32_t* __restrict__ cols, const int64_t* __restrict__ sblk, const T* __restrict__ A,
-    const T* __restrict__ b, const T* __restrict__ x, const T* __restrict__ Lb, T* __restrict__ t_out) {
-  constexpr int NP2 = NP * NP;
-  __shared__ T sp[NW][NP][WAVE];
-  __shared__ T sres[NP][WAVE];
-  const int lane = threadIdx.x % WAVE, iw = threadIdx.x / WAVE;
-  const int64_t s = blockIdx.x, r = s * WAVE + lane;
-  const bool valid = r < n;
-  ss_residual<T, NP>(s, lane, iw, cols, sblk, A, b, x, valid, sp, sres);
-  if (!valid) return;
-  const T* Lr = Lb + s * WAVE * NP2 + lane;
-  for (int j = iw; j < NP; j += NW) {
-    T acc = 0;
-#pragma unroll
-    for (int i = 0; i < NP; ++i) acc += Lr[(i * NP + j) * WAVE] * sres[i][lane];
-    t_out[r * NP + j] = acc;
-  }
-}
-
-// ------------------------------------------------------------------
-// Component-split kernels for wide blocks (n_p = 20 on level 0): H wavefronts
-// per 64-row slice, wavefront h owns output components [h n_p/H, (h+1) n_p/H)
-// of the slice's rows; each keeps n_p/H accumulators and the row's gathered x
-// block, so less state per thread and more loads in flight.  The residual is
-// exchanged through LDS for the D^{-1} and L_e^T products.
+// V-cycle kernels on D^{-1}-prescaled operators.  The damped block-Jacobi
+// sweep x <- x + omega D^{-1} (b - A x) is evaluated as
+//     x <- (1 - omega) x + omega (bt - At_off x),   bt = D^{-1} b,  At = D^{-1} A,
+// where the diagonal block of At is the identity and is not stored, and the
+// restricted residual L_e^T (b - A x)_e as Lt_e^T (bt - At x)_e with
+// Lt_e = D_e L_e.  The sweeps thus read neither D^{-1} nor the diagonal block.
+//
+// Level 0 (component-split): H wavefronts per 64-row slice, wavefront h owns
+// output components [h NI, (h+1) NI), NI = n_p / H (H = 1 is one thread per
+// row).  Off-diagonal blocks use the sliced layout with W_s - 1 slots per
+// slice: block (r, w') at ((sblk[s] - 64 s + 64 w') n_p^2 + (i n_p + j) 64 + lane),
+// its column at cols[sblk[s] + 64 (w' + 1) + lane].
 template <typename T, int NP, int H>
-__device__ __forceinline__ void hs_residual(int64_t r, int lane, int h, bool valid, const int32_t* __restrict__ cols,
-                                            const int64_t* __restrict__ sblk, const T* __restrict__ A,
-                                            const T* __restrict__ b, const T* __restrict__ x, T (*sres)[WAVE]) {
+__device__ __forceinline__ void hs_scaled_residual(int64_t r, int lane, int h, const int32_t* __restrict__ cols,
+                                                   const int64_t* __restrict__ sblk, const T* __restrict__ At,
+                                                   const T* __restrict__ bt, const T* __restrict__ x, T* acc) {
   constexpr int NP2 = NP * NP, NI = NP / H;
+  const int64_t s = r / WAVE;
+  const int64_t B = sblk[s];
+  const int Wo = (int)((sblk[s + 1] - B) / WAVE) - 1;
+  const int64_t Bo = B - WAVE * s;
+#pragma unroll
+  for (int t = 0; t < NI; ++t) acc[t] = bt[r * NP + h * NI + t] - x[r * NP + h * NI + t];
+  for (int w = 0; w < Wo; ++w) {
+    const int32_t c = cols[B + (int64_t)WAVE * (w + 1) + lane];
+    T xv[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) xv[j] = x[(int64_t)c * NP + j];
+    const T* Ab = At + (Bo + (int64_t)WAVE * w) * NP2 + (int64_t)h * NI * NP * WAVE + lane;
+#pragma unroll
+    for (int t = 0; t < NI; ++t)
+#pragma unroll
+      for (int j = 0; j < NP; ++j) acc[t] -= Ab[(t * NP + j) * WAVE] * xv[j];
+  }
+}
+
+// sweep on level 0
+template <typename T, int NP, int H>
+__global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* __restrict__ cols,
+                                                     const int64_t* __restrict__ sblk, const T* __restrict__ At,
+                                                     const T* __restrict__ bt, const T* __restrict__ xin, T omega,
+                                                     T* __restrict__ xout) {
+  constexpr int NI = NP / H;
+  const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
+  const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
+  if (r >= n) return;
+  T acc[NI];
+  hs_scaled_residual<T, NP, H>(r, lane, h, cols, sblk, At, bt, xin, acc);
+#pragma unroll
+  for (int t = 0; t < NI; ++t) {
+    const int64_t k = r * NP + h * NI + t;
+    xout[k] = xin[k] + omega * acc[t];
+  }
+}
+
+// residual + restriction on level 0: t_e = Lt_e^T (bt - At x)_e
+template <typename T, int NP, int H>
+__global__ __launch_bounds__(WAVE * H) void k_restrict0(int64_t n, const int32_t* __restrict__ cols,
+                                                        const int64_t* __restrict__ sblk, const T* __restrict__ At,
+                                                        const T* __restrict__ bt, const T* __restrict__ x,
+                                                        const T* __restrict__ Lt, T* __restrict__ t_out) {
+  constexpr int NP2 = NP * NP, NI = NP / H;
+  __shared__ T sres[NP][WAVE];
+  const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
+  const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
+  const bool valid = r < n;
   if (valid) {
     T acc[NI];
-#pragma unroll
-    for (int t = 0; t < NI; ++t) acc[t] = b[r * NP + h * NI + t];
-    const int64_t B = sblk[r / WAVE];
-    const int W = (int)((sblk[r / WAVE + 1] - B) / WAVE);
-    for (int w = 0; w < W; ++w) {
-      const int32_t c = cols[B + (int64_t)WAVE * w + lane];
-      T xv[NP];
-#pragma unroll
-      for (int j = 0; j < NP; ++j) xv[j] = x[(int64_t)c * NP + j];
-      const T* Ab = A + (B + (int64_t)WAVE * w) * NP2 + (int64_t)h * NI * NP * WAVE + lane;
-#pragma unroll
-      for (int t = 0; t < NI; ++t)
-#pragma unroll
-        for (int j = 0; j < NP; ++j) acc[t] -= Ab[(t * NP + j) * WAVE] * xv[j];
-    }
+    hs_scaled_residual<T, NP, H>(r, lane, h, cols, sblk, At, bt, x, acc);
 #pragma unroll
     for (int t = 0; t < NI; ++t) sres[h * NI + t][lane] = acc[t];
   }
   __syncthreads();
-}
-
-template <typename T, int NP, int H>
-__global__ __launch_bounds__(WAVE * H) void k_smooth_hs(int64_t n, const int32_t* __restrict__ cols,
-                                                        const int64_t* __restrict__ sblk, const T* __restrict__ A,
-                                                        const T* __restrict__ Dinv, const T* __restrict__ b,
-                                                        const T* __restrict__ xin, T omega, T* __restrict__ xout) {
-  constexpr int NP2 = NP * NP, NI = NP / H;
-  __shared__ T sres[NP][WAVE];
-  const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
-  const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
-  const bool valid = r < n;
-  hs_residual<T, NP, H>(r, lane, h, valid, cols, sblk, A, b, xin, sres);
   if (!valid) return;
-  const T* D = Dinv + (int64_t)blockIdx.x * WAVE * NP2 + lane;
-#pragma unroll
-  for (int t = 0; t < NI; ++t) {
-    const int i = h * NI + t;
-    T s = 0;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) s += D[(i * NP + j) * WAVE] * sres[j][lane];
-    xout[r * NP + i] = xin[r * NP + i] + omega * s;
-  }
-}
-
-template <typename T, int NP, int H>
-__global__ __launch_bounds__(WAVE * H) void k_residual_restrict_hs(
-    int64_t n, const int32_t* __restrict__ cols, const int64_t* __restrict__ sblk, const T* __restrict__ A,
-    const T* __restrict__ b, const T* __restrict__ x, const T* __restrict__ Lb, T* __restrict__ t_out) {
-  constexpr int NP2 = NP * NP, NI = NP / H;
-  __shared__ T sres[NP][WAVE];
-  const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
-  const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
-  const bool valid = r < n;
-  hs_residual<T, NP, H>(r, lane, h, valid, cols, sblk, A, b, x, sres);
-  if (!valid) return;
-  const T* Lr = Lb + (int64_t)blockIdx.x * WAVE * NP2 + lane;
+  const T* Lr = Lt + (int64_t)blockIdx.x * WAVE * NP2 + lane;
 #pragma unroll
   for (int t = 0; t < NI; ++t) {
     const int j = h * NI + t;
@@ -608,14 +405,65 @@ __global__ __launch_bounds__(WAVE * H) void k_residual_restrict_hs(
   }
 }
 
-// ------------------------------------------------------------------
-// Wave-per-row kernels for the coarse levels.  Row r's blocks are stored as a
-// dense n_p x (len_r n_p) strip, component-major (unpadded):
-//     R[(off_r n_p + i) (len_r n_p) ... ] -> element (i, k) at base_r + i * len_r n_p + k,
-// with k = w n_p + j for slot w, column j.  One wavefront per row: lane l
-// handles k = l, l + 64, ... for every i (coalesced strip loads, a short chain
-// per lane); the n_p partial sums are reduced with xor-shuffles so every lane
-// holds the row residual.
+// level-0 entry from the FP64 outer residual: bt = D^{-1} (T) r, x = omega bt
+template <typename T, int NP, int H>
+__global__ __launch_bounds__(WAVE * H) void k_entry0(int64_t n, const double* __restrict__ src,
+                                                     const T* __restrict__ Dinv, T omega, T* __restrict__ bt,
+                                                     T* __restrict__ x) {
+  constexpr int NP2 = NP * NP, NI = NP / H;
+  const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
+  const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
+  if (r >= n) return;
+  T v[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) v[j] = (T)src[r * NP + j];
+  const T* D = Dinv + (int64_t)blockIdx.x * WAVE * NP2 + lane;
+#pragma unroll
+  for (int t = 0; t < NI; ++t) {
+    const int i = h * NI + t;
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) s += D[(i * NP + j) * WAVE] * v[j];
+    bt[r * NP + i] = s;
+    x[r * NP + i] = omega * s;
+  }
+}
+
+// coarse-level entry: b_I = sum over children of t_e; bt = D^{-1} b, x = omega bt
+// (no D^{-1}: the coarsest level, bt receives b itself)
+template <typename T, int NP>
+__global__ __launch_bounds__(TPB) void k_entry_c(int64_t n, const int32_t* __restrict__ child_start,
+                                                 const T* __restrict__ t, const T* __restrict__ Dinv, T omega,
+                                                 T* __restrict__ bt, T* __restrict__ x) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  T bv[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) bv[j] = 0;
+  for (int32_t e = child_start[r]; e < child_start[r + 1]; ++e)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) bv[j] += t[(int64_t)e * NP + j];
+  if (Dinv == nullptr) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j) bt[r * NP + j] = bv[j];
+    return;
+  }
+  const T* D = Dinv + (r / WAVE) * WAVE * NP2 + (r % WAVE);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) s += D[(i * NP + j) * WAVE] * bv[j];
+    bt[r * NP + i] = s;
+    x[r * NP + i] = omega * s;
+  }
+}
+
+// Coarse levels (wave per row): row r's off-diagonal blocks are a dense
+// n_p x (len_r - 1) n_p strip, component-major, unpadded, at (woff[r] - r) n_p^2;
+// lane l takes strip columns k = l, l + 64, ... for every component; the n_p
+// partial sums are reduced with xor-shuffles.  Columns: wcols[woff[r] + 1 + w].
 template <typename T>
 __device__ __forceinline__ T wave_allsum(T v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -623,60 +471,57 @@ __device__ __forceinline__ T wave_allsum(T v) {
 }
 
 template <typename T, int NP>
-__device__ __forceinline__ void wpr_residual(int64_t r, int lane, const int32_t* __restrict__ cols,
-                                             const int64_t* __restrict__ roff, const T* __restrict__ R,
-                                             const T* __restrict__ b, const T* __restrict__ x, T* res) {
-  const int64_t o = roff[r];
-  const int len = (int)(roff[r + 1] - o);
-  const int K = len * NP;
-  const T* Rr = R + o * NP * NP;
+__device__ __forceinline__ void wpr_scaled_residual(int64_t r, int lane, const int32_t* __restrict__ wcols,
+                                                    const int64_t* __restrict__ woff, const T* __restrict__ R,
+                                                    const T* __restrict__ bt, const T* __restrict__ x, T* res) {
+  const int64_t o = woff[r];
+  const int K = (int)(woff[r + 1] - o - 1) * NP;
+  const T* Rr = R + (o - r) * NP * NP;
   T acc[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) acc[i] = 0;
   for (int k = lane; k < K; k += WAVE) {
     const int w = k / NP, j = k - w * NP;
-    const T xv = x[(int64_t)cols[o + w] * NP + j];
+    const T xv = x[(int64_t)wcols[o + 1 + w] * NP + j];
 #pragma unroll
     for (int i = 0; i < NP; ++i) acc[i] += Rr[(int64_t)i * K + k] * xv;
   }
 #pragma unroll
-  for (int i = 0; i < NP; ++i) res[i] = b[r * NP + i] - wave_allsum(acc[i]);
+  for (int i = 0; i < NP; ++i) res[i] = bt[r * NP + i] - x[r * NP + i] - wave_allsum(acc[i]);
 }
 
 template <typename T, int NP>
-__global__ __launch_bounds__(TPB) void k_smooth_wpr(int64_t n, const int32_t* __restrict__ cols,
-                                                    const int64_t* __restrict__ roff, const T* __restrict__ R,
-                                                    const T* __restrict__ Dinv, const T* __restrict__ b,
-                                                    const T* __restrict__ xin, T omega, T* __restrict__ xout) {
-  constexpr int NP2 = NP * NP;
+__global__ __launch_bounds__(TPB) void k_sweep_wpr(int64_t n, const int32_t* __restrict__ wcols,
+                                                   const int64_t* __restrict__ woff, const T* __restrict__ R,
+                                                   const T* __restrict__ bt, const T* __restrict__ xin, T omega,
+                                                   T* __restrict__ xout) {
   const int lane = threadIdx.x % WAVE;
   const int64_t r = (int64_t)blockIdx.x * (TPB / WAVE) + threadIdx.x / WAVE;
   if (r >= n) return;
   T res[NP];
-  wpr_residual<T, NP>(r, lane, cols, roff, R, b, xin, res);
+  wpr_scaled_residual<T, NP>(r, lane, wcols, woff, R, bt, xin, res);
   if (lane < NP) {
-    const T* D = Dinv + (r / WAVE) * WAVE * NP2 + (r % WAVE);
-    T s = 0;
+    T v = res[0];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) s += D[(lane * NP + j) * WAVE] * res[j];
-    xout[r * NP + lane] = xin[r * NP + lane] + omega * s;
+    for (int i = 1; i < NP; ++i)
+      if (lane == i) v = res[i];
+    xout[r * NP + lane] = xin[r * NP + lane] + omega * v;
   }
 }
 
 template <typename T, int NP>
-__global__ __launch_bounds__(TPB) void k_residual_restrict_wpr(int64_t n, const int32_t* __restrict__ cols,
-                                                               const int64_t* __restrict__ roff,
-                                                               const T* __restrict__ R, const T* __restrict__ b,
-                                                               const T* __restrict__ x, const T* __restrict__ Lb,
-                                                               T* __restrict__ t) {
+__global__ __launch_bounds__(TPB) void k_restrict_wpr(int64_t n, const int32_t* __restrict__ wcols,
+                                                      const int64_t* __restrict__ woff, const T* __restrict__ R,
+                                                      const T* __restrict__ bt, const T* __restrict__ x,
+                                                      const T* __restrict__ Lt, T* __restrict__ t) {
   constexpr int NP2 = NP * NP;
   const int lane = threadIdx.x % WAVE;
   const int64_t r = (int64_t)blockIdx.x * (TPB / WAVE) + threadIdx.x / WAVE;
   if (r >= n) return;
   T res[NP];
-  wpr_residual<T, NP>(r, lane, cols, roff, R, b, x, res);
+  wpr_scaled_residual<T, NP>(r, lane, wcols, woff, R, bt, x, res);
   if (lane < NP) {
-    const T* Lr = Lb + (r / WAVE) * WAVE * NP2 + (r % WAVE);
+    const T* Lr = Lt + (r / WAVE) * WAVE * NP2 + (r % WAVE);
     T s = 0;
 #pragma unroll
     for (int i = 0; i < NP; ++i) s += Lr[(i * NP + lane) * WAVE] * res[i];
@@ -684,22 +529,67 @@ __global__ __launch_bounds__(TPB) void k_residual_restrict_wpr(int64_t n, const 
   }
 }
 
-// sliced-ELL (FP64) -> wave-per-row strips (type T), setup
+// ----------------------------------------------------------- prescaling (setup)
+// At_off(r, w) = D_r^{-1} A(r, w), w >= 1, into the level-0 sliced layout without slot 0
 template <typename T, int NP>
-__global__ void k_to_wpr(int64_t n, const int64_t* __restrict__ sblk, const int64_t* __restrict__ roff,
-                         const double* __restrict__ A, T* __restrict__ R) {
+__global__ void k_scale_sliced(int64_t n, const int64_t* __restrict__ sblk, const double* __restrict__ A,
+                               const double* __restrict__ Dinv, T* __restrict__ At) {
   constexpr int NP2 = NP * NP;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  const int64_t B = sblk[r / WAVE];
+  const int64_t s = r / WAVE;
   const int lane = (int)(r % WAVE);
-  const int64_t o = roff[r];
-  const int len = (int)(roff[r + 1] - o);
-  const int K = len * NP;
-  T* Rr = R + o * NP2;
-  for (int w = 0; w < len; ++w)
+  const int64_t B = sblk[s], Bo = B - WAVE * s;
+  const int W = (int)((sblk[s + 1] - B) / WAVE);
+  const double* D = Dinv + s * WAVE * NP2 + lane;
+  for (int w = 1; w < W; ++w)
     for (int i = 0; i < NP; ++i)
-      for (int j = 0; j < NP; ++j) Rr[(int64_t)i * K + w * NP + j] = (T)A[blk_off(B, w, NP2, i * NP + j, lane)];
+      for (int j = 0; j < NP; ++j) {
+        double acc = 0.0;
+        for (int m = 0; m < NP; ++m) acc += D[(i * NP + m) * WAVE] * A[blk_off(B, w, NP2, m * NP + j, lane)];
+        At[(Bo + (int64_t)WAVE * (w - 1)) * NP2 + (i * NP + j) * WAVE + lane] = (T)acc;
+      }
+}
+
+// coarse strips: off-diagonal blocks of D^{-1} A, component-major, unpadded
+template <typename T, int NP>
+__global__ void k_scale_wpr(int64_t n, const int64_t* __restrict__ sblk, const int64_t* __restrict__ woff,
+                            const double* __restrict__ A, const double* __restrict__ Dinv, T* __restrict__ R) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int64_t s = r / WAVE;
+  const int lane = (int)(r % WAVE);
+  const int64_t B = sblk[s];
+  const int64_t o = woff[r];
+  const int len = (int)(woff[r + 1] - o);
+  const int K = (len - 1) * NP;
+  T* Rr = R + (o - r) * NP2;
+  const double* D = Dinv + s * WAVE * NP2 + lane;
+  for (int w = 1; w < len; ++w)
+    for (int i = 0; i < NP; ++i)
+      for (int j = 0; j < NP; ++j) {
+        double acc = 0.0;
+        for (int m = 0; m < NP; ++m) acc += D[(i * NP + m) * WAVE] * A[blk_off(B, w, NP2, m * NP + j, lane)];
+        Rr[(int64_t)i * K + (w - 1) * NP + j] = (T)acc;
+      }
+}
+
+// Lt_e = D_e L_e (D_e the diagonal block of A), per-row layout
+template <typename T, int NP>
+__global__ void k_scale_L(int64_t n, const int64_t* __restrict__ sblk, const double* __restrict__ A,
+                          const double* __restrict__ L, T* __restrict__ Lt) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int lane = (int)(r % WAVE);
+  const int64_t B = sblk[r / WAVE];
+  for (int i = 0; i < NP; ++i)
+    for (int j = 0; j < NP; ++j) {
+      double acc = 0.0;
+      for (int m = 0; m < NP; ++m) acc += A[blk_off(B, 0, NP2, i * NP + m, lane)] * L[row_off(r, NP2, m * NP + j)];
+      Lt[row_off(r, NP2, i * NP + j)] = (T)acc;
+    }
 }
 
 // ---------------------------------------------------------- outer (FP64) kernels
@@ -789,47 +679,6 @@ __global__ void k_reduce(const double* __restrict__ part, int nb, int nd, double
   }
 }
 
-// q = A p (FP64, level 0) with partial sums of (p, q) and (p, r)
-template <int NP>
-__global__ __launch_bounds__(TPB) void k_spmv_dots(int64_t n, const int32_t* __restrict__ cols,
-                                                   const int64_t* __restrict__ sblk, const double* __restrict__ A,
-                                                   const double* __restrict__ p, const double* __restrict__ rr,
-                                                   double* __restrict__ q, double* __restrict__ part) {
-  constexpr int NP2 = NP * NP;
-  __shared__ double sh[TPB / WAVE];
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double pq = 0.0, pr = 0.0;
-  if (r < n) {
-    const int lane = (int)(r % WAVE);
-    const int64_t B = sblk[r / WAVE];
-    const int W = (int)((sblk[r / WAVE + 1] - B) / WAVE);
-    double acc[NP];
-#pragma unroll
-    for (int i = 0; i < NP; ++i) acc[i] = 0.0;
-    for (int w = 0; w < W; ++w) {
-      const int32_t c = cols[B + (int64_t)WAVE * w + lane];
-      double xv[NP];
-#pragma unroll
-      for (int j = 0; j < NP; ++j) xv[j] = p[(int64_t)c * NP + j];
-      const double* Ab = A + (B + (int64_t)WAVE * w) * NP2 + lane;
-#pragma unroll
-      for (int i = 0; i < NP; ++i)
-#pragma unroll
-        for (int j = 0; j < NP; ++j) acc[i] += Ab[(i * NP + j) * WAVE] * xv[j];
-    }
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      q[r * NP + i] = acc[i];
-      const double pi = p[r * NP + i];
-      pq += pi * acc[i];
-      pr += pi * rr[r * NP + i];
-    }
-  }
-  pq = block_sum(pq, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = pq;
-  pr = block_sum(pr, sh);
-  if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = pr;
-}
 
 // ------------------------------------------------------------------
 // Error-free transformations (Knuth TwoSum; FMA TwoProduct) for the outer
@@ -857,100 +706,7 @@ __device__ __forceinline__ void dot2_acc(double a, double x, double& s, double& 
   c = (c + (t + ep));
 }
 
-// q = A p (compensated) with partial sums of (p, q) and (p, r)
-template <int NP>
-__global__ __launch_bounds__(TPB) void k_spmv2_dots(int64_t n, const int32_t* __restrict__ cols,
-                                                    const int64_t* __restrict__ sblk, const double* __restrict__ A,
-                                                    const double* __restrict__ p, const double* __restrict__ rr,
-                                                    double* __restrict__ q, double* __restrict__ part) {
-#pragma clang fp contract(off)
-  constexpr int NP2 = NP * NP;
-  __shared__ double sh[TPB / WAVE];
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double pq = 0.0, pr = 0.0;
-  if (r < n) {
-    const int lane = (int)(r % WAVE);
-    const int64_t B = sblk[r / WAVE];
-    const int W = (int)((sblk[r / WAVE + 1] - B) / WAVE);
-    double s[NP], c[NP];
-#pragma unroll
-    for (int i = 0; i < NP; ++i) s[i] = c[i] = 0.0;
-    for (int w = 0; w < W; ++w) {
-      const int32_t col = cols[B + (int64_t)WAVE * w + lane];
-      double xv[NP];
-#pragma unroll
-      for (int j = 0; j < NP; ++j) xv[j] = p[(int64_t)col * NP + j];
-      const double* Ab = A + (B + (int64_t)WAVE * w) * NP2 + lane;
-#pragma unroll
-      for (int i = 0; i < NP; ++i)
-#pragma unroll
-        for (int j = 0; j < NP; ++j) dot2_acc(Ab[(i * NP + j) * WAVE], xv[j], s[i], c[i]);
-    }
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      const double qi = (s[i] + c[i]);
-      q[r * NP + i] = qi;
-      const double pi = p[r * NP + i];
-      pq += pi * qi;
-      pr += pi * rr[r * NP + i];
-    }
-  }
-  pq = block_sum(pq, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = pq;
-  pr = block_sum(pr, sh);
-  if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = pr;
-}
 
-// true residual rt = b - A (xh + xl), compensated; partial ||rt||^2
-template <int NP>
-__global__ __launch_bounds__(TPB) void k_residual2(int64_t n, const int32_t* __restrict__ cols,
-                                                   const int64_t* __restrict__ sblk, const double* __restrict__ A,
-                                                   const double* __restrict__ b, const double* __restrict__ xh,
-                                                   const double* __restrict__ xl, double* __restrict__ rt,
-                                                   double* __restrict__ part) {
-#pragma clang fp contract(off)
-  constexpr int NP2 = NP * NP;
-  __shared__ double sh[TPB / WAVE];
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double rr = 0.0;
-  if (r < n) {
-    const int lane = (int)(r % WAVE);
-    const int64_t B = sblk[r / WAVE];
-    const int W = (int)((sblk[r / WAVE + 1] - B) / WAVE);
-    double s[NP], c[NP];
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      s[i] = b[r * NP + i];
-      c[i] = 0.0;
-    }
-    for (int w = 0; w < W; ++w) {
-      const int32_t col = cols[B + (int64_t)WAVE * w + lane];
-      double hv[NP], lv[NP];
-#pragma unroll
-      for (int j = 0; j < NP; ++j) {
-        hv[j] = xh[(int64_t)col * NP + j];
-        lv[j] = xl[(int64_t)col * NP + j];
-      }
-      const double* Ab = A + (B + (int64_t)WAVE * w) * NP2 + lane;
-#pragma unroll
-      for (int i = 0; i < NP; ++i)
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-          const double a = Ab[(i * NP + j) * WAVE];
-          dot2_acc(-a, hv[j], s[i], c[i]);
-          c[i] = __builtin_fma(-a, lv[j], c[i]);
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      const double v = (s[i] + c[i]);
-      rt[r * NP + i] = v;
-      rr += v * v;
-    }
-  }
-  rr = block_sum(rr, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = rr;
-}
 
 // x_hi + x_lo += alpha p (double-double); r -= alpha q; partial ||r||^2
 __global__ __launch_bounds__(TPB) void k_update_xr2(int64_t m, const double* __restrict__ p,
@@ -989,7 +745,7 @@ __global__ __launch_bounds__(WAVE * H) void k_spmv_dots_hs(int64_t n, const int3
                                                            double* __restrict__ part) {
 #pragma clang fp contract(off)
   constexpr int NP2 = NP * NP, NI = NP / H;
-  __shared__ double sh[TPB / WAVE];
+  __shared__ double sh[H];
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
   const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
   double pq = 0.0, pr = 0.0;
@@ -1041,7 +797,7 @@ __global__ __launch_bounds__(WAVE * H) void k_residual2_hs(int64_t n, const int3
                                                            double* __restrict__ part) {
 #pragma clang fp contract(off)
   constexpr int NP2 = NP * NP, NI = NP / H;
-  __shared__ double sh[TPB / WAVE];
+  __shared__ double sh[H];
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
   const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
   double rr = 0.0;

@@ -42,6 +42,16 @@ using namespace cdg;
     default: break;                          \
   }
 
+// component split of the level-0 kernels (wavefronts per 64-row slice)
+#define H_DISPATCH(hv, ...)                                \
+  switch (hv) {                                            \
+    case 1: { constexpr int H = 1; __VA_ARGS__; } break;   \
+    case 2: { constexpr int H = 2; __VA_ARGS__; } break;   \
+    case 4: { constexpr int H = 4; __VA_ARGS__; } break;   \
+    case 5: { constexpr int H = 5; __VA_ARGS__; } break;   \
+    default: break;                                        \
+  }
+
 namespace {
 
 struct DLevel {
@@ -49,12 +59,14 @@ struct DLevel {
   int32_t* cols = nullptr;
   int64_t* sblk = nullptr;
   int32_t* perm = nullptr;  // internal -> hierarchy id
-  double* A64 = nullptr;
-  float* A32 = nullptr;
-  double* D64 = nullptr;
-  float* D32 = nullptr;
-  double* L64 = nullptr;
-  float* L32 = nullptr;
+  double* A64 = nullptr;  // A_l, FP64, sliced (Galerkin products, outer SpMV, export)
+  double* D64 = nullptr;  // D_l^{-1}, FP64, per-row layout
+  double* L64 = nullptr;  // L_e, FP64, per-row layout
+  // V-cycle operators in the multigrid precision T (FP64 mode: Dm = D64, Lm = L64)
+  void* At = nullptr;  // level 0: off-diagonal blocks of D^{-1} A, sliced without slot 0
+  void* Dm = nullptr;  // D^{-1}
+  void* Lt = nullptr;  // D L_e (D the diagonal block of A)
+  void* Lm = nullptr;  // L_e
   int32_t* parent = nullptr;
   int32_t* child_start = nullptr;
   int32_t* blk_row = nullptr;
@@ -70,11 +82,11 @@ struct DLevel {
   TPOut *xo = nullptr, *yo = nullptr, *mo = nullptr, *so = nullptr;
   int64_t *xpp = nullptr, *ypp = nullptr, *mpp = nullptr, *spp = nullptr;
   int64_t nxo = 0, nyo = 0, nmo = 0, nso = 0;
-  // wave-per-row strips of A_l (coarse levels): compact columns, row offsets
+  // coarse levels: off-diagonal strips of D^{-1} A (wave per row), compact
+  // columns (slot 0 = the row itself) and row offsets
   int32_t* wcols = nullptr;
   int64_t* woff = nullptr;
-  float* R32 = nullptr;
-  double* R64 = nullptr;
+  void* R = nullptr;
 };
 
 struct ProfEv {
@@ -89,6 +101,7 @@ struct cdgmg_handle {
   cdgmg_options o;
   hipStream_t stream = nullptr;
   int np = 0, d = 0, W0 = 0, L = 0;
+  int H0 = 1;  // wavefronts per slice of the level-0 kernels
   int64_t N0 = 0;
   std::vector<DLevel> lv;
   std::vector<void*> allocs;
@@ -311,17 +324,34 @@ int upload_problem(cdgmg_handle* h) {
     RETURN_IF(upload(h, &D.perm, H.perm));
     RETURN_IF(dalloc(h, &D.A64, (size_t)D.slots * np2));
     HIPCHK(hipMemsetAsync(D.A64, 0, (size_t)D.slots * np2 * sizeof(double), h->stream));
-    if (fp32) RETURN_IF(dalloc(h, &D.A32, (size_t)D.slots * np2));
+    const size_t rowblk = (size_t)D.ns * SLICE * np2;
     if (l < P.L) {
-      RETURN_IF(dalloc(h, &D.D64, (size_t)D.ns * SLICE * np2));
-      if (fp32) RETURN_IF(dalloc(h, &D.D32, (size_t)D.ns * SLICE * np2));
+      RETURN_IF(dalloc(h, &D.D64, rowblk));
       std::vector<double> Lr = to_rows(H.Lblk, H.n, np2);
       RETURN_IF(upload(h, &D.L64, Lr));
       if (fp32) {
-        std::vector<float> Lf(Lr.begin(), Lr.end());
-        RETURN_IF(upload(h, &D.L32, Lf));
+        float* tmp;
+        RETURN_IF(upload(h, &tmp, std::vector<float>(Lr.begin(), Lr.end())));
+        D.Lm = tmp;
+        RETURN_IF(dalloc(h, &tmp, rowblk));
+        D.Dm = tmp;
+        RETURN_IF(dalloc(h, &tmp, rowblk));
+        D.Lt = tmp;
+      } else {
+        D.Lm = D.L64;
+        D.Dm = D.D64;
+        double* tmp;
+        RETURN_IF(dalloc(h, &tmp, rowblk));
+        D.Lt = tmp;
       }
       RETURN_IF(upload(h, &D.parent, H.parent));
+    }
+    if (l == 0 && P.L > 0) {
+      const size_t na = (size_t)(D.slots - SLICE * D.ns) * np2;
+      void* tmp;
+      RETURN_IF(dalloc(h, (char**)&tmp, na * (fp32 ? sizeof(float) : sizeof(double))));
+      HIPCHK(hipMemsetAsync(tmp, 0, na * (fp32 ? sizeof(float) : sizeof(double)), h->stream));
+      D.At = tmp;
     }
     if (l >= 1 && l < P.L) {
       std::vector<int32_t> wc(H.nnzb);
@@ -330,10 +360,10 @@ int upload_problem(cdgmg_handle* h) {
           wc[H.row_blk[r] + w] = H.cols[H.slice_blk[r / SLICE] + (int64_t)SLICE * w + r % SLICE];
       RETURN_IF(upload(h, &D.wcols, wc));
       RETURN_IF(upload(h, &D.woff, H.row_blk));
-      if (fp32)
-        RETURN_IF(dalloc(h, &D.R32, (size_t)H.nnzb * np2));
-      else
-        RETURN_IF(dalloc(h, &D.R64, (size_t)H.nnzb * np2));
+      const size_t nr = (size_t)(H.nnzb - H.n) * np2;
+      void* tmp;
+      RETURN_IF(dalloc(h, (char**)&tmp, nr * (fp32 ? sizeof(float) : sizeof(double))));
+      D.R = tmp;
     }
     if (l >= 1) {
       std::vector<int32_t> cs(H.child_start.begin(), H.child_start.end());
@@ -401,7 +431,28 @@ int upload_problem(cdgmg_handle* h) {
   return CDGMG_OK;
 }
 
-// kappa -> A_0 -> (D^{-1}, Galerkin) per level -> coarsest inverse -> FP32 copies
+template <typename T, int NP>
+void prescale(cdgmg_handle* h) {
+  constexpr int NP2 = NP * NP;
+  for (int l = 0; l < h->L; ++l) {
+    DLevel& D = h->lv[l];
+    if (l == 0)
+      launch(h, -1, k_scale_sliced<T, NP>, dim3(grid_for(D.n)), dim3(TPB), D.n, (const int64_t*)D.sblk,
+             (const double*)D.A64, (const double*)D.D64, (T*)D.At);
+    else
+      launch(h, -1, k_scale_wpr<T, NP>, dim3(grid_for(D.n)), dim3(TPB), D.n, (const int64_t*)D.sblk,
+             (const int64_t*)D.woff, (const double*)D.A64, (const double*)D.D64, (T*)D.R);
+    launch(h, -1, k_scale_L<T, NP>, dim3(grid_for(D.n)), dim3(TPB), D.n, (const int64_t*)D.sblk,
+           (const double*)D.A64, (const double*)D.L64, (T*)D.Lt);
+    if ((void*)D.Dm != (void*)D.D64) {
+      const int64_t nb = D.ns * SLICE * NP2;
+      launch(h, -1, k_cast<double, T>, dim3(grid_for(nb)), dim3(TPB), nb, (const double*)D.D64, (T*)D.Dm);
+    }
+  }
+}
+
+// kappa -> A_0 -> (D^{-1}, Galerkin) per level -> prescaled V-cycle operators
+// -> coarsest inverse
 int build_operators(cdgmg_handle* h, const double* kappa_dev) {
   const int np = h->np, np2 = np * np;
   DLevel& l0 = h->lv[0];
@@ -446,15 +497,12 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev) {
   }
   RETURN_IF(check_err(h, CDGMG_ERR_SINGULAR, flux ? "setup: a diagonal or mass block is singular"
                                                   : "setup: a diagonal block is not positive definite"));
-  // wave-per-row strips of the coarse operators used by the V-cycle
-  for (int l = 1; l < h->L; ++l) {
-    DLevel& D = h->lv[l];
-    if (D.R32)
-      NP_DISPATCH(np, launch(h, -1, k_to_wpr<float, NP>, dim3(grid_for(D.n)), dim3(TPB), D.n,
-                             (const int64_t*)D.sblk, (const int64_t*)D.woff, (const double*)D.A64, D.R32));
-    if (D.R64)
-      NP_DISPATCH(np, launch(h, -1, k_to_wpr<double, NP>, dim3(grid_for(D.n)), dim3(TPB), D.n,
-                             (const int64_t*)D.sblk, (const int64_t*)D.woff, (const double*)D.A64, D.R64));
+  // prescaled V-cycle operators D^{-1} A (off-diagonal), D L_e, and D^{-1} in the
+  // multigrid precision
+  if (h->o.mg_precision == CDGMG_MG_FP32) {
+    NP_DISPATCH(np, prescale<float, NP>(h));
+  } else {
+    NP_DISPATCH(np, prescale<double, NP>(h));
   }
   // coarsest: dense scatter + Gauss-Jordan inverse (ping-pong)
   DLevel& cl = h->lv[h->L];
@@ -472,130 +520,65 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev) {
     HIPCHK(hipMemcpyAsync(h->Ainv64, in, (size_t)nd * nd * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
   RETURN_IF(check_err(h, CDGMG_ERR_SINGULAR, flux ? "setup: the coarsest operator is singular"
                                                   : "setup: the coarsest operator is not positive definite"));
-  if (h->o.mg_precision == CDGMG_MG_FP32) {
-    for (int l = 0; l <= h->L; ++l) {
-      DLevel& D = h->lv[l];
-      const int64_t na = D.slots * np2;
-      launch(h, -1, k_cast<double, float>, dim3(grid_for(na)), dim3(TPB), na, (const double*)D.A64, D.A32);
-      if (l < h->L) {
-        const int64_t nb = D.ns * SLICE * np2;
-        launch(h, -1, k_cast<double, float>, dim3(grid_for(nb)), dim3(TPB), nb, (const double*)D.D64, D.D32);
-      }
-    }
+  if (h->o.mg_precision == CDGMG_MG_FP32)
     launch(h, -1, k_cast<double, float>, dim3(grid_for(nd * nd)), dim3(TPB), nd * nd, (const double*)h->Ainv64,
            h->Ainv32);
-  }
   HIPCHK(hipGetLastError());
   return CDGMG_OK;
 }
 
 // ---------------------------------------------------------------- V-cycle
 template <typename T>
-struct Ops;
+const T* ainv(const cdgmg_handle* h);
 template <>
-struct Ops<float> {
-  static const float* A(const DLevel& d) { return d.A32; }
-  static const float* D(const DLevel& d) { return d.D32; }
-  static const float* L(const DLevel& d) { return d.L32; }
-  static const float* Ainv(const cdgmg_handle* h) { return h->Ainv32; }
-  static const float* R(const DLevel& d) { return d.R32; }
-};
+const float* ainv<float>(const cdgmg_handle* h) {
+  return h->Ainv32;
+}
 template <>
-struct Ops<double> {
-  static const double* A(const DLevel& d) { return d.A64; }
-  static const double* D(const DLevel& d) { return d.D64; }
-  static const double* L(const DLevel& d) { return d.L64; }
-  static const double* Ainv(const cdgmg_handle* h) { return h->Ainv64; }
-  static const double* R(const DLevel& d) { return d.R64; }
-};
-
-// V-cycle kernel family per level: thread per row, slot-split (NW wavefronts
-// share a slice's slots) or wave per row (coarse strips)
-enum { KM_ROW = 0, KM_SS = 1, KM_WPR = 2, KM_HS2 = 3, KM_HS4 = 4 };
-int kmode(const cdgmg_handle* h, int l) {
-  const int v = h->o.kernel_variant;
-  if (v == 1) return KM_ROW;
-  if (v == 2) return KM_SS;
-  if (l >= 1) return KM_WPR;
-  if (v == 3) return KM_ROW;
-  if (v == 4) return KM_SS;
-  if (v == 5) return h->np % 2 == 0 ? KM_HS2 : KM_ROW;
-  if (v == 6) return h->np % 4 == 0 ? KM_HS4 : (h->np % 2 == 0 ? KM_HS2 : KM_ROW);
-  if (h->np % 4 == 0 && h->np >= 20) return KM_HS4;  // auto
-  if (h->np % 2 == 0 && h->np >= 6) return KM_HS2;
-  return KM_ROW;
+const double* ainv<double>(const cdgmg_handle* h) {
+  return h->Ainv64;
 }
 
-// launch helpers for the component-split family (H must divide n_p)
-template <typename T, int NP, int H>
-void launch_hs_smooth(cdgmg_handle* h, int cls, DLevel& d, const T* A, const T* Dv, const T* b, const T* x, T omega,
-                      T* xo) {
-  if constexpr (NP % H == 0)
-    launch(h, cls, k_smooth_hs<T, NP, H>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n, (const int32_t*)d.cols,
-           (const int64_t*)d.sblk, A, Dv, b, x, omega, xo);
+// wavefronts per 64-row slice of the level-0 kernels: 0 picks by n_p (the
+// n_p = 10, 20 blocks need the split to keep enough loads in flight)
+int pick_h0(int np, int variant) {
+  if (variant == 0) return (np % 4 == 0 && np >= 20) ? 4 : ((np % 2 == 0 && np >= 6) ? 2 : 1);
+  if ((variant == 1 || variant == 2 || variant == 4 || variant == 5) && np % variant == 0) return variant;
+  return 0;
 }
-template <int NP, int H>
-void launch_spmv_hs(cdgmg_handle* h, DLevel& d, bool accurate) {
-  if constexpr (NP % H == 0) {
-    if (accurate)
-      launch(h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, true>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
-             (const int32_t*)d.cols, (const int64_t*)d.sblk, (const double*)d.A64, (const double*)h->p,
-             (const double*)h->r, h->q, h->part);
-    else
-      launch(h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, false>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
-             (const int32_t*)d.cols, (const int64_t*)d.sblk, (const double*)d.A64, (const double*)h->p,
-             (const double*)h->r, h->q, h->part);
-  }
-}
-template <int NP, int H>
-void launch_residual2_hs(cdgmg_handle* h, DLevel& d) {
-  if constexpr (NP % H == 0)
-    launch(h, CDGMG_K_VECTOR, k_residual2_hs<NP, H>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
-           (const int32_t*)d.cols, (const int64_t*)d.sblk, (const double*)d.A64, (const double*)h->b,
-           (const double*)h->x, (const double*)h->xl, h->r, h->part);
-}
-template <typename T, int NP, int H>
-void launch_hs_restrict(cdgmg_handle* h, DLevel& d, const T* A, const T* b, const T* x, const T* L, T* t) {
-  if constexpr (NP % H == 0)
-    launch(h, CDGMG_K_RESTRICT, k_residual_restrict_hs<T, NP, H>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
-           (const int32_t*)d.cols, (const int64_t*)d.sblk, A, b, x, L, t);
-}
-bool use_rs(const cdgmg_handle* h, int l) { return kmode(h, l) == KM_SS; }
-
-// thread-per-row kernels: one-wavefront workgroups on small levels spread the
-// few wavefronts over the compute units
-inline int row_tpb(const cdgmg_handle* h, int l) { return h->lv[l].n < 100000 ? WAVE : TPB; }
 
 template <typename T, int NP>
 void smooth_sweeps(cdgmg_handle* h, int l, int count, T** x, T** xb) {
   DLevel& d = h->lv[l];
   const T omega = (T)h->o.omega;
   const int cls = l == 0 ? CDGMG_K_SMOOTH0 : CDGMG_K_SMOOTH;
-  const int km = kmode(h, l);
   for (int s = 0; s < count; ++s) {
-    if (km == KM_HS2)
-      launch_hs_smooth<T, NP, 2>(h, cls, d, Ops<T>::A(d), Ops<T>::D(d), (const T*)d.b, (const T*)*x, omega, *xb);
-    else if (km == KM_HS4)
-      launch_hs_smooth<T, NP, 4>(h, cls, d, Ops<T>::A(d), Ops<T>::D(d), (const T*)d.b, (const T*)*x, omega, *xb);
-    else if (km == KM_WPR)
-      launch(h, cls, k_smooth_wpr<T, NP>, dim3(grid_for(d.n * WAVE)), dim3(TPB), d.n, (const int32_t*)d.wcols,
-             (const int64_t*)d.woff, Ops<T>::R(d), Ops<T>::D(d), (const T*)d.b, (const T*)*x, omega, *xb);
-    else if (km == KM_SS)
-      launch(h, cls, k_smooth_ss<T, NP>, dim3((unsigned)d.ns), dim3(WAVE * NW), d.n, (const int32_t*)d.cols,
-             (const int64_t*)d.sblk, Ops<T>::A(d), Ops<T>::D(d), (const T*)d.b, (const T*)*x, omega, *xb);
-    else
-      launch(h, cls, k_smooth<T, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n, (const int32_t*)d.cols,
-             (const int64_t*)d.sblk, Ops<T>::A(d), Ops<T>::D(d), (const T*)d.b, (const T*)*x, omega, *xb);
+    if (l == 0) {
+      H_DISPATCH(h->H0, if constexpr (NP % H == 0) launch(h, cls, k_sweep0<T, NP, H>, dim3((unsigned)d.ns),
+                                                          dim3(WAVE * H), d.n, (const int32_t*)d.cols,
+                                                          (const int64_t*)d.sblk, (const T*)d.At, (const T*)d.b,
+                                                          (const T*)*x, omega, *xb));
+    } else {
+      launch(h, cls, k_sweep_wpr<T, NP>, dim3(grid_for(d.n * WAVE)), dim3(TPB), d.n, (const int32_t*)d.wcols,
+             (const int64_t*)d.woff, (const T*)d.R, (const T*)d.b, (const T*)*x, omega, *xb);
+    }
     std::swap(*x, *xb);
   }
 }
 
+// thread-per-row kernels: one-wavefront workgroups on small levels spread the
+// few wavefronts over the compute units
+inline int row_tpb(const cdgmg_handle* h, int l) { return h->lv[l].n < 100000 ? WAVE : TPB; }
+
+// One V-cycle z = B r (Sec. 4): on each level the first pre-smoothing sweep
+// starts from zero and is fused with forming D^{-1} b; residual and
+// restriction are fused; the coarsest level applies the dense inverse.
 template <typename T, int NP>
 void vcycle_t(cdgmg_handle* h, const double* r64, double* z64) {
   const int L = h->L;
   const T omega = (T)h->o.omega;
   const int nu1 = h->o.nu1, nu2 = h->o.nu2;
-  const dim3 ssb(WAVE * NW);
+  const T w1 = nu1 > 0 ? omega : T(0);
   std::vector<T*> xs(L + 1), xbs(L + 1);
   for (int l = 0; l <= L; ++l) {
     xs[l] = (T*)h->lv[l].x;
@@ -604,7 +587,7 @@ void vcycle_t(cdgmg_handle* h, const double* r64, double* z64) {
   if (L == 0) {
     DLevel& d = h->lv[0];
     launch(h, CDGMG_K_VECTOR, k_cast<double, T>, dim3(grid_for(d.n * NP)), dim3(TPB), d.n * NP, r64, (T*)d.b);
-    launch(h, CDGMG_K_COARSE, k_dense_gemv<T>, dim3(grid_for(h->nd * WAVE)), dim3(TPB), h->nd, Ops<T>::Ainv(h),
+    launch(h, CDGMG_K_COARSE, k_dense_gemv<T>, dim3(grid_for(h->nd * WAVE)), dim3(TPB), h->nd, ainv<T>(h),
            (const T*)d.b, xs[0]);
     launch(h, CDGMG_K_VECTOR, k_cast<T, double>, dim3(grid_for(d.n * NP)), dim3(TPB), d.n * NP, (const T*)xs[0],
            z64);
@@ -612,50 +595,38 @@ void vcycle_t(cdgmg_handle* h, const double* r64, double* z64) {
   }
   for (int l = 0; l < L; ++l) {
     DLevel& d = h->lv[l];
-    const bool rs = use_rs(h, l);
-    const T* Dv = nu1 > 0 ? Ops<T>::D(d) : nullptr;
-    const int tpb = row_tpb(h, l);
     if (l == 0) {
-      if (nu1 > 0) {
-        launch(h, CDGMG_K_SMOOTH, k_smooth_first<T, double, NP>, dim3(grid_for(d.n, tpb)), dim3(tpb), d.n, r64,
-               (T*)d.b, Dv, omega, xs[0]);
-      } else {
-        launch(h, CDGMG_K_VECTOR, k_cast<double, T>, dim3(grid_for(d.n * NP)), dim3(TPB), d.n * NP, r64, (T*)d.b);
-        (void)hipMemsetAsync(xs[0], 0, d.n * NP * sizeof(T), h->stream);
-      }
+      H_DISPATCH(h->H0, if constexpr (NP % H == 0) launch(h, CDGMG_K_SMOOTH, k_entry0<T, NP, H>, 
+                                                          dim3((unsigned)d.ns), dim3(WAVE * H), d.n, r64,
+                                                          (const T*)d.Dm, w1, (T*)d.b, xs[0]));
     } else {
-      launch(h, CDGMG_K_SMOOTH, k_gather_smooth_first<T, NP>, dim3(grid_for(d.n, tpb)), dim3(tpb), d.n,
-             (const int32_t*)d.child_start, (const T*)h->lv[l - 1].t, (T*)d.b, Dv, omega, xs[l]);
-      if (nu1 == 0) (void)hipMemsetAsync(xs[l], 0, d.n * NP * sizeof(T), h->stream);
+      const int tpb = row_tpb(h, l);
+      launch(h, CDGMG_K_SMOOTH, k_entry_c<T, NP>, dim3(grid_for(d.n, tpb)), dim3(tpb), d.n,
+             (const int32_t*)d.child_start, (const T*)h->lv[l - 1].t, (const T*)d.Dm, w1, (T*)d.b, xs[l]);
     }
-    smooth_sweeps<T, NP>(h, l, nu1 - 1 > 0 ? nu1 - 1 : 0, &xs[l], &xbs[l]);
-    if (kmode(h, l) == KM_HS2)
-      launch_hs_restrict<T, NP, 2>(h, d, Ops<T>::A(d), (const T*)d.b, (const T*)xs[l], Ops<T>::L(d), (T*)d.t);
-    else if (kmode(h, l) == KM_HS4)
-      launch_hs_restrict<T, NP, 4>(h, d, Ops<T>::A(d), (const T*)d.b, (const T*)xs[l], Ops<T>::L(d), (T*)d.t);
-    else if (kmode(h, l) == KM_WPR)
-      launch(h, CDGMG_K_RESTRICT, k_residual_restrict_wpr<T, NP>, dim3(grid_for(d.n * WAVE)), dim3(TPB), d.n,
-             (const int32_t*)d.wcols, (const int64_t*)d.woff, Ops<T>::R(d), (const T*)d.b, (const T*)xs[l],
-             Ops<T>::L(d), (T*)d.t);
-    else if (rs)
-      launch(h, CDGMG_K_RESTRICT, k_residual_restrict_ss<T, NP>, dim3((unsigned)d.ns), ssb, d.n,
-             (const int32_t*)d.cols, (const int64_t*)d.sblk, Ops<T>::A(d), (const T*)d.b, (const T*)xs[l],
-             Ops<T>::L(d), (T*)d.t);
-    else
-      launch(h, CDGMG_K_RESTRICT, k_residual_restrict<T, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n,
-             (const int32_t*)d.cols, (const int64_t*)d.sblk, Ops<T>::A(d), (const T*)d.b, (const T*)xs[l],
-             Ops<T>::L(d), (T*)d.t);
+    smooth_sweeps<T, NP>(h, l, nu1 > 1 ? nu1 - 1 : 0, &xs[l], &xbs[l]);
+    if (l == 0) {
+      H_DISPATCH(h->H0, if constexpr (NP % H == 0) launch(h, CDGMG_K_RESTRICT, k_restrict0<T, NP, H>,
+                                                          dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
+                                                          (const int32_t*)d.cols, (const int64_t*)d.sblk,
+                                                          (const T*)d.At, (const T*)d.b, (const T*)xs[0],
+                                                          (const T*)d.Lt, (T*)d.t));
+    } else {
+      launch(h, CDGMG_K_RESTRICT, k_restrict_wpr<T, NP>, dim3(grid_for(d.n * WAVE)), dim3(TPB), d.n,
+             (const int32_t*)d.wcols, (const int64_t*)d.woff, (const T*)d.R, (const T*)d.b, (const T*)xs[l],
+             (const T*)d.Lt, (T*)d.t);
+    }
   }
   DLevel& c = h->lv[L];
-  launch(h, CDGMG_K_COARSE, k_gather_smooth_first<T, NP>, dim3(grid_for(c.n, WAVE)), dim3(WAVE), c.n,
-         (const int32_t*)c.child_start, (const T*)h->lv[L - 1].t, (T*)c.b, (const T*)nullptr, omega, (T*)nullptr);
-  launch(h, CDGMG_K_COARSE, k_dense_gemv<T>, dim3(grid_for(h->nd * WAVE)), dim3(TPB), h->nd, Ops<T>::Ainv(h),
+  launch(h, CDGMG_K_COARSE, k_entry_c<T, NP>, dim3(grid_for(c.n, WAVE)), dim3(WAVE), c.n,
+         (const int32_t*)c.child_start, (const T*)h->lv[L - 1].t, (const T*)nullptr, omega, (T*)c.b, (T*)nullptr);
+  launch(h, CDGMG_K_COARSE, k_dense_gemv<T>, dim3(grid_for(h->nd * WAVE)), dim3(TPB), h->nd, ainv<T>(h),
          (const T*)c.b, xs[L]);
   for (int l = L - 1; l >= 0; --l) {
     DLevel& d = h->lv[l];
     const int tpb = row_tpb(h, l);
     launch(h, CDGMG_K_PROLONG, k_prolong<T, NP>, dim3(grid_for(d.n, tpb)), dim3(tpb), d.n, (const int32_t*)d.parent,
-           Ops<T>::L(d), (const T*)xs[l + 1], xs[l]);
+           (const T*)d.Lm, (const T*)xs[l + 1], xs[l]);
     smooth_sweeps<T, NP>(h, l, nu2, &xs[l], &xbs[l]);
   }
   launch(h, CDGMG_K_VECTOR, k_cast<T, double>, dim3(grid_for(h->N0 * NP)), dim3(TPB), h->N0 * NP,
@@ -689,18 +660,13 @@ int read_scalar(cdgmg_handle* h, int slot, double* out) {
 // recursive residual is replaced by it); returns ||r||^2
 int true_residual(cdgmg_handle* h, double* rr) {
   DLevel& d = h->lv[0];
-  const int km0 = kmode(h, 0);
-  const unsigned g = (km0 == KM_HS2 || km0 == KM_HS4) ? (unsigned)d.ns : grid_for(d.n);
-  if (km0 == KM_HS4) {
-    NP_DISPATCH(h->np, launch_residual2_hs<NP, 4>(h, d));
-  } else if (km0 == KM_HS2) {
-    NP_DISPATCH(h->np, launch_residual2_hs<NP, 2>(h, d));
-  } else {
-    NP_DISPATCH(h->np, launch(h, CDGMG_K_VECTOR, k_residual2<NP>, dim3(g), dim3(TPB), d.n, (const int32_t*)d.cols,
-                              (const int64_t*)d.sblk, (const double*)d.A64, (const double*)h->b,
-                              (const double*)h->x, (const double*)h->xl, h->r, h->part));
-  }
-  launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)g, 1, h->scal, SC_TMP);
+  NP_DISPATCH(h->np, H_DISPATCH(h->H0, if constexpr (NP % H == 0) launch(h, CDGMG_K_VECTOR, k_residual2_hs<NP, H>,
+                                                                       dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
+                                                                       (const int32_t*)d.cols, (const int64_t*)d.sblk,
+                                                                       (const double*)d.A64, (const double*)h->b,
+                                                                       (const double*)h->x, (const double*)h->xl,
+                                                                       h->r, h->part)));
+  launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)d.ns, 1, h->scal, SC_TMP);
   return read_scalar(h, SC_TMP, rr);
 }
 
@@ -770,20 +736,19 @@ int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
         launch(h, CDGMG_K_VECTOR, k_update_p, dim3(grid_for(m)), dim3(TPB), m, (const double*)h->z, h->p,
                (const double*)h->scal, 1.0, it == 0 ? 1 : 0);
       }
-      const int km0 = kmode(h, 0);
-      const unsigned g = (km0 == KM_HS2 || km0 == KM_HS4) ? (unsigned)d0.ns : grid_for(d0.n);
-      if (km0 == KM_HS4) {
-        NP_DISPATCH(np, launch_spmv_hs<NP, 4>(h, d0, accurate));
-      } else if (km0 == KM_HS2) {
-        NP_DISPATCH(np, launch_spmv_hs<NP, 2>(h, d0, accurate));
-      } else if (accurate) {
-        NP_DISPATCH(np, launch(h, CDGMG_K_SPMV, k_spmv2_dots<NP>, dim3(g), dim3(TPB), d0.n,
-                               (const int32_t*)d0.cols, (const int64_t*)d0.sblk, (const double*)d0.A64,
-                               (const double*)h->p, (const double*)h->r, h->q, h->part));
+      const unsigned g = (unsigned)d0.ns;
+      if (accurate) {
+        NP_DISPATCH(np, H_DISPATCH(h->H0, if constexpr (NP % H == 0) launch(
+                                              h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, true>, dim3(g), dim3(WAVE * H),
+                                              d0.n, (const int32_t*)d0.cols, (const int64_t*)d0.sblk,
+                                              (const double*)d0.A64, (const double*)h->p, (const double*)h->r, h->q,
+                                              h->part)));
       } else {
-        NP_DISPATCH(np, launch(h, CDGMG_K_SPMV, k_spmv_dots<NP>, dim3(g), dim3(TPB), d0.n,
-                               (const int32_t*)d0.cols, (const int64_t*)d0.sblk, (const double*)d0.A64,
-                               (const double*)h->p, (const double*)h->r, h->q, h->part));
+        NP_DISPATCH(np, H_DISPATCH(h->H0, if constexpr (NP % H == 0) launch(
+                                              h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, false>, dim3(g), dim3(WAVE * H),
+                                              d0.n, (const int32_t*)d0.cols, (const int64_t*)d0.sblk,
+                                              (const double*)d0.A64, (const double*)h->p, (const double*)h->r, h->q,
+                                              h->part)));
       }
       launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)g, 2, h->scal, SC_PQ);
       launch(h, CDGMG_K_VECTOR, k_scalars, dim3(1), dim3(1), h->scal, fcg ? 2 : 3);
@@ -943,6 +908,13 @@ int cdgmg_setup(const cdgmg_mesh* mesh, int p, const double* kappa_dev, const cd
     set_error(std::string("setup: ") + e.what());
     rc = CDGMG_ERR_NOMEM;
   }
+  if (!rc) {
+    h->H0 = pick_h0(h->P.np, o.kernel_variant);
+    if (!h->H0) {
+      set_error("setup: kernel_variant must be 0 or one of 1, 2, 4, 5 dividing n_p = " + std::to_string(h->P.np));
+      rc = CDGMG_ERR_ARG;
+    }
+  }
   if (!rc) rc = upload_problem(h);
   if (!rc) rc = build_operators(h, kappa_dev);
   if (!rc && hipStreamSynchronize(h->stream) != hipSuccess) {
@@ -1039,7 +1011,7 @@ int cdgmg_apply_A(cdgmg_handle* h, int level, int precision, const void* x_dev, 
     double *xi = h->t1, *yi = h->t2;
     launch(h, -1, k_permute<double>, dim3(grid_for(d.n * np)), dim3(TPB), d.n, np, (const int32_t*)d.perm,
            (const double*)x_dev, xi, 0);
-    NP_DISPATCH(np, launch(h, -1, k_spmv<double, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n, (const int32_t*)d.cols,
+    NP_DISPATCH(np, launch(h, -1, k_spmv<double, double, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n, (const int32_t*)d.cols,
                            (const int64_t*)d.sblk, (const double*)d.A64, (const double*)xi, yi));
     launch(h, -1, k_permute<double>, dim3(grid_for(d.n * np)), dim3(TPB), d.n, np, (const int32_t*)d.perm,
            (const double*)yi, (double*)y_dev, 1);
@@ -1047,8 +1019,9 @@ int cdgmg_apply_A(cdgmg_handle* h, int level, int precision, const void* x_dev, 
     float *xi = (float*)h->t1, *yi = (float*)h->t2;
     launch(h, -1, k_permute<float>, dim3(grid_for(d.n * np)), dim3(TPB), d.n, np, (const int32_t*)d.perm,
            (const float*)x_dev, xi, 0);
-    NP_DISPATCH(np, launch(h, -1, k_spmv<float, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n, (const int32_t*)d.cols,
-                           (const int64_t*)d.sblk, (const float*)d.A32, (const float*)xi, yi));
+    NP_DISPATCH(np, launch(h, -1, k_spmv<double, float, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n,
+                           (const int32_t*)d.cols, (const int64_t*)d.sblk, (const double*)d.A64, (const float*)xi,
+                           yi));
     launch(h, -1, k_permute<float>, dim3(grid_for(d.n * np)), dim3(TPB), d.n, np, (const int32_t*)d.perm,
            (const float*)yi, (float*)y_dev, 1);
   }
