@@ -307,16 +307,51 @@ __global__ __launch_bounds__(TPB) void k_prolong(int64_t n, const int32_t* __res
   }
 }
 
-// coarsest: x = A_L^{-1} b, one wavefront per row
+// coarsest: x = A_L^{-1} b, one wavefront per row; the inverse is stored with
+// a leading dimension ld (a multiple of 64) and zero padding columns, b with
+// zero padding up to ld, so every lane reads whole 16-byte vectors
 template <typename T>
-__global__ void k_dense_gemv(int64_t n, const T* __restrict__ Ainv, const T* __restrict__ b, T* __restrict__ x) {
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int k = 4;
+  __device__ static float dot(const float4& a, const float4& b) {
+    return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
+  }
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int k = 2;
+  __device__ static double dot(const double2& a, const double2& b) { return a.x * b.x + a.y * b.y; }
+};
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_dense_gemv(int64_t n, int64_t ld, const T* __restrict__ Ainv,
+                                                    const T* __restrict__ b, T* __restrict__ x) {
+  using V = typename Vec16<T>::type;
+  constexpr int KV = Vec16<T>::k;
   const int64_t row = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
   const int lane = threadIdx.x % WAVE;
   if (row >= n) return;
+  const V* Ar = reinterpret_cast<const V*>(Ainv + row * ld);
+  const V* bv = reinterpret_cast<const V*>(b);
+  const int64_t nv = ld / KV;
   T s = 0;
-  for (int64_t c = lane; c < n; c += WAVE) s += Ainv[row * n + c] * b[c];
+#pragma unroll 4
+  for (int64_t c = lane; c < nv; c += WAVE) s += Vec16<T>::dot(Ar[c], bv[c]);
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
   if (lane == 0) x[row] = s;
+}
+
+// dst (n x ld, zero padding columns) = (D) src (n x n)
+template <typename S, typename D>
+__global__ void k_pad_cast(int64_t n, int64_t ld, const S* __restrict__ src, D* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * ld) return;
+  const int64_t r = i / ld, c = i % ld;
+  dst[i] = c < n ? (D)src[r * n + c] : D(0);
 }
 
 // ------------------------------------------------------------------
@@ -356,22 +391,33 @@ __device__ __forceinline__ void hs_scaled_residual(int64_t r, int lane, int h, c
   }
 }
 
-// sweep on level 0
-template <typename T, int NP, int H>
+// sweep on level 0; with DOT, also the slice's partial sum of (xout, dv) in
+// FP64 (part[slice]), which the outer loop needs of the preconditioned residual
+template <typename T, int NP, int H, bool DOT>
 __global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* __restrict__ cols,
                                                      const int64_t* __restrict__ sblk, const T* __restrict__ At,
                                                      const T* __restrict__ bt, const T* __restrict__ xin, T omega,
-                                                     T* __restrict__ xout) {
+                                                     T* __restrict__ xout, const double* __restrict__ dv,
+                                                     double* __restrict__ part) {
   constexpr int NI = NP / H;
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
   const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
-  if (r >= n) return;
-  T acc[NI];
-  hs_scaled_residual<T, NP, H>(r, lane, h, cols, sblk, At, bt, xin, acc);
+  double d = 0.0;
+  if (r < n) {
+    T acc[NI];
+    hs_scaled_residual<T, NP, H>(r, lane, h, cols, sblk, At, bt, xin, acc);
 #pragma unroll
-  for (int t = 0; t < NI; ++t) {
-    const int64_t k = r * NP + h * NI + t;
-    xout[k] = xin[k] + omega * acc[t];
+    for (int t = 0; t < NI; ++t) {
+      const int64_t k = r * NP + h * NI + t;
+      const T v = xin[k] + omega * acc[t];
+      xout[k] = v;
+      if constexpr (DOT) d += (double)v * dv[k];
+    }
+  }
+  if constexpr (DOT) {
+    __shared__ double sh[H];
+    d = block_sum(d, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = d;
   }
 }
 
@@ -460,72 +506,113 @@ __global__ __launch_bounds__(TPB) void k_entry_c(int64_t n, const int32_t* __res
   }
 }
 
-// Coarse levels (wave per row): row r's off-diagonal blocks are a dense
+// Coarse levels (G lanes per row): row r's off-diagonal blocks are a dense
 // n_p x (len_r - 1) n_p strip, component-major, unpadded, at (woff[r] - r) n_p^2;
-// lane l takes strip columns k = l, l + 64, ... for every component; the n_p
-// partial sums are reduced with xor-shuffles.  Columns: wcols[woff[r] + 1 + w].
-template <typename T>
-__device__ __forceinline__ T wave_allsum(T v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// the G lanes of row r take strip columns k = g, g + G, ... for every
+// component, and the n_p partial sums are reduced with xor-shuffles inside the
+// aligned G-lane group.  64 / G rows share a wavefront, so short rows still
+// keep many independent loads in flight.  Columns: wcols[woff[r] + 1 + w].
+template <int G, typename T>
+__device__ __forceinline__ T group_allsum(T v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-template <typename T, int NP>
-__device__ __forceinline__ void wpr_scaled_residual(int64_t r, int lane, const int32_t* __restrict__ wcols,
+template <typename T, int NP, int G>
+__device__ __forceinline__ void grp_scaled_residual(int64_t r, int g, const int32_t* __restrict__ wcols,
                                                     const int64_t* __restrict__ woff, const T* __restrict__ R,
                                                     const T* __restrict__ bt, const T* __restrict__ x, T* res) {
+  // U strip columns per lane per chunk: all their loads are issued before the
+  // first product, so a chunk costs one memory latency
+  constexpr int U = G >= 32 ? 2 : 64 / G;
   const int64_t o = woff[r];
   const int K = (int)(woff[r + 1] - o - 1) * NP;
   const T* Rr = R + (o - r) * NP * NP;
   T acc[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) acc[i] = 0;
-  for (int k = lane; k < K; k += WAVE) {
-    const int w = k / NP, j = k - w * NP;
-    const T xv = x[(int64_t)wcols[o + 1 + w] * NP + j];
+  for (int k0 = g; k0 < K; k0 += U * G) {
+    // column indices and strip values first (independent), then the x gather;
+    // past the strip end a lane re-reads its first column (in bounds, weight 0)
+    int c[U], j[U];
+    T xv[U], rv[U][NP];
 #pragma unroll
-    for (int i = 0; i < NP; ++i) acc[i] += Rr[(int64_t)i * K + k] * xv;
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * G;
+      const int kk = k < K ? k : g;
+      const int w = kk / NP;
+      j[u] = kk - w * NP;
+      c[u] = wcols[o + 1 + w];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) rv[u][i] = Rr[(int64_t)i * K + kk];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const T v = x[(int64_t)c[u] * NP + j[u]];
+      xv[u] = k0 + u * G < K ? v : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int i = 0; i < NP; ++i) acc[i] += rv[u][i] * xv[u];
   }
 #pragma unroll
-  for (int i = 0; i < NP; ++i) res[i] = bt[r * NP + i] - x[r * NP + i] - wave_allsum(acc[i]);
+  for (int i = 0; i < NP; ++i) res[i] = group_allsum<G>(acc[i]);
 }
 
-template <typename T, int NP>
-__global__ __launch_bounds__(TPB) void k_sweep_wpr(int64_t n, const int32_t* __restrict__ wcols,
+// lane g of a group writes components g, g + G, ...
+template <typename T, int NP, int G>
+__global__ __launch_bounds__(TPB) void k_sweep_grp(int64_t n, const int32_t* __restrict__ wcols,
                                                    const int64_t* __restrict__ woff, const T* __restrict__ R,
                                                    const T* __restrict__ bt, const T* __restrict__ xin, T omega,
                                                    T* __restrict__ xout) {
-  const int lane = threadIdx.x % WAVE;
-  const int64_t r = (int64_t)blockIdx.x * (TPB / WAVE) + threadIdx.x / WAVE;
+  const int64_t gid = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const int64_t r = gid / G;
+  const int g = (int)(gid % G);
   if (r >= n) return;
-  T res[NP];
-  wpr_scaled_residual<T, NP>(r, lane, wcols, woff, R, bt, xin, res);
-  if (lane < NP) {
-    T v = res[0];
+  T sum[NP];
+  grp_scaled_residual<T, NP, G>(r, g, wcols, woff, R, bt, xin, sum);
 #pragma unroll
-    for (int i = 1; i < NP; ++i)
-      if (lane == i) v = res[i];
-    xout[r * NP + lane] = xin[r * NP + lane] + omega * v;
+  for (int m = 0; m < (NP + G - 1) / G; ++m) {
+    const int i = g + m * G;
+    if (i < NP) {
+      T si = sum[0];
+#pragma unroll
+      for (int q = 1; q < NP; ++q)
+        if (q == i) si = sum[q];
+      const T xi = xin[r * NP + i];
+      xout[r * NP + i] = xi + omega * (bt[r * NP + i] - xi - si);
+    }
   }
 }
 
-template <typename T, int NP>
-__global__ __launch_bounds__(TPB) void k_restrict_wpr(int64_t n, const int32_t* __restrict__ wcols,
+// every lane forms the whole scaled residual of its row (n_p values), then
+// lane g writes t_j = sum_i Lt(i, j) res_i for j = g, g + G, ...
+template <typename T, int NP, int G>
+__global__ __launch_bounds__(TPB) void k_restrict_grp(int64_t n, const int32_t* __restrict__ wcols,
                                                       const int64_t* __restrict__ woff, const T* __restrict__ R,
                                                       const T* __restrict__ bt, const T* __restrict__ x,
                                                       const T* __restrict__ Lt, T* __restrict__ t) {
   constexpr int NP2 = NP * NP;
-  const int lane = threadIdx.x % WAVE;
-  const int64_t r = (int64_t)blockIdx.x * (TPB / WAVE) + threadIdx.x / WAVE;
+  const int64_t gid = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const int64_t r = gid / G;
+  const int g = (int)(gid % G);
   if (r >= n) return;
   T res[NP];
-  wpr_scaled_residual<T, NP>(r, lane, wcols, woff, R, bt, x, res);
-  if (lane < NP) {
-    const T* Lr = Lt + (r / WAVE) * WAVE * NP2 + (r % WAVE);
-    T s = 0;
+  grp_scaled_residual<T, NP, G>(r, g, wcols, woff, R, bt, x, res);
 #pragma unroll
-    for (int i = 0; i < NP; ++i) s += Lr[(i * NP + lane) * WAVE] * res[i];
-    t[r * NP + lane] = s;
+  for (int i = 0; i < NP; ++i) res[i] = bt[r * NP + i] - x[r * NP + i] - res[i];
+  const T* Lr = Lt + (r / WAVE) * WAVE * NP2 + (r % WAVE);
+#pragma unroll
+  for (int m = 0; m < (NP + G - 1) / G; ++m) {
+    const int j = g + m * G;
+    if (j < NP) {
+      T s = 0;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) s += Lr[(i * NP + j) * WAVE] * res[i];
+      t[r * NP + j] = s;
+    }
   }
 }
 
@@ -866,12 +953,26 @@ __global__ void k_scalars(double* s, int mode) {
   }
 }
 
-// p = z + sign * beta * p  (first iteration: p = z)
-__global__ void k_update_p(int64_t m, const double* __restrict__ z, double* __restrict__ p,
-                           const double* __restrict__ s, double sign, int first) {
+// p = z + sign * beta * p  (first iteration: p = z); z in the multigrid precision
+template <typename T>
+__global__ void k_update_p(int64_t m, const T* __restrict__ z, double* __restrict__ p, const double* __restrict__ s,
+                           double sign, int first) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
-  p[i] = first ? z[i] : z[i] + sign * s[SC_BETA] * p[i];
+  const double zi = (double)z[i];
+  p[i] = first ? zi : zi + sign * s[SC_BETA] * p[i];
+}
+
+// partial sums of (z, v), z in the multigrid precision, grid-stride
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_dot_t(int64_t m, const T* __restrict__ z, const double* __restrict__ v,
+                                               double* __restrict__ part) {
+  __shared__ double sh[TPB / WAVE];
+  double s0 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    s0 += (double)z[i] * v[i];
+  s0 = block_sum(s0, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s0;
 }
 
 // x += alpha p; r -= alpha q; partial ||r||^2

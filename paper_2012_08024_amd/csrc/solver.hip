@@ -52,6 +52,15 @@ using namespace cdg;
     default: break;                                        \
   }
 
+// lanes per row of the coarse-level kernels
+#define G_DISPATCH(gv, ...)                                  \
+  switch (gv) {                                              \
+    case 8: { constexpr int G = 8; __VA_ARGS__; } break;     \
+    case 16: { constexpr int G = 16; __VA_ARGS__; } break;   \
+    case 32: { constexpr int G = 32; __VA_ARGS__; } break;   \
+    default: { constexpr int G = 64; __VA_ARGS__; } break;   \
+  }
+
 namespace {
 
 struct DLevel {
@@ -87,6 +96,7 @@ struct DLevel {
   int32_t* wcols = nullptr;
   int64_t* woff = nullptr;
   void* R = nullptr;
+  int grp_s = 64, grp_r = 64;  // lanes per row of the sweep and of the restriction
 };
 
 struct ProfEv {
@@ -110,12 +120,12 @@ struct cdgmg_handle {
   double *UA = nullptr, *UH = nullptr, *M = nullptr, *kappa = nullptr;
   int8_t *hostflag = nullptr, *revslot = nullptr;
   // coarsest
-  int64_t nd = 0;
+  int64_t nd = 0, ld = 0;
   double *Ainv64 = nullptr, *dense1 = nullptr;
-  float* Ainv32 = nullptr;
+  void* AinvP = nullptr;  // A_L^{-1} in the multigrid precision, leading dimension ld
   // outer vectors (internal order, FP64)
-  double *b = nullptr, *x = nullptr, *xl = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr,
-         *y = nullptr, *t1 = nullptr, *t2 = nullptr;
+  double *b = nullptr, *x = nullptr, *xl = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *t1 = nullptr,
+         *t2 = nullptr;
   double *scal = nullptr, *part = nullptr;
   int nparts = 0;
   int* err = nullptr;
@@ -364,6 +374,16 @@ int upload_problem(cdgmg_handle* h) {
       void* tmp;
       RETURN_IF(dalloc(h, (char**)&tmp, nr * (fp32 ? sizeof(float) : sizeof(double))));
       D.R = tmp;
+      // lanes per row by the mean strip width (measured on n_p = 10 strips of
+      // 53 columns: the sweep is fastest with 32 lanes on large levels and 16
+      // on smaller ones, the restriction, which also reads D L_e, with 16)
+      const double kmean = (double)(H.nnzb - H.n) * np / std::max<int64_t>(H.n, 1);
+      if (kmean <= 96) {
+        D.grp_s = H.n >= 16384 ? 32 : 16;
+        D.grp_r = 16;
+      } else {
+        D.grp_s = D.grp_r = kmean <= 192 ? 32 : 64;
+      }
     }
     if (l >= 1) {
       std::vector<int32_t> cs(H.child_start.begin(), H.child_start.end());
@@ -387,6 +407,8 @@ int upload_problem(cdgmg_handle* h) {
     D.xb = tmp;
     RETURN_IF(dalloc(h, &tmp, vb / sizeof(double)));
     D.t = tmp;
+    // padding entries past n n_p stay zero (the dense coarsest product reads them)
+    for (void* v : {D.b, D.x, D.xb, D.t}) HIPCHK(hipMemsetAsync(v, 0, vb, h->stream));
   }
   // level-0 kappa-free blocks
   RETURN_IF(upload(h, &h->UA, to_sliced(P.UA, P.lv[0], h->W0, np2)));
@@ -403,10 +425,15 @@ int upload_problem(cdgmg_handle* h) {
   }
   RETURN_IF(dalloc(h, &h->Ainv64, (size_t)h->nd * h->nd));
   RETURN_IF(dalloc(h, &h->dense1, (size_t)h->nd * h->nd));
-  if (fp32) RETURN_IF(dalloc(h, &h->Ainv32, (size_t)h->nd * h->nd));
+  h->ld = (h->nd + 63) / 64 * 64;
+  {
+    void* tmp;
+    RETURN_IF(dalloc(h, (char**)&tmp, (size_t)h->nd * h->ld * (fp32 ? sizeof(float) : sizeof(double))));
+    h->AinvP = tmp;
+  }
   // outer vectors
   const size_t m = (size_t)h->lv[0].ns * SLICE * np;
-  for (double** v : {&h->b, &h->x, &h->xl, &h->r, &h->z, &h->p, &h->q, &h->y, &h->t1, &h->t2}) {
+  for (double** v : {&h->b, &h->x, &h->xl, &h->r, &h->p, &h->q, &h->t1, &h->t2}) {
     RETURN_IF(dalloc(h, v, m));
     HIPCHK(hipMemsetAsync(*v, 0, m * sizeof(double), h->stream));
   }
@@ -521,24 +548,16 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev) {
   RETURN_IF(check_err(h, CDGMG_ERR_SINGULAR, flux ? "setup: the coarsest operator is singular"
                                                   : "setup: the coarsest operator is not positive definite"));
   if (h->o.mg_precision == CDGMG_MG_FP32)
-    launch(h, -1, k_cast<double, float>, dim3(grid_for(nd * nd)), dim3(TPB), nd * nd, (const double*)h->Ainv64,
-           h->Ainv32);
+    launch(h, -1, k_pad_cast<double, float>, dim3(grid_for(nd * h->ld)), dim3(TPB), nd, h->ld,
+           (const double*)h->Ainv64, (float*)h->AinvP);
+  else
+    launch(h, -1, k_pad_cast<double, double>, dim3(grid_for(nd * h->ld)), dim3(TPB), nd, h->ld,
+           (const double*)h->Ainv64, (double*)h->AinvP);
   HIPCHK(hipGetLastError());
   return CDGMG_OK;
 }
 
 // ---------------------------------------------------------------- V-cycle
-template <typename T>
-const T* ainv(const cdgmg_handle* h);
-template <>
-const float* ainv<float>(const cdgmg_handle* h) {
-  return h->Ainv32;
-}
-template <>
-const double* ainv<double>(const cdgmg_handle* h) {
-  return h->Ainv64;
-}
-
 // wavefronts per 64-row slice of the level-0 kernels: 0 picks by n_p (the
 // n_p = 10, 20 blocks need the split to keep enough loads in flight)
 int pick_h0(int np, int variant) {
@@ -547,23 +566,44 @@ int pick_h0(int np, int variant) {
   return 0;
 }
 
+// count damped block-Jacobi sweeps on level l (ping-pong x <-> xb); with dv
+// given, the last level-0 sweep also leaves the partial sums of (x, dv) in
+// h->part, one per slice
 template <typename T, int NP>
-void smooth_sweeps(cdgmg_handle* h, int l, int count, T** x, T** xb) {
+void smooth_sweeps(cdgmg_handle* h, int l, int count, T** x, T** xb, const double* dv = nullptr) {
   DLevel& d = h->lv[l];
   const T omega = (T)h->o.omega;
   const int cls = l == 0 ? CDGMG_K_SMOOTH0 : CDGMG_K_SMOOTH;
   for (int s = 0; s < count; ++s) {
     if (l == 0) {
-      H_DISPATCH(h->H0, if constexpr (NP % H == 0) launch(h, cls, k_sweep0<T, NP, H>, dim3((unsigned)d.ns),
-                                                          dim3(WAVE * H), d.n, (const int32_t*)d.cols,
-                                                          (const int64_t*)d.sblk, (const T*)d.At, (const T*)d.b,
-                                                          (const T*)*x, omega, *xb));
+      const bool dot = dv && s == count - 1;
+      if (dot) {
+        H_DISPATCH(h->H0, if constexpr (NP % H == 0) launch(
+                              h, cls, k_sweep0<T, NP, H, true>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
+                              (const int32_t*)d.cols, (const int64_t*)d.sblk, (const T*)d.At, (const T*)d.b,
+                              (const T*)*x, omega, *xb, dv, h->part));
+      } else {
+        H_DISPATCH(h->H0, if constexpr (NP % H == 0) launch(
+                              h, cls, k_sweep0<T, NP, H, false>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
+                              (const int32_t*)d.cols, (const int64_t*)d.sblk, (const T*)d.At, (const T*)d.b,
+                              (const T*)*x, omega, *xb, (const double*)nullptr, (double*)nullptr));
+      }
     } else {
-      launch(h, cls, k_sweep_wpr<T, NP>, dim3(grid_for(d.n * WAVE)), dim3(TPB), d.n, (const int32_t*)d.wcols,
-             (const int64_t*)d.woff, (const T*)d.R, (const T*)d.b, (const T*)*x, omega, *xb);
+      G_DISPATCH(d.grp_s, launch(h, cls, k_sweep_grp<T, NP, G>, dim3(grid_for(d.n * G)), dim3(TPB), d.n,
+                                 (const int32_t*)d.wcols, (const int64_t*)d.woff, (const T*)d.R, (const T*)d.b,
+                                 (const T*)*x, omega, *xb));
     }
     std::swap(*x, *xb);
   }
+}
+
+// partial sums of (z, dv) into h->part
+template <typename T>
+void dot_t(cdgmg_handle* h, const T* z, const double* dv, int* nparts) {
+  const int64_t m = h->N0 * h->np;
+  const unsigned g = std::min<unsigned>(1024, grid_for(m));
+  launch(h, CDGMG_K_VECTOR, k_dot_t<T>, dim3(g), dim3(TPB), m, z, dv, h->part);
+  *nparts = (int)g;
 }
 
 // thread-per-row kernels: one-wavefront workgroups on small levels spread the
@@ -573,8 +613,10 @@ inline int row_tpb(const cdgmg_handle* h, int l) { return h->lv[l].n < 100000 ? 
 // One V-cycle z = B r (Sec. 4): on each level the first pre-smoothing sweep
 // starts from zero and is fused with forming D^{-1} b; residual and
 // restriction are fused; the coarsest level applies the dense inverse.
+// Returns z in the multigrid precision (a level-0 work vector).  With dv
+// given, *nparts partial sums of (z, dv) are left in h->part.
 template <typename T, int NP>
-void vcycle_t(cdgmg_handle* h, const double* r64, double* z64) {
+T* vcycle_t(cdgmg_handle* h, const double* r64, const double* dv, int* nparts) {
   const int L = h->L;
   const T omega = (T)h->o.omega;
   const int nu1 = h->o.nu1, nu2 = h->o.nu2;
@@ -587,11 +629,10 @@ void vcycle_t(cdgmg_handle* h, const double* r64, double* z64) {
   if (L == 0) {
     DLevel& d = h->lv[0];
     launch(h, CDGMG_K_VECTOR, k_cast<double, T>, dim3(grid_for(d.n * NP)), dim3(TPB), d.n * NP, r64, (T*)d.b);
-    launch(h, CDGMG_K_COARSE, k_dense_gemv<T>, dim3(grid_for(h->nd * WAVE)), dim3(TPB), h->nd, ainv<T>(h),
-           (const T*)d.b, xs[0]);
-    launch(h, CDGMG_K_VECTOR, k_cast<T, double>, dim3(grid_for(d.n * NP)), dim3(TPB), d.n * NP, (const T*)xs[0],
-           z64);
-    return;
+    launch(h, CDGMG_K_COARSE, k_dense_gemv<T>, dim3(grid_for(h->nd * WAVE)), dim3(TPB), h->nd, h->ld,
+           (const T*)h->AinvP, (const T*)d.b, xs[0]);
+    if (dv) dot_t<T>(h, xs[0], dv, nparts);
+    return xs[0];
   }
   for (int l = 0; l < L; ++l) {
     DLevel& d = h->lv[l];
@@ -612,33 +653,51 @@ void vcycle_t(cdgmg_handle* h, const double* r64, double* z64) {
                                                           (const T*)d.At, (const T*)d.b, (const T*)xs[0],
                                                           (const T*)d.Lt, (T*)d.t));
     } else {
-      launch(h, CDGMG_K_RESTRICT, k_restrict_wpr<T, NP>, dim3(grid_for(d.n * WAVE)), dim3(TPB), d.n,
-             (const int32_t*)d.wcols, (const int64_t*)d.woff, (const T*)d.R, (const T*)d.b, (const T*)xs[l],
-             (const T*)d.Lt, (T*)d.t);
+      G_DISPATCH(d.grp_r, launch(h, CDGMG_K_RESTRICT, k_restrict_grp<T, NP, G>, dim3(grid_for(d.n * G)), dim3(TPB),
+                             d.n, (const int32_t*)d.wcols, (const int64_t*)d.woff, (const T*)d.R, (const T*)d.b,
+                             (const T*)xs[l], (const T*)d.Lt, (T*)d.t));
     }
   }
   DLevel& c = h->lv[L];
   launch(h, CDGMG_K_COARSE, k_entry_c<T, NP>, dim3(grid_for(c.n, WAVE)), dim3(WAVE), c.n,
          (const int32_t*)c.child_start, (const T*)h->lv[L - 1].t, (const T*)nullptr, omega, (T*)c.b, (T*)nullptr);
-  launch(h, CDGMG_K_COARSE, k_dense_gemv<T>, dim3(grid_for(h->nd * WAVE)), dim3(TPB), h->nd, ainv<T>(h),
-         (const T*)c.b, xs[L]);
+  launch(h, CDGMG_K_COARSE, k_dense_gemv<T>, dim3(grid_for(h->nd * WAVE)), dim3(TPB), h->nd, h->ld,
+         (const T*)h->AinvP, (const T*)c.b, xs[L]);
   for (int l = L - 1; l >= 0; --l) {
     DLevel& d = h->lv[l];
     const int tpb = row_tpb(h, l);
     launch(h, CDGMG_K_PROLONG, k_prolong<T, NP>, dim3(grid_for(d.n, tpb)), dim3(tpb), d.n, (const int32_t*)d.parent,
            (const T*)d.Lm, (const T*)xs[l + 1], xs[l]);
-    smooth_sweeps<T, NP>(h, l, nu2, &xs[l], &xbs[l]);
+    smooth_sweeps<T, NP>(h, l, nu2, &xs[l], &xbs[l], l == 0 ? dv : nullptr);
   }
-  launch(h, CDGMG_K_VECTOR, k_cast<T, double>, dim3(grid_for(h->N0 * NP)), dim3(TPB), h->N0 * NP,
-         (const T*)xs[0], z64);
+  if (dv) {
+    if (nu2 > 0)
+      *nparts = (int)h->lv[0].ns;
+    else
+      dot_t<T>(h, xs[0], dv, nparts);
+  }
+  return xs[0];
 }
 
-void vcycle(cdgmg_handle* h, const double* r64, double* z64) {
+// z = B r; returns z in the multigrid precision
+void* vcycle(cdgmg_handle* h, const double* r64, const double* dv, int* nparts) {
+  void* z = nullptr;
   if (h->o.mg_precision == CDGMG_MG_FP32) {
-    NP_DISPATCH(h->np, vcycle_t<float, NP>(h, r64, z64));
+    NP_DISPATCH(h->np, z = vcycle_t<float, NP>(h, r64, dv, nparts));
   } else {
-    NP_DISPATCH(h->np, vcycle_t<double, NP>(h, r64, z64));
+    NP_DISPATCH(h->np, z = vcycle_t<double, NP>(h, r64, dv, nparts));
   }
+  return z;
+}
+
+// z64 = B r in FP64 (C ABI)
+void vcycle64(cdgmg_handle* h, const double* r64, double* z64) {
+  void* z = vcycle(h, r64, nullptr, nullptr);
+  const int64_t m = h->N0 * h->np;
+  if (h->o.mg_precision == CDGMG_MG_FP32)
+    launch(h, CDGMG_K_VECTOR, k_cast<float, double>, dim3(grid_for(m)), dim3(TPB), m, (const float*)z, z64);
+  else
+    launch(h, CDGMG_K_VECTOR, k_cast<double, double>, dim3(grid_for(m)), dim3(TPB), m, (const double*)z, z64);
 }
 
 // ---------------------------------------------------------------- outer solve
@@ -722,20 +781,22 @@ int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
   } else {
     const bool fcg = h->o.outer == CDGMG_OUTER_FCG;
     while (it < h->o.max_iter) {
-      vcycle(h, h->r, h->z);
-      if (fcg) {
-        if (it > 0) {
-          dot_into(h, m, h->z, h->q, SC_ZQ);
-          launch(h, CDGMG_K_VECTOR, k_scalars, dim3(1), dim3(1), h->scal, 0);
-        }
-        launch(h, CDGMG_K_VECTOR, k_update_p, dim3(grid_for(m)), dim3(TPB), m, (const double*)h->z, h->p,
-               (const double*)h->scal, -1.0, it == 0 ? 1 : 0);
-      } else {
-        dot_into(h, m, h->z, h->r, SC_ZR);
-        if (it > 0) launch(h, CDGMG_K_VECTOR, k_scalars, dim3(1), dim3(1), h->scal, 1);
-        launch(h, CDGMG_K_VECTOR, k_update_p, dim3(grid_for(m)), dim3(TPB), m, (const double*)h->z, h->p,
-               (const double*)h->scal, 1.0, it == 0 ? 1 : 0);
-      }
+      // z = B r stays in the multigrid precision; its dot with q (FCG) or r
+      // (PCG) comes fused with the last level-0 sweep
+      int nz = 0;
+      const double* dv = fcg ? (it > 0 ? h->q : nullptr) : h->r;
+      void* z = vcycle(h, h->r, dv, &nz);
+      if (dv) launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, nz, 1, h->scal,
+                     fcg ? (int)SC_ZQ : (int)SC_ZR);
+      if (fcg && it > 0) launch(h, CDGMG_K_VECTOR, k_scalars, dim3(1), dim3(1), h->scal, 0);
+      if (!fcg && it > 0) launch(h, CDGMG_K_VECTOR, k_scalars, dim3(1), dim3(1), h->scal, 1);
+      const double sign = fcg ? -1.0 : 1.0;
+      if (h->o.mg_precision == CDGMG_MG_FP32)
+        launch(h, CDGMG_K_VECTOR, k_update_p<float>, dim3(grid_for(m)), dim3(TPB), m, (const float*)z, h->p,
+               (const double*)h->scal, sign, it == 0 ? 1 : 0);
+      else
+        launch(h, CDGMG_K_VECTOR, k_update_p<double>, dim3(grid_for(m)), dim3(TPB), m, (const double*)z, h->p,
+               (const double*)h->scal, sign, it == 0 ? 1 : 0);
       const unsigned g = (unsigned)d0.ns;
       if (accurate) {
         NP_DISPATCH(np, H_DISPATCH(h->H0, if constexpr (NP % H == 0) launch(
@@ -1011,8 +1072,9 @@ int cdgmg_apply_A(cdgmg_handle* h, int level, int precision, const void* x_dev, 
     double *xi = h->t1, *yi = h->t2;
     launch(h, -1, k_permute<double>, dim3(grid_for(d.n * np)), dim3(TPB), d.n, np, (const int32_t*)d.perm,
            (const double*)x_dev, xi, 0);
-    NP_DISPATCH(np, launch(h, -1, k_spmv<double, double, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n, (const int32_t*)d.cols,
-                           (const int64_t*)d.sblk, (const double*)d.A64, (const double*)xi, yi));
+    NP_DISPATCH(np, launch(h, -1, k_spmv<double, double, NP>, dim3(grid_for(d.n)), dim3(TPB), d.n,
+                           (const int32_t*)d.cols, (const int64_t*)d.sblk, (const double*)d.A64, (const double*)xi,
+                           yi));
     launch(h, -1, k_permute<double>, dim3(grid_for(d.n * np)), dim3(TPB), d.n, np, (const int32_t*)d.perm,
            (const double*)yi, (double*)y_dev, 1);
   } else {
@@ -1035,7 +1097,7 @@ int cdgmg_vcycle(cdgmg_handle* h, const double* r_dev, double* z_dev) {
   const int np = h->np;
   launch(h, -1, k_permute<double>, dim3(grid_for(h->N0 * np)), dim3(TPB), h->N0, np, (const int32_t*)d.perm,
          r_dev, h->t1, 0);
-  vcycle(h, h->t1, h->t2);
+  vcycle64(h, h->t1, h->t2);
   launch(h, -1, k_permute<double>, dim3(grid_for(h->N0 * np)), dim3(TPB), h->N0, np, (const int32_t*)d.perm,
          (const double*)h->t2, z_dev, 1);
   HIPCHK(hipGetLastError());
