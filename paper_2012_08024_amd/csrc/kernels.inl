@@ -364,25 +364,28 @@ __global__ void k_pad_cast(int64_t n, int64_t ld, const S* __restrict__ src, D* 
 //
 // Level 0 (component-split): H wavefronts per 64-row slice, wavefront h owns
 // output components [h NI, (h+1) NI), NI = n_p / H (H = 1 is one thread per
-// row).  Off-diagonal blocks use the sliced layout with W_s - 1 slots per
-// slice: block (r, w') at ((sblk[s] - 64 s + 64 w') n_p^2 + (i n_p + j) 64 + lane),
-// its column at cols[sblk[s] + 64 (w' + 1) + lane].
-template <typename T, int NP, int H>
+// row).  Every level-0 slice has the n_f + 1 slots of the element's facets
+// (zero blocks where a facet has no neighbour), so the slot loops are unrolled
+// and the column indices of all slots are loaded first.  Off-diagonal blocks:
+// block (r, w') at ((64 n_f s + 64 w') n_p^2 + (i n_p + j) 64 + lane), its
+// column at cols[64 (n_f + 1) s + 64 (w' + 1) + lane].
+template <typename T, int NP, int H, int NF>
 __device__ __forceinline__ void hs_scaled_residual(int64_t r, int lane, int h, const int32_t* __restrict__ cols,
-                                                   const int64_t* __restrict__ sblk, const T* __restrict__ At,
-                                                   const T* __restrict__ bt, const T* __restrict__ x, T* acc) {
+                                                   const T* __restrict__ At, const T* __restrict__ bt,
+                                                   const T* __restrict__ x, T* acc) {
   constexpr int NP2 = NP * NP, NI = NP / H;
   const int64_t s = r / WAVE;
-  const int64_t B = sblk[s];
-  const int Wo = (int)((sblk[s + 1] - B) / WAVE) - 1;
-  const int64_t Bo = B - WAVE * s;
+  const int64_t B = s * WAVE * (NF + 1), Bo = s * WAVE * NF;
+  int32_t c[NF];
+#pragma unroll
+  for (int w = 0; w < NF; ++w) c[w] = cols[B + (int64_t)WAVE * (w + 1) + lane];
 #pragma unroll
   for (int t = 0; t < NI; ++t) acc[t] = bt[r * NP + h * NI + t] - x[r * NP + h * NI + t];
-  for (int w = 0; w < Wo; ++w) {
-    const int32_t c = cols[B + (int64_t)WAVE * (w + 1) + lane];
+#pragma unroll
+  for (int w = 0; w < NF; ++w) {
     T xv[NP];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) xv[j] = x[(int64_t)c * NP + j];
+    for (int j = 0; j < NP; ++j) xv[j] = x[(int64_t)c[w] * NP + j];
     const T* Ab = At + (Bo + (int64_t)WAVE * w) * NP2 + (int64_t)h * NI * NP * WAVE + lane;
 #pragma unroll
     for (int t = 0; t < NI; ++t)
@@ -393,9 +396,8 @@ __device__ __forceinline__ void hs_scaled_residual(int64_t r, int lane, int h, c
 
 // sweep on level 0; with DOT, also the slice's partial sum of (xout, dv) in
 // FP64 (part[slice]), which the outer loop needs of the preconditioned residual
-template <typename T, int NP, int H, bool DOT>
-__global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* __restrict__ cols,
-                                                     const int64_t* __restrict__ sblk, const T* __restrict__ At,
+template <typename T, int NP, int H, int NF, bool DOT>
+__global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* __restrict__ cols, const T* __restrict__ At,
                                                      const T* __restrict__ bt, const T* __restrict__ xin, T omega,
                                                      T* __restrict__ xout, const double* __restrict__ dv,
                                                      double* __restrict__ part) {
@@ -405,7 +407,7 @@ __global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* _
   double d = 0.0;
   if (r < n) {
     T acc[NI];
-    hs_scaled_residual<T, NP, H>(r, lane, h, cols, sblk, At, bt, xin, acc);
+    hs_scaled_residual<T, NP, H, NF>(r, lane, h, cols, At, bt, xin, acc);
 #pragma unroll
     for (int t = 0; t < NI; ++t) {
       const int64_t k = r * NP + h * NI + t;
@@ -422,9 +424,8 @@ __global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* _
 }
 
 // residual + restriction on level 0: t_e = Lt_e^T (bt - At x)_e
-template <typename T, int NP, int H>
-__global__ __launch_bounds__(WAVE * H) void k_restrict0(int64_t n, const int32_t* __restrict__ cols,
-                                                        const int64_t* __restrict__ sblk, const T* __restrict__ At,
+template <typename T, int NP, int H, int NF>
+__global__ __launch_bounds__(WAVE * H) void k_restrict0(int64_t n, const int32_t* __restrict__ cols, const T* __restrict__ At,
                                                         const T* __restrict__ bt, const T* __restrict__ x,
                                                         const T* __restrict__ Lt, T* __restrict__ t_out) {
   constexpr int NP2 = NP * NP, NI = NP / H;
@@ -434,7 +435,7 @@ __global__ __launch_bounds__(WAVE * H) void k_restrict0(int64_t n, const int32_t
   const bool valid = r < n;
   if (valid) {
     T acc[NI];
-    hs_scaled_residual<T, NP, H>(r, lane, h, cols, sblk, At, bt, x, acc);
+    hs_scaled_residual<T, NP, H, NF>(r, lane, h, cols, At, bt, x, acc);
 #pragma unroll
     for (int t = 0; t < NI; ++t) sres[h * NI + t][lane] = acc[t];
   }
@@ -821,12 +822,12 @@ __global__ __launch_bounds__(TPB) void k_update_xr2(int64_t m, const double* __r
   if (threadIdx.x == 0) part[blockIdx.x] = rr;
 }
 
-// Component-split outer kernels (H wavefronts per slice, as k_smooth_hs):
-// q = A p with partial sums of (p, q), (p, r); COMP selects the compensated
-// (Dot2) accumulation.  One partial per slice.
-template <int NP, int H, bool COMP>
+// Component-split outer kernels on A_0 (H wavefronts per slice, the n_f + 1
+// slots unrolled as in the level-0 sweep): q = A p with partial sums of
+// (p, q), (p, r); COMP selects the compensated (Dot2) accumulation.  One
+// partial per slice.
+template <int NP, int H, int NF, bool COMP>
 __global__ __launch_bounds__(WAVE * H) void k_spmv_dots_hs(int64_t n, const int32_t* __restrict__ cols,
-                                                           const int64_t* __restrict__ sblk,
                                                            const double* __restrict__ A, const double* __restrict__ p,
                                                            const double* __restrict__ rr, double* __restrict__ q,
                                                            double* __restrict__ part) {
@@ -837,13 +838,17 @@ __global__ __launch_bounds__(WAVE * H) void k_spmv_dots_hs(int64_t n, const int3
   const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
   double pq = 0.0, pr = 0.0;
   if (r < n) {
-    const int64_t B = sblk[r / WAVE];
-    const int W = (int)((sblk[r / WAVE + 1] - B) / WAVE);
+    constexpr int W = NF + 1;
+    const int64_t B = (r / WAVE) * WAVE * W;
+    int32_t cw[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) cw[w] = cols[B + (int64_t)WAVE * w + lane];
     double s[NI], c[NI];
 #pragma unroll
     for (int t = 0; t < NI; ++t) s[t] = c[t] = 0.0;
+#pragma unroll
     for (int w = 0; w < W; ++w) {
-      const int32_t col = cols[B + (int64_t)WAVE * w + lane];
+      const int32_t col = cw[w];
       double xv[NP];
 #pragma unroll
       for (int j = 0; j < NP; ++j) xv[j] = p[(int64_t)col * NP + j];
@@ -875,9 +880,8 @@ __global__ __launch_bounds__(WAVE * H) void k_spmv_dots_hs(int64_t n, const int3
 }
 
 // true residual rt = b - A (xh + xl), compensated, component-split; partial ||rt||^2 per slice
-template <int NP, int H>
+template <int NP, int H, int NF>
 __global__ __launch_bounds__(WAVE * H) void k_residual2_hs(int64_t n, const int32_t* __restrict__ cols,
-                                                           const int64_t* __restrict__ sblk,
                                                            const double* __restrict__ A, const double* __restrict__ b,
                                                            const double* __restrict__ xh,
                                                            const double* __restrict__ xl, double* __restrict__ rt,
@@ -889,16 +893,20 @@ __global__ __launch_bounds__(WAVE * H) void k_residual2_hs(int64_t n, const int3
   const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
   double rr = 0.0;
   if (r < n) {
-    const int64_t B = sblk[r / WAVE];
-    const int W = (int)((sblk[r / WAVE + 1] - B) / WAVE);
+    constexpr int W = NF + 1;
+    const int64_t B = (r / WAVE) * WAVE * W;
+    int32_t cw[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) cw[w] = cols[B + (int64_t)WAVE * w + lane];
     double s[NI], c[NI];
 #pragma unroll
     for (int t = 0; t < NI; ++t) {
       s[t] = b[r * NP + h * NI + t];
       c[t] = 0.0;
     }
+#pragma unroll
     for (int w = 0; w < W; ++w) {
-      const int32_t col = cols[B + (int64_t)WAVE * w + lane];
+      const int32_t col = cw[w];
       double hv[NP], lv[NP];
 #pragma unroll
       for (int j = 0; j < NP; ++j) {

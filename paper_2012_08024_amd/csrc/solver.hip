@@ -52,6 +52,24 @@ using namespace cdg;
     default: break;                                        \
   }
 
+// level-0 kernels: facets per element n_f (3 in 2D, 4 in 3D) and the
+// wavefront split H; only the n_p of the element's dimension are instantiated
+constexpr bool l0_pair(int np, int nf) {
+  return nf == 3 ? (np == 3 || np == 6 || np == 10) : (np == 4 || np == 10 || np == 20);
+}
+#define L0_DISPATCH(hh, ...)                                                                                \
+  switch ((hh)->P.nf) {                                                                                     \
+    case 3: {                                                                                               \
+      constexpr int NF = 3;                                                                                 \
+      H_DISPATCH((hh)->H0, if constexpr (NP % H == 0 && l0_pair(NP, NF)) { __VA_ARGS__; });                \
+    } break;                                                                                                \
+    case 4: {                                                                                               \
+      constexpr int NF = 4;                                                                                 \
+      H_DISPATCH((hh)->H0, if constexpr (NP % H == 0 && l0_pair(NP, NF)) { __VA_ARGS__; });                \
+    } break;                                                                                                \
+    default: break;                                                                                         \
+  }
+
 // lanes per row of the coarse-level kernels
 #define G_DISPATCH(gv, ...)                                  \
   switch (gv) {                                              \
@@ -558,10 +576,11 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev) {
 }
 
 // ---------------------------------------------------------------- V-cycle
-// wavefronts per 64-row slice of the level-0 kernels: 0 picks by n_p (the
-// n_p = 10, 20 blocks need the split to keep enough loads in flight)
+// wavefronts per 64-row slice of the level-0 kernels: 0 picks by n_p (one
+// wavefront per slice up to n_p = 10; the n_p = 20 blocks are split in four
+// to keep the register state of a lane small)
 int pick_h0(int np, int variant) {
-  if (variant == 0) return (np % 4 == 0 && np >= 20) ? 4 : ((np % 2 == 0 && np >= 6) ? 2 : 1);
+  if (variant == 0) return np >= 20 ? 4 : 1;
   if ((variant == 1 || variant == 2 || variant == 4 || variant == 5) && np % variant == 0) return variant;
   return 0;
 }
@@ -578,15 +597,13 @@ void smooth_sweeps(cdgmg_handle* h, int l, int count, T** x, T** xb, const doubl
     if (l == 0) {
       const bool dot = dv && s == count - 1;
       if (dot) {
-        H_DISPATCH(h->H0, if constexpr (NP % H == 0) launch(
-                              h, cls, k_sweep0<T, NP, H, true>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
-                              (const int32_t*)d.cols, (const int64_t*)d.sblk, (const T*)d.At, (const T*)d.b,
-                              (const T*)*x, omega, *xb, dv, h->part));
+        L0_DISPATCH(h, launch(h, cls, k_sweep0<T, NP, H, NF, true>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
+                              (const int32_t*)d.cols, (const T*)d.At, (const T*)d.b, (const T*)*x, omega, *xb, dv,
+                              h->part));
       } else {
-        H_DISPATCH(h->H0, if constexpr (NP % H == 0) launch(
-                              h, cls, k_sweep0<T, NP, H, false>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
-                              (const int32_t*)d.cols, (const int64_t*)d.sblk, (const T*)d.At, (const T*)d.b,
-                              (const T*)*x, omega, *xb, (const double*)nullptr, (double*)nullptr));
+        L0_DISPATCH(h, launch(h, cls, k_sweep0<T, NP, H, NF, false>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
+                              (const int32_t*)d.cols, (const T*)d.At, (const T*)d.b, (const T*)*x, omega, *xb,
+                              (const double*)nullptr, (double*)nullptr));
       }
     } else {
       G_DISPATCH(d.grp_s, launch(h, cls, k_sweep_grp<T, NP, G>, dim3(grid_for(d.n * G)), dim3(TPB), d.n,
@@ -647,11 +664,9 @@ T* vcycle_t(cdgmg_handle* h, const double* r64, const double* dv, int* nparts) {
     }
     smooth_sweeps<T, NP>(h, l, nu1 > 1 ? nu1 - 1 : 0, &xs[l], &xbs[l]);
     if (l == 0) {
-      H_DISPATCH(h->H0, if constexpr (NP % H == 0) launch(h, CDGMG_K_RESTRICT, k_restrict0<T, NP, H>,
-                                                          dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
-                                                          (const int32_t*)d.cols, (const int64_t*)d.sblk,
-                                                          (const T*)d.At, (const T*)d.b, (const T*)xs[0],
-                                                          (const T*)d.Lt, (T*)d.t));
+      L0_DISPATCH(h, launch(h, CDGMG_K_RESTRICT, k_restrict0<T, NP, H, NF>, dim3((unsigned)d.ns), dim3(WAVE * H),
+                            d.n, (const int32_t*)d.cols, (const T*)d.At, (const T*)d.b, (const T*)xs[0],
+                            (const T*)d.Lt, (T*)d.t));
     } else {
       G_DISPATCH(d.grp_r, launch(h, CDGMG_K_RESTRICT, k_restrict_grp<T, NP, G>, dim3(grid_for(d.n * G)), dim3(TPB),
                              d.n, (const int32_t*)d.wcols, (const int64_t*)d.woff, (const T*)d.R, (const T*)d.b,
@@ -719,12 +734,10 @@ int read_scalar(cdgmg_handle* h, int slot, double* out) {
 // recursive residual is replaced by it); returns ||r||^2
 int true_residual(cdgmg_handle* h, double* rr) {
   DLevel& d = h->lv[0];
-  NP_DISPATCH(h->np, H_DISPATCH(h->H0, if constexpr (NP % H == 0) launch(h, CDGMG_K_VECTOR, k_residual2_hs<NP, H>,
-                                                                       dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
-                                                                       (const int32_t*)d.cols, (const int64_t*)d.sblk,
-                                                                       (const double*)d.A64, (const double*)h->b,
-                                                                       (const double*)h->x, (const double*)h->xl,
-                                                                       h->r, h->part)));
+  NP_DISPATCH(h->np, L0_DISPATCH(h, launch(h, CDGMG_K_VECTOR, k_residual2_hs<NP, H, NF>, dim3((unsigned)d.ns),
+                                            dim3(WAVE * H), d.n, (const int32_t*)d.cols, (const double*)d.A64,
+                                            (const double*)h->b, (const double*)h->x, (const double*)h->xl, h->r,
+                                            h->part)));
   launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)d.ns, 1, h->scal, SC_TMP);
   return read_scalar(h, SC_TMP, rr);
 }
@@ -799,17 +812,13 @@ int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
                (const double*)h->scal, sign, it == 0 ? 1 : 0);
       const unsigned g = (unsigned)d0.ns;
       if (accurate) {
-        NP_DISPATCH(np, H_DISPATCH(h->H0, if constexpr (NP % H == 0) launch(
-                                              h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, true>, dim3(g), dim3(WAVE * H),
-                                              d0.n, (const int32_t*)d0.cols, (const int64_t*)d0.sblk,
-                                              (const double*)d0.A64, (const double*)h->p, (const double*)h->r, h->q,
-                                              h->part)));
+        NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, NF, true>, dim3(g),
+                                              dim3(WAVE * H), d0.n, (const int32_t*)d0.cols, (const double*)d0.A64,
+                                              (const double*)h->p, (const double*)h->r, h->q, h->part)));
       } else {
-        NP_DISPATCH(np, H_DISPATCH(h->H0, if constexpr (NP % H == 0) launch(
-                                              h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, false>, dim3(g), dim3(WAVE * H),
-                                              d0.n, (const int32_t*)d0.cols, (const int64_t*)d0.sblk,
-                                              (const double*)d0.A64, (const double*)h->p, (const double*)h->r, h->q,
-                                              h->part)));
+        NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, NF, false>, dim3(g),
+                                              dim3(WAVE * H), d0.n, (const int32_t*)d0.cols, (const double*)d0.A64,
+                                              (const double*)h->p, (const double*)h->r, h->q, h->part)));
       }
       launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)g, 2, h->scal, SC_PQ);
       launch(h, CDGMG_K_VECTOR, k_scalars, dim3(1), dim3(1), h->scal, fcg ? 2 : 3);
