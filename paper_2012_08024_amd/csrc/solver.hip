@@ -149,6 +149,7 @@ struct cdgmg_handle {
   int* err = nullptr;
   double* hscal = nullptr;
   int* herr = nullptr;
+  hipEvent_t ev_rr = nullptr;  // ||r||^2 of the last update copied to hscal
   // profiling
   std::vector<ProfEv> evs;
   std::vector<hipEvent_t> pool;
@@ -731,14 +732,18 @@ int read_scalar(cdgmg_handle* h, int slot, double* out) {
 }
 
 // compensated true residual r = b - A (x_hi + x_lo), written into h->r (the
-// recursive residual is replaced by it); returns ||r||^2
-int true_residual(cdgmg_handle* h, double* rr) {
+// recursive residual is replaced by it); ||r||^2 lands in scal[SC_TMP]
+void enqueue_true_residual(cdgmg_handle* h) {
   DLevel& d = h->lv[0];
   NP_DISPATCH(h->np, L0_DISPATCH(h, launch(h, CDGMG_K_VECTOR, k_residual2_hs<NP, H, NF>, dim3((unsigned)d.ns),
                                             dim3(WAVE * H), d.n, (const int32_t*)d.cols, (const double*)d.A64,
                                             (const double*)h->b, (const double*)h->x, (const double*)h->xl, h->r,
                                             h->part)));
   launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)d.ns, 1, h->scal, SC_TMP);
+}
+
+int true_residual(cdgmg_handle* h, double* rr) {
+  enqueue_true_residual(h);
   return read_scalar(h, SC_TMP, rr);
 }
 
@@ -764,7 +769,16 @@ void collect_profile(cdgmg_handle* h, cdgmg_solve_info* info) {
   }
 }
 
-// solve A x = b with h->b set (internal order); result in h->x
+// solve A x = b with h->b set (internal order); result in x_hi + x_lo.
+//
+// One iteration is the V-cycle z = B r followed by the Krylov update (the dot
+// of z, the new direction p, q = A p, x and r).  The host needs ||r||^2 after
+// each update; the V-cycle of the next iteration is enqueued before the host
+// waits for it, so the device does not idle during the round trip.  That
+// V-cycle reads r, so a reliable update (r replaced by the compensated true
+// residual once ||r|| dropped 100x) is applied after the following update,
+// before the next V-cycle is enqueued.  Convergence is accepted on the true
+// residual only, at the same iteration as without the look-ahead.
 int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
   auto t0 = std::chrono::steady_clock::now();
   const int64_t m = h->N0 * h->np;
@@ -780,76 +794,111 @@ int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
     set_error("solve: right-hand side is not finite");
     return CDGMG_ERR_NAN;
   }
+  if (!h->ev_rr) HIPCHK(hipEventCreateWithFlags(&h->ev_rr, hipEventDisableTiming));
   const double nb = std::sqrt(bb);
+  const double tol = h->o.tol;
+  const bool fcg = h->o.outer == CDGMG_OUTER_FCG;
   int it = 0;
-  double rel = 0.0, rel_true = 0.0;
+  double rel = 0.0, rel_prev = 0.0, rel_true = 0.0;
   int status = CDGMG_NOT_CONVERGED;
   double rho_last = nb;
   // near the tolerance the rounding of a plain FP64 q = A p (about
   // eps |A| |alpha p| per step) would make the recursive residual drift from
   // the true one; from rel <= 1e4 tol on, q is accumulated compensated
   bool accurate = false;
+  bool replace_pending = false;
+  void* z = nullptr;
+  int nz = 0;
+  bool zdot = false;
+  // V-cycle of iteration `iter` on the current r (its dot with q or r fused)
+  auto enqueue_vcycle = [&](int iter) {
+    const double* dv = fcg ? (iter > 0 ? h->q : nullptr) : h->r;
+    z = vcycle(h, h->r, dv, &nz);
+    zdot = dv != nullptr;
+  };
+  // the Krylov update of iteration `iter` after its V-cycle; ||r||^2 -> SC_RR
+  auto enqueue_update = [&](int iter) {
+    if (zdot)
+      launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, nz, 1, h->scal,
+             fcg ? (int)SC_ZQ : (int)SC_ZR);
+    if (iter > 0) launch(h, CDGMG_K_VECTOR, k_scalars, dim3(1), dim3(1), h->scal, fcg ? 0 : 1);
+    const double sign = fcg ? -1.0 : 1.0;
+    if (h->o.mg_precision == CDGMG_MG_FP32)
+      launch(h, CDGMG_K_VECTOR, k_update_p<float>, dim3(grid_for(m)), dim3(TPB), m, (const float*)z, h->p,
+             (const double*)h->scal, sign, iter == 0 ? 1 : 0);
+    else
+      launch(h, CDGMG_K_VECTOR, k_update_p<double>, dim3(grid_for(m)), dim3(TPB), m, (const double*)z, h->p,
+             (const double*)h->scal, sign, iter == 0 ? 1 : 0);
+    const unsigned g = (unsigned)d0.ns;
+    if (accurate) {
+      NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, NF, true>, dim3(g),
+                                            dim3(WAVE * H), d0.n, (const int32_t*)d0.cols, (const double*)d0.A64,
+                                            (const double*)h->p, (const double*)h->r, h->q, h->part)));
+    } else {
+      NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, NF, false>, dim3(g),
+                                            dim3(WAVE * H), d0.n, (const int32_t*)d0.cols, (const double*)d0.A64,
+                                            (const double*)h->p, (const double*)h->r, h->q, h->part)));
+    }
+    launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)g, 2, h->scal, SC_PQ);
+    launch(h, CDGMG_K_VECTOR, k_scalars, dim3(1), dim3(1), h->scal, fcg ? 2 : 3);
+    const unsigned gu = std::min<unsigned>(1024, grid_for(m));
+    launch(h, CDGMG_K_VECTOR, k_update_xr2, dim3(gu), dim3(TPB), m, (const double*)h->p, (const double*)h->q, h->x,
+           h->xl, h->r, (const double*)h->scal, h->part);
+    launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)gu, 1, h->scal, SC_RR);
+  };
   if (nb == 0.0) {
     status = CDGMG_OK;
   } else {
-    const bool fcg = h->o.outer == CDGMG_OUTER_FCG;
+    enqueue_vcycle(0);
     while (it < h->o.max_iter) {
-      // z = B r stays in the multigrid precision; its dot with q (FCG) or r
-      // (PCG) comes fused with the last level-0 sweep
-      int nz = 0;
-      const double* dv = fcg ? (it > 0 ? h->q : nullptr) : h->r;
-      void* z = vcycle(h, h->r, dv, &nz);
-      if (dv) launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, nz, 1, h->scal,
-                     fcg ? (int)SC_ZQ : (int)SC_ZR);
-      if (fcg && it > 0) launch(h, CDGMG_K_VECTOR, k_scalars, dim3(1), dim3(1), h->scal, 0);
-      if (!fcg && it > 0) launch(h, CDGMG_K_VECTOR, k_scalars, dim3(1), dim3(1), h->scal, 1);
-      const double sign = fcg ? -1.0 : 1.0;
-      if (h->o.mg_precision == CDGMG_MG_FP32)
-        launch(h, CDGMG_K_VECTOR, k_update_p<float>, dim3(grid_for(m)), dim3(TPB), m, (const float*)z, h->p,
-               (const double*)h->scal, sign, it == 0 ? 1 : 0);
-      else
-        launch(h, CDGMG_K_VECTOR, k_update_p<double>, dim3(grid_for(m)), dim3(TPB), m, (const double*)z, h->p,
-               (const double*)h->scal, sign, it == 0 ? 1 : 0);
-      const unsigned g = (unsigned)d0.ns;
-      if (accurate) {
-        NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, NF, true>, dim3(g),
-                                              dim3(WAVE * H), d0.n, (const int32_t*)d0.cols, (const double*)d0.A64,
-                                              (const double*)h->p, (const double*)h->r, h->q, h->part)));
-      } else {
-        NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, NF, false>, dim3(g),
-                                              dim3(WAVE * H), d0.n, (const int32_t*)d0.cols, (const double*)d0.A64,
-                                              (const double*)h->p, (const double*)h->r, h->q, h->part)));
-      }
-      launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)g, 2, h->scal, SC_PQ);
-      launch(h, CDGMG_K_VECTOR, k_scalars, dim3(1), dim3(1), h->scal, fcg ? 2 : 3);
-      const unsigned gu = std::min<unsigned>(1024, grid_for(m));
-      launch(h, CDGMG_K_VECTOR, k_update_xr2, dim3(gu), dim3(TPB), m, (const double*)h->p, (const double*)h->q,
-             h->x, h->xl, h->r, (const double*)h->scal, h->part);
-      launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)gu, 1, h->scal, SC_RR);
-      double rr;
-      RETURN_IF(read_scalar(h, SC_RR, &rr));
+      enqueue_update(it);
+      const bool replaced = replace_pending;
+      if (replaced) enqueue_true_residual(h);
+      replace_pending = false;
+      HIPCHK(hipMemcpyAsync(h->hscal, h->scal, SC_N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipEventRecord(h->ev_rr, h->stream));
+      // look ahead unless this update is expected to converge (the last
+      // reduction factor applied once more reaches the tolerance)
+      const bool expect_done = it >= 2 && rel_prev > 0.0 && rel * (rel / rel_prev) <= tol;
+      const bool ahead = it + 1 < h->o.max_iter && !expect_done;
+      if (ahead) enqueue_vcycle(it + 1);
+      HIPCHK(hipEventSynchronize(h->ev_rr));
+      const double rr = h->hscal[SC_RR];
+      const double rt = replaced ? h->hscal[SC_TMP] : 0.0;
       ++it;
-      if (!std::isfinite(rr)) {
+      if (!std::isfinite(rr) || !std::isfinite(rt)) {
         set_error("solve: residual is not finite");
         status = CDGMG_ERR_NAN;
         break;
       }
+      rel_prev = rel;
       rel = std::sqrt(rr) / nb;
-      if (rel <= 1e4 * h->o.tol) accurate = true;
+      if (rel <= 1e4 * tol) accurate = true;
       if (info && info->history && it <= info->history_len) info->history[it - 1] = rel;
-      // reliable updates: the recursive residual is replaced by the compensated
-      // true residual whenever it has dropped 100x since the last replacement,
-      // and before convergence is accepted
-      if (rel <= h->o.tol || std::sqrt(rr) <= 1e-2 * rho_last) {
-        double rt;
-        RETURN_IF(true_residual(h, &rt));
+      bool stale = false;  // the enqueued look-ahead V-cycle read an r that is replaced now
+      if (replaced) {
         rel_true = std::sqrt(rt) / nb;
         rho_last = std::sqrt(rt);
-        if (rel_true <= h->o.tol) {
+        if (rel_true <= tol) {
           status = CDGMG_OK;
           break;
         }
       }
+      if (rel <= tol) {
+        // convergence is accepted on the compensated true residual
+        double rt2;
+        RETURN_IF(true_residual(h, &rt2));
+        rel_true = std::sqrt(rt2) / nb;
+        rho_last = std::sqrt(rt2);
+        if (rel_true <= tol) {
+          status = CDGMG_OK;
+          break;
+        }
+        stale = true;
+      } else if (std::sqrt(rr) <= 1e-2 * rho_last) {
+        replace_pending = true;
+      }
+      if (it < h->o.max_iter && (!ahead || stale)) enqueue_vcycle(it);
     }
   }
   if (status != CDGMG_OK && status != CDGMG_ERR_NAN && nb != 0.0) {
@@ -1191,6 +1240,7 @@ int cdgmg_destroy(cdgmg_handle* h) {
   if (h->stream || !h->allocs.empty()) (void)hipStreamSynchronize(h->stream);
   for (void* p : h->allocs) (void)hipFree(p);
   for (auto e : h->pool) (void)hipEventDestroy(e);
+  if (h->ev_rr) (void)hipEventDestroy(h->ev_rr);
   if (h->hscal) (void)hipHostFree(h->hscal);
   if (h->herr) (void)hipHostFree(h->herr);
   delete h;
