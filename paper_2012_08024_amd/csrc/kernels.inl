@@ -214,39 +214,164 @@ __global__ void k_block_inverse_bm(int64_t n, const double* __restrict__ src, do
 }
 
 // coarsest level: scatter the sliced blocks into a dense row-major matrix
+// dense[(r n_p + i) ld + c n_p + j] += A(r, c)_{ij} over the stored blocks
 template <int NP>
-__global__ void k_dense_scatter(int64_t n, const int32_t* __restrict__ cols, const int64_t* __restrict__ sblk,
-                                const double* __restrict__ A, double* __restrict__ dense) {
+__global__ void k_dense_scatter(int64_t n, int64_t ld, const int32_t* __restrict__ cols,
+                                const int64_t* __restrict__ sblk, const double* __restrict__ A,
+                                double* __restrict__ dense) {
   constexpr int NP2 = NP * NP;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   const int lane = (int)(r % WAVE);
   const int64_t B = sblk[r / WAVE];
   const int W = (int)((sblk[r / WAVE + 1] - B) / WAVE);
-  const int64_t nd = n * NP;
   for (int w = 0; w < W; ++w) {
     const int32_t c = cols[B + (int64_t)WAVE * w + lane];
     for (int i = 0; i < NP; ++i)
       for (int j = 0; j < NP; ++j)
-        dense[(r * NP + i) * nd + (int64_t)c * NP + j] += A[blk_off(B, w, NP2, i * NP + j, lane)];
+        dense[(r * NP + i) * ld + (int64_t)c * NP + j] += A[blk_off(B, w, NP2, i * NP + j, lane)];
   }
 }
 
-// one Gauss-Jordan step of the in-place inverse (out-of-place between two buffers)
-__global__ void k_gj_step(int64_t n, int64_t k, const double* __restrict__ in, double* __restrict__ out,
-                          int* __restrict__ err, int definite) {
+// ------------------------------------------------- coarsest inverse (setup)
+// Blocked Gauss-Jordan inversion in place, without pivoting (the coarsest
+// Galerkin operator is SPD; a flux-coarsened one is only checked for nonzero
+// pivots), on an ld x ld matrix, ld a multiple of GJB, whose padding is the
+// identity.  For each diagonal block K, with P = A_KK^{-1}:
+//   A_KJ <- P A_KJ (J != K);  A_IJ <- A_IJ - A_IK A_KJ (I, J != K);
+//   A_IK <- -A_IK P (I != K);  A_KK <- P.
+constexpr int GJB = 64;
+
+// dense <- 0 with ones on the padding diagonal (i = j >= nd)
+__global__ void k_dense_init(int64_t nd, int64_t ld, double* __restrict__ dense) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n * n) return;
-  const int64_t i = idx / n, j = idx % n;
-  const double p = in[k * n + k];
-  if (idx == 0 && (definite ? !(p > 0.0) : !(p != 0.0))) *err = 1;
-  const double rk = (j == k) ? 1.0 : in[k * n + j];
-  if (i == k) {
-    out[idx] = rk / p;
-  } else {
-    const double v = (j == k) ? 0.0 : in[idx];
-    out[idx] = v - in[i * n + k] * rk / p;
+  if (idx >= ld * ld) return;
+  const int64_t i = idx / ld, j = idx % ld;
+  dense[idx] = (i == j && i >= nd) ? 1.0 : 0.0;
+}
+
+// P = A_KK^{-1} by unblocked Gauss-Jordan in LDS (one workgroup of 256);
+// writes P into A_KK and into Pout; err = 1 on a non-positive (definite) or
+// zero pivot
+__global__ __launch_bounds__(256) void k_gj_pivot(int64_t ld, int K, double* __restrict__ dense,
+                                                  double* __restrict__ Pout, int* __restrict__ err, int definite) {
+  __shared__ double S[GJB][GJB + 1];
+  __shared__ double rowk[GJB], colk[GJB];
+  const int tid = threadIdx.x;
+  double* Akk = dense + (int64_t)K * GJB * ld + (int64_t)K * GJB;
+  for (int e = tid; e < GJB * GJB; e += 256) S[e / GJB][e % GJB] = Akk[(int64_t)(e / GJB) * ld + e % GJB];
+  __syncthreads();
+  bool bad = false;
+  for (int k = 0; k < GJB; ++k) {
+    const double p = S[k][k];
+    if (tid < GJB) {
+      rowk[tid] = S[k][tid];
+      colk[tid] = S[tid][k];
+    }
+    __syncthreads();
+    if (tid == 0 && (definite ? !(p > 0.0) : !(p != 0.0 && p == p))) bad = true;
+    const double ip = 1.0 / p;
+    for (int e = tid; e < GJB * GJB; e += 256) {
+      const int i = e / GJB, j = e % GJB;
+      double v;
+      if (i == k)
+        v = (j == k) ? ip : rowk[j] * ip;
+      else
+        v = (j == k) ? -colk[i] * ip : S[i][j] - colk[i] * rowk[j] * ip;
+      S[i][j] = v;
+    }
+    __syncthreads();
   }
+  if (tid == 0 && bad) *err = 1;
+  for (int e = tid; e < GJB * GJB; e += 256) {
+    const double v = S[e / GJB][e % GJB];
+    Akk[(int64_t)(e / GJB) * ld + e % GJB] = v;
+    Pout[e] = v;
+  }
+}
+
+// row panel: A_KJ <- P A_KJ for J != K (workgroup J)
+__global__ __launch_bounds__(256) void k_gj_row(int64_t ld, int K, double* __restrict__ dense,
+                                                const double* __restrict__ P) {
+  const int J = blockIdx.x;
+  if (J == K) return;
+  __shared__ double Ps[GJB][GJB];
+  __shared__ double Bs[GJB][GJB];
+  const int tid = threadIdx.x;
+  double* Akj = dense + (int64_t)K * GJB * ld + (int64_t)J * GJB;
+  for (int e = tid; e < GJB * GJB; e += 256) {
+    Ps[e / GJB][e % GJB] = P[e];
+    Bs[e / GJB][e % GJB] = Akj[(int64_t)(e / GJB) * ld + e % GJB];
+  }
+  __syncthreads();
+  for (int e = tid; e < GJB * GJB; e += 256) {
+    const int i = e / GJB, j = e % GJB;
+    double acc = 0.0;
+    for (int k = 0; k < GJB; ++k) acc += Ps[i][k] * Bs[k][j];
+    Akj[(int64_t)i * ld + j] = acc;
+  }
+}
+
+// column panel: A_IK <- -A_IK P for I != K (workgroup I)
+__global__ __launch_bounds__(256) void k_gj_col(int64_t ld, int K, double* __restrict__ dense,
+                                                const double* __restrict__ P) {
+  const int I = blockIdx.x;
+  if (I == K) return;
+  __shared__ double Ps[GJB][GJB];
+  __shared__ double Bs[GJB][GJB];
+  const int tid = threadIdx.x;
+  double* Aik = dense + (int64_t)I * GJB * ld + (int64_t)K * GJB;
+  for (int e = tid; e < GJB * GJB; e += 256) {
+    Ps[e / GJB][e % GJB] = P[e];
+    Bs[e / GJB][e % GJB] = Aik[(int64_t)(e / GJB) * ld + e % GJB];
+  }
+  __syncthreads();
+  for (int e = tid; e < GJB * GJB; e += 256) {
+    const int i = e / GJB, j = e % GJB;
+    double acc = 0.0;
+    for (int k = 0; k < GJB; ++k) acc += Bs[i][k] * Ps[k][j];
+    Aik[(int64_t)i * ld + j] = -acc;
+  }
+}
+
+// trailing update: A_IJ <- A_IJ - A_IK A_KJ for I, J != K (workgroup (J, I));
+// 256 threads, 4 x 4 outputs each; A_IK is staged transposed
+__global__ __launch_bounds__(256) void k_gj_update(int64_t ld, int K, double* __restrict__ dense) {
+  const int J = blockIdx.x, I = blockIdx.y;
+  if (I == K || J == K) return;
+  __shared__ double At[GJB][GJB];  // At[k][i] = A_IK(i, k)
+  __shared__ double Bs[GJB][GJB];  // Bs[k][j] = A_KJ(k, j)
+  const int tid = threadIdx.x;
+  const double* Aik = dense + (int64_t)I * GJB * ld + (int64_t)K * GJB;
+  const double* Akj = dense + (int64_t)K * GJB * ld + (int64_t)J * GJB;
+  for (int e = tid; e < GJB * GJB; e += 256) {
+    const int r = e / GJB, c = e % GJB;
+    At[c][r] = Aik[(int64_t)r * ld + c];
+    Bs[r][c] = Akj[(int64_t)r * ld + c];
+  }
+  __syncthreads();
+  const int ti = tid / 16, tj = tid % 16;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int k = 0; k < GJB; ++k) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) av[a] = At[k][ti * 4 + a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bv[b] = Bs[k][tj * 4 + b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+  }
+  double* Aij = dense + (int64_t)I * GJB * ld + (int64_t)J * GJB;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) Aij[(int64_t)(ti * 4 + a) * ld + tj * 4 + b] -= acc[a][b];
 }
 
 template <typename S, typename D>
@@ -343,15 +468,6 @@ __global__ __launch_bounds__(TPB) void k_dense_gemv(int64_t n, int64_t ld, const
   for (int64_t c = lane; c < nv; c += WAVE) s += Vec16<T>::dot(Ar[c], bv[c]);
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
   if (lane == 0) x[row] = s;
-}
-
-// dst (n x ld, zero padding columns) = (D) src (n x n)
-template <typename S, typename D>
-__global__ void k_pad_cast(int64_t n, int64_t ld, const S* __restrict__ src, D* __restrict__ dst) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n * ld) return;
-  const int64_t r = i / ld, c = i % ld;
-  dst[i] = c < n ? (D)src[r * n + c] : D(0);
 }
 
 // ------------------------------------------------------------------

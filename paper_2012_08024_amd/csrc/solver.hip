@@ -139,7 +139,7 @@ struct cdgmg_handle {
   int8_t *hostflag = nullptr, *revslot = nullptr;
   // coarsest
   int64_t nd = 0, ld = 0;
-  double *Ainv64 = nullptr, *dense1 = nullptr;
+  double *dense = nullptr, *gjP = nullptr;  // coarsest operator -> its inverse (ld x ld, FP64); pivot block
   void* AinvP = nullptr;  // A_L^{-1} in the multigrid precision, leading dimension ld
   // outer vectors (internal order, FP64)
   double *b = nullptr, *x = nullptr, *xl = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *t1 = nullptr,
@@ -442,13 +442,15 @@ int upload_problem(cdgmg_handle* h) {
     set_error("setup: coarsest level has " + std::to_string(h->nd) + " unknowns (limit 12000); use more levels");
     return CDGMG_ERR_ARG;
   }
-  RETURN_IF(dalloc(h, &h->Ainv64, (size_t)h->nd * h->nd));
-  RETURN_IF(dalloc(h, &h->dense1, (size_t)h->nd * h->nd));
-  h->ld = (h->nd + 63) / 64 * 64;
-  {
-    void* tmp;
-    RETURN_IF(dalloc(h, (char**)&tmp, (size_t)h->nd * h->ld * (fp32 ? sizeof(float) : sizeof(double))));
+  h->ld = (h->nd + GJB - 1) / GJB * GJB;
+  RETURN_IF(dalloc(h, &h->dense, (size_t)h->ld * h->ld));
+  RETURN_IF(dalloc(h, &h->gjP, (size_t)GJB * GJB));
+  if (fp32) {
+    float* tmp;
+    RETURN_IF(dalloc(h, &tmp, (size_t)h->nd * h->ld));
     h->AinvP = tmp;
+  } else {
+    h->AinvP = h->dense;
   }
   // outer vectors
   const size_t m = (size_t)h->lv[0].ns * SLICE * np;
@@ -552,26 +554,24 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev) {
   }
   // coarsest: dense scatter + Gauss-Jordan inverse (ping-pong)
   DLevel& cl = h->lv[h->L];
-  const int64_t nd = h->nd;
-  HIPCHK(hipMemsetAsync(h->dense1, 0, (size_t)nd * nd * sizeof(double), h->stream));
-  NP_DISPATCH(np, launch(h, -1, k_dense_scatter<NP>, dim3(grid_for(cl.n)), dim3(TPB), cl.n,
-                         (const int32_t*)cl.cols, (const int64_t*)cl.sblk, (const double*)cl.A64, h->dense1));
-  double* in = h->dense1;
-  double* out = h->Ainv64;
-  for (int64_t k = 0; k < nd; ++k) {
-    launch(h, -1, k_gj_step, dim3(grid_for(nd * nd)), dim3(TPB), nd, k, (const double*)in, out, h->err, definite);
-    std::swap(in, out);
+  const int64_t nd = h->nd, ld = h->ld;
+  launch(h, -1, k_dense_init, dim3(grid_for(ld * ld)), dim3(TPB), nd, ld, h->dense);
+  NP_DISPATCH(np, launch(h, -1, k_dense_scatter<NP>, dim3(grid_for(cl.n)), dim3(TPB), cl.n, ld,
+                         (const int32_t*)cl.cols, (const int64_t*)cl.sblk, (const double*)cl.A64, h->dense));
+  const int nbk = (int)(ld / GJB);
+  for (int K = 0; K < nbk; ++K) {
+    launch(h, -1, k_gj_pivot, dim3(1), dim3(256), ld, K, h->dense, h->gjP, h->err, definite);
+    if (nbk > 1) {
+      launch(h, -1, k_gj_row, dim3(nbk), dim3(256), ld, K, h->dense, (const double*)h->gjP);
+      launch(h, -1, k_gj_update, dim3(nbk, nbk), dim3(256), ld, K, h->dense);
+      launch(h, -1, k_gj_col, dim3(nbk), dim3(256), ld, K, h->dense, (const double*)h->gjP);
+    }
   }
-  if (in != h->Ainv64)
-    HIPCHK(hipMemcpyAsync(h->Ainv64, in, (size_t)nd * nd * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
   RETURN_IF(check_err(h, CDGMG_ERR_SINGULAR, flux ? "setup: the coarsest operator is singular"
                                                   : "setup: the coarsest operator is not positive definite"));
   if (h->o.mg_precision == CDGMG_MG_FP32)
-    launch(h, -1, k_pad_cast<double, float>, dim3(grid_for(nd * h->ld)), dim3(TPB), nd, h->ld,
-           (const double*)h->Ainv64, (float*)h->AinvP);
-  else
-    launch(h, -1, k_pad_cast<double, double>, dim3(grid_for(nd * h->ld)), dim3(TPB), nd, h->ld,
-           (const double*)h->Ainv64, (double*)h->AinvP);
+    launch(h, -1, k_cast<double, float>, dim3(grid_for(nd * ld)), dim3(TPB), nd * ld, (const double*)h->dense,
+           (float*)h->AinvP);
   HIPCHK(hipGetLastError());
   return CDGMG_OK;
 }
