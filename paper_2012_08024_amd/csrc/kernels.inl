@@ -54,14 +54,44 @@ __global__ void k_kappa_perm(int64_t n, const int32_t* __restrict__ perm, const 
 // pivoting (the block is symmetric positive definite: every pivot is a
 // positive Schur-complement diagonal).  err is set on a non-positive pivot.
 template <int NP>
-__global__ void k_diag_inverse(int64_t n, const int64_t* __restrict__ sblk, const double* __restrict__ A,
-                               double* __restrict__ Dinv, int* __restrict__ err, int definite) {
+__global__ __launch_bounds__(TPB) void k_diag_inverse(int64_t n, const int64_t* __restrict__ sblk,
+                                                      const double* __restrict__ A, double* __restrict__ Dinv,
+                                                      int* __restrict__ err, int definite) {
   constexpr int NP2 = NP * NP;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   const int lane = (int)(r % WAVE);
   const int64_t B = sblk[r / WAVE];
   double* D = Dinv + (r / WAVE) * WAVE * NP2 + lane;
+  if constexpr (NP <= 10) {
+    // the block in registers (static indices after unrolling)
+    double a[NP2];
+#pragma unroll
+    for (int ij = 0; ij < NP2; ++ij) a[ij] = A[blk_off(B, 0, NP2, ij, lane)];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const double p = a[k * NP + k];
+      if (definite ? !(p > 0.0) : !(p != 0.0)) {
+        *err = 1;
+        return;
+      }
+      const double ip = 1.0 / p;
+      a[k * NP + k] = 1.0;
+#pragma unroll
+      for (int j = 0; j < NP; ++j) a[k * NP + j] *= ip;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        if (i == k) continue;
+        const double f = a[i * NP + k];
+        a[i * NP + k] = 0.0;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) a[i * NP + j] -= f * a[k * NP + j];
+      }
+    }
+#pragma unroll
+    for (int ij = 0; ij < NP2; ++ij) D[ij * WAVE] = a[ij];
+    return;
+  }
   for (int ij = 0; ij < NP2; ++ij) D[ij * WAVE] = A[blk_off(B, 0, NP2, ij, lane)];
   for (int k = 0; k < NP; ++k) {
     const double p = D[(k * NP + k) * WAVE];
@@ -83,7 +113,8 @@ __global__ void k_diag_inverse(int64_t n, const int64_t* __restrict__ sblk, cons
 
 // K7 (Galerkin): coarse block k = (I, t) accumulates L_e^T A_f(e, w) L_c over its
 // plan entries (fixed order -> deterministic).  One workgroup per coarse block,
-// one thread per entry (i, j).
+// one thread per entry (i, j); the operands of up to GCH plan entries are
+// staged in LDS at once so their loads overlap.
 template <int NP>
 __global__ void k_galerkin(int64_t nblk, const int32_t* __restrict__ blk_row, const int64_t* __restrict__ row_blk,
                            const int64_t* __restrict__ plan_ptr, const int32_t* __restrict__ plan_e,
@@ -92,34 +123,40 @@ __global__ void k_galerkin(int64_t nblk, const int32_t* __restrict__ blk_row, co
                            const double* __restrict__ Lf, const int64_t* __restrict__ csblk,
                            double* __restrict__ Ac) {
   constexpr int NP2 = NP * NP;
-  __shared__ double sA[NP2], sLe[NP2], sLc[NP2], sT[NP2];
+  constexpr int GCH = NP2 <= 100 ? 8 : 2;
+  __shared__ double sA[GCH][NP2], sLe[GCH][NP2], sLc[GCH][NP2], sT[GCH][NP2];
   const int64_t k = blockIdx.x;
   if (k >= nblk) return;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
   const int i = tid / NP, j = tid % NP;
   double acc = 0.0;
-  for (int64_t q = plan_ptr[k]; q < plan_ptr[k + 1]; ++q) {
-    const int32_t e = plan_e[q];
-    const int w = plan_w[q];
-    const int64_t Be = fsblk[e / WAVE];
-    const int32_t c = fcols[Be + (int64_t)WAVE * w + e % WAVE];
-    if (tid < NP2) {
-      sA[tid] = Af[blk_off(Be, w, NP2, tid, e % WAVE)];
-      sLe[tid] = Lf[row_off(e, NP2, tid)];
-      sLc[tid] = Lf[row_off(c, NP2, tid)];
+  const int64_t q0 = plan_ptr[k], q1 = plan_ptr[k + 1];
+  for (int64_t qc = q0; qc < q1; qc += GCH) {
+    const int nc = (int)(q1 - qc < GCH ? q1 - qc : GCH);
+    for (int x = tid; x < nc * NP2; x += nt) {
+      const int t = x / NP2, ij = x % NP2;
+      const int32_t e = plan_e[qc + t];
+      const int w = plan_w[qc + t];
+      const int64_t Be = fsblk[e / WAVE];
+      const int32_t c = fcols[Be + (int64_t)WAVE * w + e % WAVE];
+      sA[t][ij] = Af[blk_off(Be, w, NP2, ij, e % WAVE)];
+      sLe[t][ij] = Lf[row_off(e, NP2, ij)];
+      sLc[t][ij] = Lf[row_off(c, NP2, ij)];
     }
     __syncthreads();
-    if (tid < NP2) {
+    for (int x = tid; x < nc * NP2; x += nt) {
+      const int t = x / NP2, ij = x % NP2, ii = ij / NP, jj = ij % NP;
       double s = 0.0;
-      for (int m = 0; m < NP; ++m) s += sA[i * NP + m] * sLc[m * NP + j];
-      sT[tid] = s;
+      for (int m = 0; m < NP; ++m) s += sA[t][ii * NP + m] * sLc[t][m * NP + jj];
+      sT[t][ij] = s;
     }
     __syncthreads();
-    if (tid < NP2) {
-      double s = 0.0;
-      for (int m = 0; m < NP; ++m) s += sLe[m * NP + i] * sT[m * NP + j];
-      acc += s;
-    }
+    if (tid < NP2)
+      for (int t = 0; t < nc; ++t) {
+        double s = 0.0;
+        for (int m = 0; m < NP; ++m) s += sLe[t][m * NP + i] * sT[t][m * NP + j];
+        acc += s;
+      }
     __syncthreads();
   }
   if (tid < NP2) {
@@ -271,14 +308,20 @@ __global__ __launch_bounds__(256) void k_gj_pivot(int64_t ld, int K, double* __r
     __syncthreads();
     if (tid == 0 && (definite ? !(p > 0.0) : !(p != 0.0 && p == p))) bad = true;
     const double ip = 1.0 / p;
-    for (int e = tid; e < GJB * GJB; e += 256) {
+    // 16 elements per thread, unrolled so that their LDS reads overlap
+    double v[GJB * GJB / 256];
+#pragma unroll
+    for (int m = 0; m < GJB * GJB / 256; ++m) {
+      const int e = tid + 256 * m;
       const int i = e / GJB, j = e % GJB;
-      double v;
-      if (i == k)
-        v = (j == k) ? ip : rowk[j] * ip;
-      else
-        v = (j == k) ? -colk[i] * ip : S[i][j] - colk[i] * rowk[j] * ip;
-      S[i][j] = v;
+      const double sij = S[i][j], ci = colk[i], rj = rowk[j];
+      const double gen = sij - ci * rj * ip;
+      v[m] = (i == k) ? ((j == k) ? ip : rj * ip) : ((j == k) ? -ci * ip : gen);
+    }
+#pragma unroll
+    for (int m = 0; m < GJB * GJB / 256; ++m) {
+      const int e = tid + 256 * m;
+      S[e / GJB][e % GJB] = v[m];
     }
     __syncthreads();
   }
@@ -734,66 +777,75 @@ __global__ __launch_bounds__(TPB) void k_restrict_grp(int64_t n, const int32_t* 
 }
 
 // ----------------------------------------------------------- prescaling (setup)
-// At_off(r, w) = D_r^{-1} A(r, w), w >= 1, into the level-0 sliced layout without slot 0
+// At_off(r, w) = D_r^{-1} A(r, w), w >= 1, into the level-0 sliced layout
+// without slot 0; one thread per output entry (slice, slot, i, j, lane),
+// grid over ns x (Wmax - 1) x n_p^2 x 64
 template <typename T, int NP>
-__global__ void k_scale_sliced(int64_t n, const int64_t* __restrict__ sblk, const double* __restrict__ A,
+__global__ void k_scale_sliced(int64_t n, int Wmax, const int64_t* __restrict__ sblk, const double* __restrict__ A,
                                const double* __restrict__ Dinv, T* __restrict__ At) {
   constexpr int NP2 = NP * NP;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  const int64_t s = r / WAVE;
-  const int lane = (int)(r % WAVE);
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = (int)(idx % WAVE);
+  int64_t rest = idx / WAVE;
+  const int ij = (int)(rest % NP2);
+  rest /= NP2;
+  const int w = (int)(rest % (Wmax - 1)) + 1;
+  const int64_t s = rest / (Wmax - 1);
+  if (s * WAVE + lane >= n) return;
   const int64_t B = sblk[s], Bo = B - WAVE * s;
-  const int W = (int)((sblk[s + 1] - B) / WAVE);
+  if (w >= (int)((sblk[s + 1] - B) / WAVE)) return;
+  const int i = ij / NP, j = ij % NP;
   const double* D = Dinv + s * WAVE * NP2 + lane;
-  for (int w = 1; w < W; ++w)
-    for (int i = 0; i < NP; ++i)
-      for (int j = 0; j < NP; ++j) {
-        double acc = 0.0;
-        for (int m = 0; m < NP; ++m) acc += D[(i * NP + m) * WAVE] * A[blk_off(B, w, NP2, m * NP + j, lane)];
-        At[(Bo + (int64_t)WAVE * (w - 1)) * NP2 + (i * NP + j) * WAVE + lane] = (T)acc;
-      }
+  double acc = 0.0;
+#pragma unroll
+  for (int m = 0; m < NP; ++m) acc += D[(i * NP + m) * WAVE] * A[blk_off(B, w, NP2, m * NP + j, lane)];
+  At[(Bo + (int64_t)WAVE * (w - 1)) * NP2 + (int64_t)ij * WAVE + lane] = (T)acc;
 }
 
-// coarse strips: off-diagonal blocks of D^{-1} A, component-major, unpadded
+// coarse strips: off-diagonal blocks of D^{-1} A, component-major, unpadded;
+// one thread per (stored block b, i, j), b over the level's row-major blocks
 template <typename T, int NP>
-__global__ void k_scale_wpr(int64_t n, const int64_t* __restrict__ sblk, const int64_t* __restrict__ woff,
-                            const double* __restrict__ A, const double* __restrict__ Dinv, T* __restrict__ R) {
+__global__ void k_scale_wpr(int64_t nnzb, const int32_t* __restrict__ blk_row, const int64_t* __restrict__ sblk,
+                            const int64_t* __restrict__ woff, const double* __restrict__ A,
+                            const double* __restrict__ Dinv, T* __restrict__ R) {
   constexpr int NP2 = NP * NP;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  const int64_t s = r / WAVE;
-  const int lane = (int)(r % WAVE);
-  const int64_t B = sblk[s];
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nnzb * NP2) return;
+  const int64_t b = idx / NP2;
+  const int ij = (int)(idx % NP2), i = ij / NP, j = ij % NP;
+  const int64_t r = blk_row[b];
   const int64_t o = woff[r];
-  const int len = (int)(woff[r + 1] - o);
-  const int K = (len - 1) * NP;
-  T* Rr = R + (o - r) * NP2;
-  const double* D = Dinv + s * WAVE * NP2 + lane;
-  for (int w = 1; w < len; ++w)
-    for (int i = 0; i < NP; ++i)
-      for (int j = 0; j < NP; ++j) {
-        double acc = 0.0;
-        for (int m = 0; m < NP; ++m) acc += D[(i * NP + m) * WAVE] * A[blk_off(B, w, NP2, m * NP + j, lane)];
-        Rr[(int64_t)i * K + (w - 1) * NP + j] = (T)acc;
-      }
+  const int w = (int)(b - o);
+  if (w == 0) return;  // diagonal block
+  const int K = (int)(woff[r + 1] - o - 1) * NP;
+  const int lane = (int)(r % WAVE);
+  const int64_t B = sblk[r / WAVE];
+  const double* D = Dinv + (r / WAVE) * WAVE * NP2 + lane;
+  double acc = 0.0;
+#pragma unroll
+  for (int m = 0; m < NP; ++m) acc += D[(i * NP + m) * WAVE] * A[blk_off(B, w, NP2, m * NP + j, lane)];
+  R[(o - r) * NP2 + (int64_t)i * K + (w - 1) * NP + j] = (T)acc;
 }
 
-// Lt_e = D_e L_e (D_e the diagonal block of A), per-row layout
+// Lt_e = D_e L_e (D_e the diagonal block of A), per-row layout; one thread
+// per (row, i, j), rows fastest
 template <typename T, int NP>
 __global__ void k_scale_L(int64_t n, const int64_t* __restrict__ sblk, const double* __restrict__ A,
                           const double* __restrict__ L, T* __restrict__ Lt) {
   constexpr int NP2 = NP * NP;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = (int)(idx % WAVE);
+  const int64_t rest = idx / WAVE;
+  const int ij = (int)(rest % NP2);
+  const int64_t s = rest / NP2;
+  const int64_t r = s * WAVE + lane;
   if (r >= n) return;
-  const int lane = (int)(r % WAVE);
-  const int64_t B = sblk[r / WAVE];
-  for (int i = 0; i < NP; ++i)
-    for (int j = 0; j < NP; ++j) {
-      double acc = 0.0;
-      for (int m = 0; m < NP; ++m) acc += A[blk_off(B, 0, NP2, i * NP + m, lane)] * L[row_off(r, NP2, m * NP + j)];
-      Lt[row_off(r, NP2, i * NP + j)] = (T)acc;
-    }
+  const int i = ij / NP, j = ij % NP;
+  const int64_t B = sblk[s];
+  double acc = 0.0;
+#pragma unroll
+  for (int m = 0; m < NP; ++m) acc += A[blk_off(B, 0, NP2, i * NP + m, lane)] * L[row_off(r, NP2, m * NP + j)];
+  Lt[row_off(r, NP2, ij)] = (T)acc;
 }
 
 // ---------------------------------------------------------- outer (FP64) kernels

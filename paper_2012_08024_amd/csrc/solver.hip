@@ -484,13 +484,15 @@ void prescale(cdgmg_handle* h) {
   constexpr int NP2 = NP * NP;
   for (int l = 0; l < h->L; ++l) {
     DLevel& D = h->lv[l];
-    if (l == 0)
-      launch(h, -1, k_scale_sliced<T, NP>, dim3(grid_for(D.n)), dim3(TPB), D.n, (const int64_t*)D.sblk,
-             (const double*)D.A64, (const double*)D.D64, (T*)D.At);
-    else
-      launch(h, -1, k_scale_wpr<T, NP>, dim3(grid_for(D.n)), dim3(TPB), D.n, (const int64_t*)D.sblk,
-             (const int64_t*)D.woff, (const double*)D.A64, (const double*)D.D64, (T*)D.R);
-    launch(h, -1, k_scale_L<T, NP>, dim3(grid_for(D.n)), dim3(TPB), D.n, (const int64_t*)D.sblk,
+    if (l == 0) {
+      const int W0 = h->W0;
+      launch(h, -1, k_scale_sliced<T, NP>, dim3(grid_for(D.ns * (W0 - 1) * NP2 * WAVE)), dim3(TPB), D.n, W0,
+             (const int64_t*)D.sblk, (const double*)D.A64, (const double*)D.D64, (T*)D.At);
+    } else {
+      launch(h, -1, k_scale_wpr<T, NP>, dim3(grid_for(D.nnzb * NP2)), dim3(TPB), D.nnzb, (const int32_t*)D.blk_row,
+             (const int64_t*)D.sblk, (const int64_t*)D.woff, (const double*)D.A64, (const double*)D.D64, (T*)D.R);
+    }
+    launch(h, -1, k_scale_L<T, NP>, dim3(grid_for(D.ns * NP2 * WAVE)), dim3(TPB), D.n, (const int64_t*)D.sblk,
            (const double*)D.A64, (const double*)D.L64, (T*)D.Lt);
     if ((void*)D.Dm != (void*)D.D64) {
       const int64_t nb = D.ns * SLICE * NP2;
