@@ -924,8 +924,25 @@ __global__ __launch_bounds__(TPB) void k_dots(int64_t m, int nd, const double* _
   }
 }
 
-// fixed-order reduction of nd partial arrays (nb entries each) into scal[off + d]
-__global__ void k_reduce(const double* __restrict__ part, int nb, int nd, double* __restrict__ scal, int off) {
+// Krylov scalars from the reduced dots: 0 FCG beta, 1 PCG beta, 2 FCG alpha,
+// 3 PCG alpha (each also keeps the denominator for the next iteration)
+__device__ __forceinline__ void krylov_scalars(double* s, int mode) {
+  if (mode == 0) s[SC_BETA] = s[SC_ZQ] / s[SC_PQOLD];
+  if (mode == 1) s[SC_BETA] = s[SC_ZR] / s[SC_ZROLD];
+  if (mode == 2) {
+    s[SC_ALPHA] = s[SC_PR] / s[SC_PQ];
+    s[SC_PQOLD] = s[SC_PQ];
+  }
+  if (mode == 3) {
+    s[SC_ALPHA] = s[SC_ZR] / s[SC_PQ];
+    s[SC_ZROLD] = s[SC_ZR];
+  }
+}
+
+// fixed-order reduction of nd partial arrays (nb entries each) into
+// scal[off + d]; then, for mode >= 0, the Krylov scalars of that mode
+__global__ void k_reduce(const double* __restrict__ part, int nb, int nd, double* __restrict__ scal, int off,
+                         int mode) {
   __shared__ double sh[TPB / WAVE];
   for (int d = 0; d < nd; ++d) {
     double s = 0.0;
@@ -933,6 +950,7 @@ __global__ void k_reduce(const double* __restrict__ part, int nb, int nd, double
     s = block_sum(s, sh);
     if (threadIdx.x == 0) scal[off + d] = s;
   }
+  if (threadIdx.x == 0 && mode >= 0) krylov_scalars(scal, mode);
 }
 
 
@@ -1115,19 +1133,6 @@ __global__ void k_out_dd(int64_t n, int np, const int32_t* __restrict__ perm, co
 // scalar bookkeeping (single thread)
 // mode 0: FCG beta = s[ZQ] / s[PQOLD]; mode 1: PCG beta = s[ZR] / s[ZROLD]
 // mode 2: FCG alpha = s[PR] / s[PQ], PQOLD = PQ; mode 3: PCG alpha = s[ZR] / s[PQ], ZROLD = ZR
-__global__ void k_scalars(double* s, int mode) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (mode == 0) s[SC_BETA] = s[SC_ZQ] / s[SC_PQOLD];
-  if (mode == 1) s[SC_BETA] = s[SC_ZR] / s[SC_ZROLD];
-  if (mode == 2) {
-    s[SC_ALPHA] = s[SC_PR] / s[SC_PQ];
-    s[SC_PQOLD] = s[SC_PQ];
-  }
-  if (mode == 3) {
-    s[SC_ALPHA] = s[SC_ZR] / s[SC_PQ];
-    s[SC_ZROLD] = s[SC_ZR];
-  }
-}
 
 // p = z + sign * beta * p  (first iteration: p = z); z in the multigrid precision
 template <typename T>
