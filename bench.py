@@ -278,12 +278,20 @@ def main():
     }
     s32.close()
     if args.copy_probe:
+        # a plain 1 GiB device copy: calibrates the HBM counters and gives the
+        # copy bandwidth this device reaches (read + write bytes per second)
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        e1.record()
         torch.cuda.synchronize()
-        result["copy_probe_bytes"] = int(src.numel() * 4)
+        nbytes = int(src.numel() * 4)
+        result["copy_probe_bytes"] = nbytes
+        result["copy_probe_gbs"] = 2 * nbytes * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     print(json.dumps(result), flush=True)
 
 

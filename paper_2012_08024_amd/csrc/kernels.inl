@@ -941,12 +941,20 @@ __device__ __forceinline__ void krylov_scalars(double* s, int mode) {
 
 // fixed-order reduction of nd partial arrays (nb entries each) into
 // scal[off + d]; then, for mode >= 0, the Krylov scalars of that mode
-__global__ void k_reduce(const double* __restrict__ part, int nb, int nd, double* __restrict__ scal, int off,
-                         int mode) {
-  __shared__ double sh[TPB / WAVE];
+// (one workgroup of RED_T threads; each thread's loads are issued together)
+constexpr int RED_T = 1024;
+__global__ __launch_bounds__(RED_T) void k_reduce(const double* __restrict__ part, int nb, int nd,
+                                                  double* __restrict__ scal, int off, int mode) {
+  __shared__ double sh[RED_T / WAVE];
   for (int d = 0; d < nd; ++d) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[d * nb + i];
+    int i = threadIdx.x;
+    for (; i + 3 * RED_T < nb; i += 4 * RED_T) {
+      const double a0 = part[d * nb + i], a1 = part[d * nb + i + RED_T], a2 = part[d * nb + i + 2 * RED_T],
+                   a3 = part[d * nb + i + 3 * RED_T];
+      s += (a0 + a1) + (a2 + a3);
+    }
+    for (; i < nb; i += RED_T) s += part[d * nb + i];
     s = block_sum(s, sh);
     if (threadIdx.x == 0) scal[off + d] = s;
   }

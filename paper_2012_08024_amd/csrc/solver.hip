@@ -723,7 +723,7 @@ void dot_into(cdgmg_handle* h, int64_t m, const double* a, const double* b, int 
   const unsigned g = std::min<unsigned>(1024, grid_for(m));
   launch(h, CDGMG_K_VECTOR, k_dots, dim3(g), dim3(TPB), m, 1, a, b, (const double*)nullptr,
          (const double*)nullptr, h->part);
-  launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)g, 1, h->scal, slot, -1);
+  launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(RED_T), (const double*)h->part, (int)g, 1, h->scal, slot, -1);
 }
 
 int read_scalar(cdgmg_handle* h, int slot, double* out) {
@@ -741,7 +741,7 @@ void enqueue_true_residual(cdgmg_handle* h) {
                                             dim3(WAVE * H), d.n, (const int32_t*)d.cols, (const double*)d.A64,
                                             (const double*)h->b, (const double*)h->x, (const double*)h->xl, h->r,
                                             h->part)));
-  launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)d.ns, 1, h->scal, SC_TMP,
+  launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(RED_T), (const double*)h->part, (int)d.ns, 1, h->scal, SC_TMP,
          -1);
 }
 
@@ -823,7 +823,7 @@ int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
   auto enqueue_update = [&](int iter) {
     // the dot of z (with q or r) and, from the second iteration on, beta
     if (zdot)
-      launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, nz, 1, h->scal,
+      launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(RED_T), (const double*)h->part, nz, 1, h->scal,
              fcg ? (int)SC_ZQ : (int)SC_ZR, iter > 0 ? (fcg ? 0 : 1) : -1);
     const double sign = fcg ? -1.0 : 1.0;
     if (h->o.mg_precision == CDGMG_MG_FP32)
@@ -842,7 +842,7 @@ int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
                                             dim3(WAVE * H), d0.n, (const int32_t*)d0.cols, (const double*)d0.A64,
                                             (const double*)h->p, (const double*)h->r, h->q, h->part)));
     }
-    launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)g, 2, h->scal, SC_PQ,
+    launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(RED_T), (const double*)h->part, (int)g, 2, h->scal, SC_PQ,
            fcg ? 2 : 3);
     // x += alpha p: double-double once the compensated phase has started
     // (x_lo stays zero before), r -= alpha q
@@ -853,7 +853,7 @@ int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
     else
       launch(h, CDGMG_K_VECTOR, k_update_xr, dim3(gu), dim3(TPB), m, (const double*)h->p, (const double*)h->q,
              h->x, h->r, (const double*)h->scal, h->part);
-    launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(TPB), (const double*)h->part, (int)gu, 1, h->scal, SC_RR,
+    launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(RED_T), (const double*)h->part, (int)gu, 1, h->scal, SC_RR,
            -1);
   };
   if (nb == 0.0) {
