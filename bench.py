@@ -292,6 +292,18 @@ def main():
         nbytes = int(src.numel() * 4)
         result["copy_probe_bytes"] = nbytes
         result["copy_probe_gbs"] = 2 * nbytes * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        # read-only stream of the same 1 GiB (torch's sum)
+        acc = torch.zeros((), dtype=torch.float32, device="cuda")
+        torch.sum(src, out=acc)
+        e0.record()
+        for _ in range(10):
+            torch.sum(src, out=acc)
+        e1.record()
+        torch.cuda.synchronize()
+        result["read_probe_gbs"] = nbytes * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        # the last dispatch before the counters are read is the 1 GiB copy
+        dst.copy_(src)
+        torch.cuda.synchronize()
     print(json.dumps(result), flush=True)
 
 
