@@ -1,0 +1,147 @@
+"""libcdgmg on the CPU: the library loads and exports every entry point that
+include/cdgmg.h declares, and its host-only calls (greedy agglomeration,
+switch, level operators formed on the host from the library's own setup
+data) agree with the oracle.  No GPU call is made."""
+import importlib.util
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.agglomerate import build_hierarchy
+from oracle.cdg import CDG
+from oracle.mesh import Topology
+from oracle.multigrid import Hierarchy
+from workloads import mesh2d_jittered_delaunay, mesh3d_kuhn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PKG = os.path.join(ROOT, "paper_2012_08024_amd")
+
+
+def _load_library():
+    if not os.path.exists(os.path.join(PKG, "libcdgmg.so")):
+        spec = importlib.util.spec_from_file_location("_cdgmg_build", os.path.join(PKG, "build.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.build()
+    import paper_2012_08024_amd as cm
+    return cm
+
+
+cm = _load_library()
+
+
+def _declared_functions():
+    with open(os.path.join(ROOT, "include", "cdgmg.h")) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(cdgmg_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_exports_every_declared_entry_point():
+    names = _declared_functions()
+    assert len(names) >= 20, names
+    missing = [n for n in names if not hasattr(cm.lib, n)]
+    assert not missing, missing
+    assert set(names) == set(cm.EXPORTED)
+
+
+def test_version_and_default_options():
+    assert cm.lib.cdgmg_version() > 0
+    o = cm.default_options()
+    assert o.gamma == 1e4 and o.omega == 0.7 and o.nu1 == 2 and o.nu2 == 2
+    assert o.mg_precision == cm.MG_FP32 and o.outer == cm.OUTER_FCG and o.coarsening == cm.COARSEN_PRIMAL
+    assert o.tol == 1e-10 and o.kernel_variant == 0
+
+
+@pytest.mark.parametrize("d,n,seed,p,coarse_dofs", [(2, 16, 11, 1, 0), (2, 23, 5, 2, 0), (3, 4, 13, 1, 0),
+                                                    (2, 20, 14, 3, 300)])
+def test_agglomeration_bit_exact_with_oracle(d, n, seed, p, coarse_dofs):
+    m = mesh2d_jittered_delaunay(n, 1) if d == 2 else mesh3d_kuhn(n, 1)
+    parents, sizes = cm.agglomerate(m, 20, seed, p=p, coarse_dofs=coarse_dofs)
+    topo = Topology(m.e2v, m.coords)
+    npb = cm.n_basis(d, p)
+    ref = build_hierarchy(m.e2v, topo.neighbor_pairs(), 20, seed,
+                          coarse_dofs=coarse_dofs if coarse_dofs else None, n_p=npb)
+    assert len(parents) == len(ref)
+    for a, b in zip(parents, ref):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+    assert sizes[0] == m.n_elem
+    for l, par in enumerate(parents):
+        assert int(par.max()) + 1 == sizes[l + 1]
+
+
+def _oracle_hosted(m, cdg):
+    nf = m.e2v.shape[1]
+    flags = np.zeros((m.n_elem, nf), dtype=np.int8)
+    for f, (a, ia, b, ib) in enumerate(cdg.topo.interior):
+        if cdg.host[f] == a:
+            flags[a, ia] = 1
+        else:
+            flags[b, ib] = 1
+    for (e, i) in cdg.topo.boundary:
+        if m.face_bc[e, i] == 0:
+            flags[e, i] = 1
+    return flags
+
+
+@pytest.mark.parametrize("mode,seed", [(0, 0), (1, 0), (1, 7)])
+@pytest.mark.parametrize("d,n", [(2, 9), (3, 3)])
+def test_switch_matches_oracle(d, n, mode, seed):
+    m = mesh2d_jittered_delaunay(n, 2) if d == 2 else mesh3d_kuhn(n, 2)
+    got = cm.switch(m, mode=mode, seed=seed)
+    cdg = CDG(m.coords, m.e2v, m.face_bc, 1, switch="consistent" if mode == 0 else "natural",
+              switch_seed=seed)
+    assert np.array_equal(got, _oracle_hosted(m, cdg))
+
+
+@pytest.mark.parametrize("coarsening", ["primal", "flux"])
+@pytest.mark.parametrize("d,n,p,levels,seed", [(2, 10, 2, 3, 3), (3, 3, 1, 3, 5)])
+def test_host_level_operators_match_oracle(d, n, p, levels, seed, coarsening):
+    m = mesh2d_jittered_delaunay(n, 1) if d == 2 else mesh3d_kuhn(n, 1)
+    parents, sizes = cm.agglomerate(m, levels, seed, p=p)
+    kappa = np.random.default_rng(seed).uniform(0.5, 2.0, m.n_elem)
+    cdg = CDG(m.coords, m.e2v, m.face_bc, p)
+    H = Hierarchy(cdg, parents, kappa=kappa, coarsening=coarsening)
+    cflag = cm.COARSEN_PRIMAL if coarsening == "primal" else cm.COARSEN_FLUX
+    for l in range(len(sizes)):
+        A = cm.bsr_to_scipy(*cm.debug_host_operator(m, p, kappa, parents, sizes, l, coarsening=cflag))
+        R = H.A[l]
+        assert abs(A - R).max() <= 1e-11 * abs(R).max(), (l, abs(A - R).max())
+
+
+def test_gamma_enters_the_host_operator():
+    m = mesh2d_jittered_delaunay(8, 1)
+    parents, sizes = cm.agglomerate(m, 2, 1, p=1)
+    kappa = np.ones(m.n_elem)
+    for gamma in (10.0, 1e3):
+        A = cm.bsr_to_scipy(*cm.debug_host_operator(m, 1, kappa, parents, sizes, 0, gamma=gamma))
+        R = CDG(m.coords, m.e2v, m.face_bc, 1, gamma=gamma).A(kappa)
+        assert abs(A - R).max() <= 1e-12 * abs(R).max()
+
+
+def test_host_error_paths():
+    m = mesh2d_jittered_delaunay(6, 1)
+    with pytest.raises(cm.CdgmgError) as ei:
+        cm.agglomerate(m, 3, 0, p=4)
+    assert ei.value.code == -1
+    bad = cm.HostMesh(m.coords, m.e2v[:, [0, 2, 1]], m.face_bc)  # inverted orientation
+    with pytest.raises(cm.CdgmgError) as ei:
+        cm.switch(bad)
+    assert ei.value.code == -2
+
+
+@pytest.mark.parametrize("coarsening", ["primal", "flux"])
+def test_host_level_operators_natural_switch(coarsening):
+    m = mesh2d_jittered_delaunay(9, 3)
+    parents, sizes = cm.agglomerate(m, 3, 2, p=2)
+    kappa = np.random.default_rng(4).uniform(0.5, 2.0, m.n_elem)
+    cdg = CDG(m.coords, m.e2v, m.face_bc, 2, switch="natural", switch_seed=9)
+    H = Hierarchy(cdg, parents, kappa=kappa, coarsening=coarsening)
+    cflag = cm.COARSEN_PRIMAL if coarsening == "primal" else cm.COARSEN_FLUX
+    for l in range(len(sizes)):
+        A = cm.bsr_to_scipy(*cm.debug_host_operator(m, 2, kappa, parents, sizes, l, coarsening=cflag,
+                                                    switch_mode=cm.SWITCH_NATURAL, switch_seed=9))
+        R = H.A[l]
+        assert abs(A - R).max() <= 1e-11 * abs(R).max(), (l, abs(A - R).max())
