@@ -109,11 +109,23 @@ def main():
                     help="V-cycle kernel family (see cdgmg_options.kernel_variant); 0 = auto")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--study", choices=["coarsening", "switch"],
+                    help="instead of the benchmark: primal vs flux coarsening over mesh size and gamma, or "
+                         "consistent vs natural switch; prints one JSON line with the table")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the solve is single-GPU; "
               "multi-GPU domain decomposition is a design note, not built)", file=sys.stderr)
         sys.exit(2)
+    if args.study:
+        import torch
+
+        from paper_2012_08024_amd import studies
+        torch.cuda.set_device(0)
+        fn = studies.study_coarsening if args.study == "coarsening" else studies.study_switch
+        rows = fn(log=log)
+        print(json.dumps({"study": args.study, "data": "synthetic", "rows": rows}), flush=True)
+        return
 
     import numpy as np
     import torch

@@ -223,6 +223,31 @@ def test_flux_coarse_operators_match_oracle(name):
     solver.close()
 
 
+@pytest.mark.parametrize("coarsening", ["primal", "flux"])
+@pytest.mark.parametrize("gamma,mode,sseed", [(10.0, 0, 0), (1e2, 1, 0), (1e3, 1, 7)])
+def test_level_operators_gamma_and_switch(gamma, mode, sseed, coarsening):
+    # the coarsening and switch studies change only setup options: the Dirichlet
+    # penalty gamma (Sec. 2.2) and the natural switch (Sec. 4.2)
+    mesh = mesh2d_jittered_delaunay(11, 2)
+    parents, sizes = cm.agglomerate(mesh, 3, 4, p=2)
+    kappa = np.random.default_rng(6).uniform(0.5, 2.0, mesh.n_elem)
+    cflag = cm.COARSEN_PRIMAL if coarsening == "primal" else cm.COARSEN_FLUX
+    print("case gamma", gamma, "switch", mode, sseed, coarsening, list(sizes), flush=True)
+    try:
+        solver = cm.Solver(mesh, 2, kappa, parents, sizes, mg_precision=cm.MG_FP64, coarsening=cflag, gamma=gamma,
+                           switch_mode=mode, switch_seed=sseed)
+    except cm.CdgmgError as e:
+        pytest.skip("flux setup refused: %s" % e)
+    cdg = CDG(mesh.coords, mesh.e2v, mesh.face_bc, 2, gamma=gamma,
+              switch="consistent" if mode == cm.SWITCH_CONSISTENT else "natural", switch_seed=sseed)
+    H = Hierarchy(cdg, parents, kappa=kappa, coarsening=coarsening)
+    for l in range(len(sizes)):
+        A = cm.bsr_to_scipy(*solver.export_operator(l))
+        R = H.A[l]
+        assert abs(A - R).max() <= 1e-11 * abs(R).max(), (l, abs(A - R).max())
+    solver.close()
+
+
 def test_flux_solve_small_mesh():
     # on a small mesh the flux-coarsened levels are still definite and the
     # flux-preconditioned FCG converges to the direct solution

@@ -2,6 +2,7 @@
 include/cdgmg.h declares, and its host-only calls (greedy agglomeration,
 switch, level operators formed on the host from the library's own setup
 data) agree with the oracle.  No GPU call is made."""
+import dataclasses
 import importlib.util
 import os
 import re
@@ -145,3 +146,29 @@ def test_host_level_operators_natural_switch(coarsening):
                                                     switch_mode=cm.SWITCH_NATURAL, switch_seed=9))
         R = H.A[l]
         assert abs(A - R).max() <= 1e-11 * abs(R).max(), (l, abs(A - R).max())
+
+
+@pytest.mark.parametrize("mode,seed", [(0, 0), (1, 0), (1, 3)])
+@pytest.mark.parametrize("d,n", [(2, 7), (3, 2)])
+def test_second_neighbour_count_matches_oracle_C(d, n, mode, seed):
+    # the study's count of C's second-neighbour couplings (Sec. 4.2) against
+    # the distance-2 nonzero blocks of the oracle's C.  Every vertex is moved
+    # slightly: a coupling through facets with orthogonal normals (unjittered
+    # boundary cubes) has a lifting product that vanishes exactly, while the
+    # count is structural.
+    from paper_2012_08024_amd.studies import face_neighbours, second_neighbour_pairs
+    m = mesh2d_jittered_delaunay(n, 4) if d == 2 else mesh3d_kuhn(n, 4)
+    coords = m.coords + 0.02 / n * np.random.default_rng(5).uniform(-1, 1, m.coords.shape)
+    m = dataclasses.replace(m, coords=coords)
+    hosted = cm.switch(m, mode=mode, seed=seed)
+    cdg = CDG(m.coords, m.e2v, m.face_bc, 1, switch="consistent" if mode == 0 else "natural", switch_seed=seed)
+    C = cdg.C(np.ones(m.n_elem)).tocsr()
+    npb = cdg.np
+    nbr = face_neighbours(m.e2v)
+    count = 0
+    for a in range(m.n_elem):
+        blk = C[a * npb:(a + 1) * npb, :]
+        cols = set(int(c) // npb for c, v in zip(blk.indices, blk.data) if abs(v) > 0)
+        count += sum(1 for b in cols if b > a and b not in nbr[a])
+    assert count == second_neighbour_pairs(m.e2v, hosted)
+    assert count > 0
