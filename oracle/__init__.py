@@ -14,7 +14,8 @@ for compact discontinuous Galerkin discretizations on unstructured meshes":
 * ``agglomerate`` greedy agglomeration, Alg. 1 and Alg. 2 (Sec. 3.1-3.2)
 * ``multigrid``   agglomerate bases, transfers, flux/primal coarsening, the
                   V-cycle with damped block Jacobi (Sec. 3.3-3.5, Sec. 4.1, Alg. 3)
-* ``krylov``      PCG and flexible CG (FCG(1), Notay 2000) outer solvers
+* ``krylov``      PCG, flexible CG (FCG(1), Notay 2000) and right-preconditioned
+                  GMRES(m) (Sec. 4) outer solvers
 * ``adjoint``     adjoint gradients dL/dkappa and dL/df of the solve
 
 Every function computes in float64 with plain NumPy / SciPy primitives and
