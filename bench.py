@@ -109,6 +109,9 @@ def main():
                     help="V-cycle kernel family (see cdgmg_options.kernel_variant); 0 = auto")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--outer", choices=["fcg", "pcg", "gmres"], default="fcg",
+                    help="outer Krylov solver (the metric is quoted with fcg)")
+    ap.add_argument("--restart", type=int, default=50, help="GMRES restart length")
     ap.add_argument("--study", choices=["coarsening", "switch"],
                     help="instead of the benchmark: primal vs flux coarsening over mesh size and gamma, or "
                          "consistent vs natural switch; prints one JSON line with the table")
@@ -143,7 +146,10 @@ def main():
     kappa_t = torch.tensor(kappa, dtype=torch.float64, device="cuda")
 
     t0 = time.perf_counter()
+    outer = {"fcg": cm.OUTER_FCG, "pcg": cm.OUTER_PCG, "gmres": cm.OUTER_GMRES}[args.outer]
+    outer_name = {"fcg": "FCG(1)", "pcg": "PCG", "gmres": "GMRES(%d)" % args.restart}[args.outer]
     s32 = cm.Solver(mesh, cfg["p"], kappa_t, parents, sizes, mg_precision=cm.MG_FP32, tol=cfg["tol"],
+                    outer=outer, restart=args.restart,
                     kernel_variant=args.kernel_variant)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
@@ -214,6 +220,7 @@ def main():
     if not args.no_fp64:
         s32_bytes = s32.device_bytes()
         s64 = cm.Solver(mesh, cfg["p"], kappa_t, parents, sizes, mg_precision=cm.MG_FP64, tol=cfg["tol"],
+                        outer=outer, restart=args.restart,
                         kernel_variant=args.kernel_variant)
         for _ in range(max(1, args.warmup)):
             u64, info64 = s64.solve(f)
@@ -254,10 +261,10 @@ def main():
         "config": {
             "workload": "%s: %dD jittered %s mesh n=%d, %d elements, CDG p=%d, %d DOFs, kappa=%s, %d-level "
                         "greedy agglomeration (seed %d), V(%d,%d) damped block Jacobi omega=%.1f, "
-                        "Galerkin coarse operators, FCG(1), tol %.0e"
+                        "Galerkin coarse operators, %s, tol %.0e"
                         % (args.config, cfg["dim"], "Delaunay" if cfg["dim"] == 2 else "Kuhn-tet", cfg["n"],
                            mesh.n_elem, cfg["p"], dofs, cfg["kappa"], len(sizes), cfg["agg_seed"], 2, 2, 0.7,
-                           cfg["tol"]),
+                           outer_name, cfg["tol"]),
             "elements": int(mesh.n_elem), "dofs": int(dofs), "p": cfg["p"], "levels": [int(x) for x in sizes],
             "nnzb": [int(x) for x in nnzb],
             "operator_complexity": float(sum(nnzb) / nnzb[0]),

@@ -54,6 +54,7 @@ extern "C" {
 #define CDGMG_MG_FP32 1          /* V-cycle in FP32 inside the FP64 outer solve */
 #define CDGMG_OUTER_FCG 0        /* flexible CG, one previous direction (Notay 2000) */
 #define CDGMG_OUTER_PCG 1        /* preconditioned CG */
+#define CDGMG_OUTER_GMRES 2      /* right-preconditioned restarted GMRES(restart), flexible form (Sec. 4) */
 #define CDGMG_COARSEN_PRIMAL 0   /* A_{l+1} = L^T A_l L (Galerkin / RAT, Sec. 3.5) */
 #define CDGMG_COARSEN_FLUX 1     /* flux-form coarsening + Schur complement (Sec. 4.1) */
 #define CDGMG_SWITCH_CONSISTENT 0
@@ -89,7 +90,7 @@ typedef struct cdgmg_options {
   double omega;        /* block-Jacobi damping; default 0.7 */
   int nu1, nu2;        /* pre/post sweeps; default 2, 2 */
   int mg_precision;    /* CDGMG_MG_FP32 (default) or CDGMG_MG_FP64 */
-  int outer;           /* CDGMG_OUTER_FCG (default) or CDGMG_OUTER_PCG */
+  int outer;           /* CDGMG_OUTER_FCG (default), CDGMG_OUTER_PCG or CDGMG_OUTER_GMRES */
   int coarsening;      /* CDGMG_COARSEN_PRIMAL (default) or CDGMG_COARSEN_FLUX */
   int switch_mode;     /* CDGMG_SWITCH_CONSISTENT (default) or CDGMG_SWITCH_NATURAL */
   uint64_t switch_seed;/* natural switch: enumeration = splitmix64(seed ^ id) */
@@ -101,6 +102,8 @@ typedef struct cdgmg_options {
                           1, 2, 4, 5 where it divides n_p (else setup fails with
                           CDGMG_ERR_ARG); coarse levels always give each row a group of
                           16 to 64 lanes, chosen by the level's mean row length */
+  int restart;         /* GMRES restart length m (1..200); default 50; the setup then holds
+                          2m + 1 FP64 work vectors (the Arnoldi basis V and Z = B V) */
 } cdgmg_options;
 
 typedef struct cdgmg_solve_info {
@@ -110,7 +113,8 @@ typedef struct cdgmg_solve_info {
   double solve_ms;             /* host wall time of the call, device-synchronised */
   double kernel_ms[CDGMG_NK];  /* summed HIP-event time per kernel class (profile != 0) */
   int64_t kernel_launches[CDGMG_NK];
-  double* history;             /* optional host [history_len]: relative residual per iteration */
+  double* history;             /* optional host [history_len]: relative residual per iteration
+                                  (GMRES: the least-squares residual estimate) */
   int history_len;
 } cdgmg_solve_info;
 

@@ -20,7 +20,7 @@ lib = ctypes.CDLL(_LIBPATH)
 
 OK, NOT_CONVERGED = 0, 1
 MG_FP64, MG_FP32 = 0, 1
-OUTER_FCG, OUTER_PCG = 0, 1
+OUTER_FCG, OUTER_PCG, OUTER_GMRES = 0, 1, 2
 COARSEN_PRIMAL, COARSEN_FLUX = 0, 1
 SWITCH_CONSISTENT, SWITCH_NATURAL = 0, 1
 K_NAMES = ["spmv", "smooth0", "smooth", "restrict", "prolong", "coarse", "vector", "unused"]
@@ -47,7 +47,7 @@ class _Opts(ctypes.Structure):
                 ("nu2", ctypes.c_int), ("mg_precision", ctypes.c_int), ("outer", ctypes.c_int),
                 ("coarsening", ctypes.c_int), ("switch_mode", ctypes.c_int),
                 ("switch_seed", ctypes.c_uint64), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("profile", ctypes.c_int), ("kernel_variant", ctypes.c_int)]
+                ("profile", ctypes.c_int), ("kernel_variant", ctypes.c_int), ("restart", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):

@@ -1016,11 +1016,71 @@ __global__ __launch_bounds__(TPB) void k_update_xr2(int64_t m, const double* __r
   if (threadIdx.x == 0) part[blockIdx.x] = rr;
 }
 
+// ------------------------------------------------------------ GMRES (Sec. 4)
+// Arnoldi basis V and preconditioned basis Z are row-major [vector][ld].
+// k_multi_dot: partial sums of (V_i, w), i < nv, GMV vectors per pass over
+// w; part[i gridDim.x + block].
+constexpr int GMV = 8;
+__global__ __launch_bounds__(TPB) void k_multi_dot(int64_t m, int nv, const double* __restrict__ V, int64_t ldv,
+                                                   const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double sh[TPB / WAVE];
+  for (int g0 = 0; g0 < nv; g0 += GMV) {
+    double acc[GMV];
+#pragma unroll
+    for (int t = 0; t < GMV; ++t) acc[t] = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+      const double wk = w[k];
+#pragma unroll
+      for (int t = 0; t < GMV; ++t)
+        if (g0 + t < nv) acc[t] += V[(int64_t)(g0 + t) * ldv + k] * wk;
+    }
+#pragma unroll
+    for (int t = 0; t < GMV; ++t) {
+      const double s = block_sum(acc[t], sh);
+      if (threadIdx.x == 0 && g0 + t < nv) part[(int64_t)(g0 + t) * gridDim.x + blockIdx.x] = s;
+    }
+  }
+}
+
+// w -= sum_{i < nv} h_i V_i
+__global__ void k_multi_axpy(int64_t m, int nv, const double* __restrict__ V, int64_t ldv,
+                             const double* __restrict__ hc, double* __restrict__ w) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  double s = 0.0;
+  for (int i = 0; i < nv; ++i) s += hc[i] * V[(int64_t)i * ldv + k];
+  w[k] -= s;
+}
+
+// dst = src / sqrt(*nrm2) (in place allowed)
+__global__ void k_scale_vec(int64_t m, const double* src, const double* __restrict__ nrm2, double* dst) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  dst[k] = src[k] / sqrt(*nrm2);
+}
+
+// x_hi + x_lo += sum_{j < nk} y_j Z_j: the correction in FP64, added to the
+// double-double iterate without rounding
+__global__ void k_update_x_multi(int64_t m, int nk, const double* __restrict__ Z, int64_t ldz,
+                                 const double* __restrict__ y, double* __restrict__ xh, double* __restrict__ xl) {
+#pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double c = 0.0;
+  for (int j = 0; j < nk; ++j) c = __builtin_fma(y[j], Z[(int64_t)j * ldz + i], c);
+  double hi, e;
+  two_sum(xh[i], c, hi, e);
+  const double lo = (xl[i] + e);
+  const double nh = (hi + lo);
+  xh[i] = nh;
+  xl[i] = (lo - (nh - hi));
+}
+
 // Component-split outer kernels on A_0 (H wavefronts per slice, the n_f + 1
 // slots unrolled as in the level-0 sweep): q = A p with partial sums of
-// (p, q), (p, r); COMP selects the compensated (Dot2) accumulation.  One
-// partial per slice.
-template <int NP, int H, int NF, bool COMP>
+// (p, q), (p, r) (DOTS); COMP selects the compensated (Dot2) accumulation.
+// One partial per slice.
+template <int NP, int H, int NF, bool COMP, bool DOTS = true>
 __global__ __launch_bounds__(WAVE * H) void k_spmv_dots_hs(int64_t n, const int32_t* __restrict__ cols,
                                                            const double* __restrict__ A, const double* __restrict__ p,
                                                            const double* __restrict__ rr, double* __restrict__ q,
@@ -1062,15 +1122,19 @@ __global__ __launch_bounds__(WAVE * H) void k_spmv_dots_hs(int64_t n, const int3
       const int i = h * NI + t;
       const double qi = COMP ? (s[t] + c[t]) : s[t];
       q[r * NP + i] = qi;
-      const double pi = p[r * NP + i];
-      pq = __builtin_fma(pi, qi, pq);
-      pr = __builtin_fma(pi, rr[r * NP + i], pr);
+      if constexpr (DOTS) {
+        const double pi = p[r * NP + i];
+        pq = __builtin_fma(pi, qi, pq);
+        pr = __builtin_fma(pi, rr[r * NP + i], pr);
+      }
     }
   }
-  pq = block_sum(pq, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = pq;
-  pr = block_sum(pr, sh);
-  if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = pr;
+  if constexpr (DOTS) {
+    pq = block_sum(pq, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = pq;
+    pr = block_sum(pr, sh);
+    if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = pr;
+  }
 }
 
 // true residual rt = b - A (xh + xl), compensated, component-split; partial ||rt||^2 per slice

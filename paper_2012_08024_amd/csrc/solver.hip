@@ -150,6 +150,11 @@ struct cdgmg_handle {
   double* hscal = nullptr;
   int* herr = nullptr;
   hipEvent_t ev_rr = nullptr;  // ||r||^2 of the last update copied to hscal
+  // GMRES: Arnoldi basis V [(m+1) x gm_ld], Z = B V [m x gm_ld], Hessenberg
+  // columns (two Gram-Schmidt passes and the norm), partial sums, y
+  double *gmV = nullptr, *gmZ = nullptr, *gmH = nullptr, *gmPart = nullptr, *gmY = nullptr;
+  double *hgmH = nullptr, *hgmY = nullptr;
+  int64_t gm_ld = 0;
   // profiling
   std::vector<ProfEv> evs;
   std::vector<hipEvent_t> pool;
@@ -457,6 +462,19 @@ int upload_problem(cdgmg_handle* h) {
   for (double** v : {&h->b, &h->x, &h->xl, &h->r, &h->p, &h->q, &h->t1, &h->t2}) {
     RETURN_IF(dalloc(h, v, m));
     HIPCHK(hipMemsetAsync(*v, 0, m * sizeof(double), h->stream));
+  }
+  if (h->o.outer == CDGMG_OUTER_GMRES) {
+    const int R = h->o.restart;
+    h->gm_ld = (int64_t)m;
+    RETURN_IF(dalloc(h, &h->gmV, (size_t)(R + 1) * m));
+    RETURN_IF(dalloc(h, &h->gmZ, (size_t)R * m));
+    RETURN_IF(dalloc(h, &h->gmH, 3 * (size_t)(R + 1)));
+    RETURN_IF(dalloc(h, &h->gmPart, (size_t)(R + 1) * 1024));
+    RETURN_IF(dalloc(h, &h->gmY, (size_t)R));
+    HIPCHK(hipMemsetAsync(h->gmV, 0, (size_t)(R + 1) * m * sizeof(double), h->stream));
+    HIPCHK(hipMemsetAsync(h->gmZ, 0, (size_t)R * m * sizeof(double), h->stream));
+    HIPCHK(hipHostMalloc((void**)&h->hgmH, 3 * (size_t)(R + 1) * sizeof(double)));
+    HIPCHK(hipHostMalloc((void**)&h->hgmY, (size_t)R * sizeof(double)));
   }
   RETURN_IF(dalloc(h, &h->scal, SC_N));
   h->nparts = (int)std::max<int64_t>(1024, (P.N0 + SLICE - 1) / SLICE + 1);
@@ -782,7 +800,7 @@ void collect_profile(cdgmg_handle* h, cdgmg_solve_info* info) {
 // residual once ||r|| dropped 100x) is applied after the following update,
 // before the next V-cycle is enqueued.  Convergence is accepted on the true
 // residual only, at the same iteration as without the look-ahead.
-int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
+int krylov_cg(cdgmg_handle* h, cdgmg_solve_info* info) {
   auto t0 = std::chrono::steady_clock::now();
   const int64_t m = h->N0 * h->np;
   const int np = h->np;
@@ -929,6 +947,177 @@ int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
   return status;
 }
 
+// z = B v into Z_j (FP64)
+void vcycle_into(cdgmg_handle* h, const double* v, double* zj) {
+  void* z = vcycle(h, v, nullptr, nullptr);
+  const int64_t m = h->N0 * h->np;
+  if (h->o.mg_precision == CDGMG_MG_FP32)
+    launch(h, CDGMG_K_VECTOR, k_cast<float, double>, dim3(grid_for(m)), dim3(TPB), m, (const float*)z, zj);
+  else
+    launch(h, CDGMG_K_VECTOR, k_cast<double, double>, dim3(grid_for(m)), dim3(TPB), m, (const double*)z, zj);
+}
+
+// Right-preconditioned restarted GMRES(m) in the flexible form (Sec. 4):
+// each cycle starts from the compensated true residual r = b - A x,
+// v_0 = r / ||r||; step j: z_j = B v_j, w = A z_j, classical Gram-Schmidt
+// against v_0..v_j applied twice (each pass one multi-dot and one multi-axpy
+// over the basis), h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}.  The host
+// applies the Givens rotations to the Hessenberg column, whose last entry is
+// the residual estimate; at the end of a cycle x += Z y (double-double).
+// The V-cycle of step j+1 is enqueued before the host reads column j.
+int krylov_gmres(cdgmg_handle* h, cdgmg_solve_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int64_t m = h->N0 * h->np;
+  const int np = h->np;
+  DLevel& d0 = h->lv[0];
+  const int R = h->o.restart;
+  const int64_t ld = h->gm_ld;
+  double* V = h->gmV;
+  double* Z = h->gmZ;
+  HIPCHK(hipMemsetAsync(h->x, 0, m * sizeof(double), h->stream));
+  HIPCHK(hipMemsetAsync(h->xl, 0, m * sizeof(double), h->stream));
+  double bb = 0.0;
+  dot_into(h, m, h->b, h->b, SC_BB);
+  RETURN_IF(read_scalar(h, SC_BB, &bb));
+  if (!std::isfinite(bb)) {
+    set_error("solve: right-hand side is not finite");
+    return CDGMG_ERR_NAN;
+  }
+  if (!h->ev_rr) HIPCHK(hipEventCreateWithFlags(&h->ev_rr, hipEventDisableTiming));
+  const double nb = std::sqrt(bb);
+  const double tol = h->o.tol;
+  std::vector<double> H((size_t)(R + 1) * R), cs(R), sn(R), g(R + 1), y(R);
+  auto Hij = [&](int i, int j) -> double& { return H[(size_t)i * R + j]; };
+  int it = 0;
+  double rel = 0.0, rel_prev = 0.0, rel_true = 0.0;
+  bool accurate = false;
+  int status = CDGMG_NOT_CONVERGED;
+  const unsigned gd = std::min<unsigned>(1024, grid_for(m));
+  auto reduce_to = [&](int nd, double* out) {
+    launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(RED_T), (const double*)h->gmPart, (int)gd, nd, out, 0, -1);
+  };
+  if (nb == 0.0) status = CDGMG_OK;
+  while (status != CDGMG_OK && it < h->o.max_iter) {
+    // cycle start: r = b - A (x_hi + x_lo), compensated
+    double rt;
+    RETURN_IF(true_residual(h, &rt));
+    if (!std::isfinite(rt)) {
+      set_error("solve: residual is not finite");
+      status = CDGMG_ERR_NAN;
+      break;
+    }
+    rel_true = std::sqrt(rt) / nb;
+    if (rel_true <= tol) {
+      status = CDGMG_OK;
+      break;
+    }
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = std::sqrt(rt);
+    launch(h, CDGMG_K_VECTOR, k_scale_vec, dim3(grid_for(m)), dim3(TPB), m, (const double*)h->r,
+           (const double*)(h->scal + SC_TMP), V);
+    vcycle_into(h, V, Z);
+    int k = 0;
+    for (int j = 0; j < R; ++j) {
+      double* w = V + (int64_t)(j + 1) * ld;
+      const double* zj = Z + (int64_t)j * ld;
+      const unsigned gs = (unsigned)d0.ns;
+      if (accurate) {
+        NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, NF, true, false>, dim3(gs),
+                                              dim3(WAVE * H), d0.n, (const int32_t*)d0.cols, (const double*)d0.A64,
+                                              zj, (const double*)nullptr, w, (double*)nullptr)));
+      } else {
+        NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, NF, false, false>, dim3(gs),
+                                              dim3(WAVE * H), d0.n, (const int32_t*)d0.cols, (const double*)d0.A64,
+                                              zj, (const double*)nullptr, w, (double*)nullptr)));
+      }
+      for (int pass = 0; pass < 2; ++pass) {
+        double* hc = h->gmH + (size_t)pass * (R + 1);
+        launch(h, CDGMG_K_VECTOR, k_multi_dot, dim3(gd), dim3(TPB), m, j + 1, (const double*)V, ld,
+               (const double*)w, h->gmPart);
+        reduce_to(j + 1, hc);
+        launch(h, CDGMG_K_VECTOR, k_multi_axpy, dim3(grid_for(m)), dim3(TPB), m, j + 1, (const double*)V, ld,
+               (const double*)hc, w);
+      }
+      double* nrm2 = h->gmH + 2 * (size_t)(R + 1);
+      launch(h, CDGMG_K_VECTOR, k_dots, dim3(gd), dim3(TPB), m, 1, (const double*)w, (const double*)w,
+             (const double*)nullptr, (const double*)nullptr, h->gmPart);
+      reduce_to(1, nrm2);
+      launch(h, CDGMG_K_VECTOR, k_scale_vec, dim3(grid_for(m)), dim3(TPB), m, (const double*)w,
+             (const double*)nrm2, w);
+      HIPCHK(hipMemcpyAsync(h->hgmH, h->gmH, 3 * (size_t)(R + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                            h->stream));
+      HIPCHK(hipEventRecord(h->ev_rr, h->stream));
+      // look ahead: the V-cycle of step j+1 needs only v_{j+1}
+      const bool expect_done = j >= 2 && rel_prev > 0.0 && rel * (rel / rel_prev) <= tol;
+      const bool ahead = j + 1 < R && it + 1 < h->o.max_iter && !expect_done;
+      if (ahead) vcycle_into(h, w, Z + (int64_t)(j + 1) * ld);
+      HIPCHK(hipEventSynchronize(h->ev_rr));
+      ++it;
+      k = j + 1;
+      const double* hh = h->hgmH;
+      for (int i = 0; i <= j; ++i) Hij(i, j) = hh[i] + hh[R + 1 + i];
+      const double hn = std::sqrt(hh[2 * (R + 1)]);
+      Hij(j + 1, j) = hn;
+      if (!std::isfinite(hn)) {
+        set_error("solve: Arnoldi vector is not finite");
+        status = CDGMG_ERR_NAN;
+        break;
+      }
+      for (int i = 0; i < j; ++i) {
+        const double a = Hij(i, j), b = Hij(i + 1, j);
+        Hij(i, j) = cs[i] * a + sn[i] * b;
+        Hij(i + 1, j) = -sn[i] * a + cs[i] * b;
+      }
+      const double den = std::hypot(Hij(j, j), Hij(j + 1, j));
+      cs[j] = Hij(j, j) / den;
+      sn[j] = Hij(j + 1, j) / den;
+      Hij(j, j) = den;
+      Hij(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      rel_prev = rel;
+      rel = std::fabs(g[j + 1]) / nb;
+      if (rel <= 1e4 * tol) accurate = true;
+      if (info && info->history && it <= info->history_len) info->history[it - 1] = rel;
+      const bool cycle_end = rel <= tol || j + 1 == R || it >= h->o.max_iter || hn == 0.0;
+      if (cycle_end) break;
+      if (!ahead) vcycle_into(h, w, Z + (int64_t)(j + 1) * ld);
+    }
+    if (status == CDGMG_ERR_NAN) break;
+    // y: back substitution on the rotated Hessenberg matrix; x += Z y
+    for (int i = k - 1; i >= 0; --i) {
+      double sacc = g[i];
+      for (int c = i + 1; c < k; ++c) sacc -= Hij(i, c) * y[c];
+      y[i] = sacc / Hij(i, i);
+    }
+    std::copy(y.begin(), y.begin() + k, h->hgmY);
+    HIPCHK(hipMemcpyAsync(h->gmY, h->hgmY, (size_t)k * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    launch(h, CDGMG_K_VECTOR, k_update_x_multi, dim3(grid_for(m)), dim3(TPB), m, k, (const double*)Z, ld,
+           (const double*)h->gmY, h->x, h->xl);
+  }
+  if (status == CDGMG_NOT_CONVERGED && nb != 0.0) {
+    double rt;
+    RETURN_IF(true_residual(h, &rt));
+    rel_true = std::sqrt(rt) / nb;
+    if (rel_true <= tol) status = CDGMG_OK;
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  auto t1 = std::chrono::steady_clock::now();
+  if (info) {
+    info->iterations = it;
+    info->rel_residual = rel_true;
+    info->conv_factor = (it > 0 && rel > 0.0) ? std::pow(rel, 1.0 / it) : 0.0;
+    info->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    collect_profile(h, info);
+  }
+  if (status == CDGMG_NOT_CONVERGED) set_error("solve: not converged within max_iter");
+  return status;
+}
+
+int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
+  return h->o.outer == CDGMG_OUTER_GMRES ? krylov_gmres(h, info) : krylov_cg(h, info);
+}
+
 int check_handle(cdgmg_handle* h) {
   if (!h) {
     set_error("null handle");
@@ -962,6 +1151,7 @@ void cdgmg_default_options(cdgmg_options* o) {
   o->max_iter = 500;
   o->profile = 0;
   o->kernel_variant = 0;
+  o->restart = 50;
 }
 
 int cdgmg_agglomerate(const cdgmg_mesh* mesh, int max_levels, int64_t coarse_dofs_max, int p, uint64_t seed,
@@ -1020,6 +1210,14 @@ int cdgmg_setup(const cdgmg_mesh* mesh, int p, const double* kappa_dev, const cd
   if (o.nu1 < 0 || o.nu2 < 0 || o.nu1 + o.nu2 == 0 || !(o.omega > 0) || !(o.tol > 0) || o.max_iter < 1 ||
       !(o.gamma > 0)) {
     set_error("setup: invalid options");
+    return CDGMG_ERR_ARG;
+  }
+  if (o.outer != CDGMG_OUTER_FCG && o.outer != CDGMG_OUTER_PCG && o.outer != CDGMG_OUTER_GMRES) {
+    set_error("setup: unknown outer solver");
+    return CDGMG_ERR_ARG;
+  }
+  if (o.outer == CDGMG_OUTER_GMRES && (o.restart < 1 || o.restart > 200)) {
+    set_error("setup: GMRES restart must lie in 1..200");
     return CDGMG_ERR_ARG;
   }
   if (o.coarsening != CDGMG_COARSEN_PRIMAL && o.coarsening != CDGMG_COARSEN_FLUX) {
@@ -1251,6 +1449,8 @@ int cdgmg_destroy(cdgmg_handle* h) {
   for (void* p : h->allocs) (void)hipFree(p);
   for (auto e : h->pool) (void)hipEventDestroy(e);
   if (h->ev_rr) (void)hipEventDestroy(h->ev_rr);
+  if (h->hgmH) (void)hipHostFree(h->hgmH);
+  if (h->hgmY) (void)hipHostFree(h->hgmY);
   if (h->hscal) (void)hipHostFree(h->hscal);
   if (h->herr) (void)hipHostFree(h->herr);
   delete h;

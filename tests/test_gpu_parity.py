@@ -13,7 +13,7 @@ import paper_2012_08024_amd as cm  # noqa: E402
 from oracle.adjoint import grad_kappa as oracle_grad_kappa  # noqa: E402
 from oracle.agglomerate import build_hierarchy  # noqa: E402
 from oracle.cdg import CDG  # noqa: E402
-from oracle.krylov import fcg, pcg  # noqa: E402
+from oracle.krylov import fcg, gmres, pcg  # noqa: E402
 from oracle.multigrid import Hierarchy  # noqa: E402
 from workloads import mesh2d_jittered_delaunay, mesh3d_kuhn, source_sine  # noqa: E402
 
@@ -151,6 +151,44 @@ def test_fcg_history_matches_oracle_fp64():
     oracle_rel = [np.linalg.norm(b - H.A[0] @ x) / np.linalg.norm(b) for x in hist[:5]]
     assert np.allclose(info.history[:5], oracle_rel, rtol=1e-6)
     solver.close()
+
+
+@pytest.mark.parametrize("restart", [5, 50])
+@pytest.mark.parametrize("name", ["2d_p2", "3d_p2"])
+def test_gmres_fp64_matches_oracle(name, restart):
+    # the paper's outer solver, right-preconditioned GMRES(m) (Sec. 4), against
+    # the oracle's with the same FP64 V-cycle: residual estimates step by step,
+    # iteration count and solution
+    mesh, solver, cdg, H, kappa, parents, sizes = _build(name, outer=cm.OUTER_GMRES, restart=restart, tol=1e-11)
+    f = source_sine(cdg.nodes_phys().reshape(-1, mesh.dim))
+    b = cdg.M0() @ f
+    hist = []
+    xo, ito, reso = gmres(H.A[0], b, lambda v: H.vcycle(v, 2, 2, 0.7), restart=restart, tol=1e-11, history=hist)
+    u, info = solver.solve(f, history=True)
+    assert info.rel_residual <= 1e-11
+    assert abs(info.iterations - ito) <= 1, (info.iterations, ito)
+    n = min(8, len(hist), info.iterations)
+    assert np.allclose(info.history[:n], hist[:n], rtol=1e-6)
+    ref = spl.spsolve(H.A[0].tocsc(), b)
+    assert np.linalg.norm(u.cpu().numpy() - ref) <= 1e-9 * np.linalg.norm(ref)
+    solver.close()
+
+
+def test_gmres_fp32_mg_reaches_tolerance():
+    mesh, solver, cdg, H, kappa, parents, sizes = _build("2d_p3", mg=cm.MG_FP32, outer=cm.OUTER_GMRES, restart=20,
+                                                         tol=1e-10)
+    f = source_sine(cdg.nodes_phys().reshape(-1, mesh.dim))
+    u, info = solver.solve(f)
+    assert info.rel_residual <= 1e-10
+    ref = spl.spsolve(H.A[0].tocsc(), cdg.M0() @ f)
+    assert np.linalg.norm(u.cpu().numpy() - ref) <= 1e-8 * np.linalg.norm(ref)
+    solver.close()
+
+
+def test_gmres_restart_out_of_range():
+    with pytest.raises(cm.CdgmgError) as ei:
+        _build("2d_p1", outer=cm.OUTER_GMRES, restart=0)
+    assert ei.value.code == -1
 
 
 @pytest.mark.parametrize("name", ["2d_p2", "3d_p2"])

@@ -53,7 +53,7 @@ def test_version_and_default_options():
     o = cm.default_options()
     assert o.gamma == 1e4 and o.omega == 0.7 and o.nu1 == 2 and o.nu2 == 2
     assert o.mg_precision == cm.MG_FP32 and o.outer == cm.OUTER_FCG and o.coarsening == cm.COARSEN_PRIMAL
-    assert o.tol == 1e-10 and o.kernel_variant == 0
+    assert o.tol == 1e-10 and o.kernel_variant == 0 and o.restart == 50
 
 
 @pytest.mark.parametrize("d,n,seed,p,coarse_dofs", [(2, 16, 11, 1, 0), (2, 23, 5, 2, 0), (3, 4, 13, 1, 0),
