@@ -195,6 +195,51 @@ class CDG:
         return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                              shape=(n, n))
 
+    def Cv(self, beta, vel):
+        """Upwind DG convection matrix of beta v . grad u, v constant (the
+        convection-diffusion example of Sec. 5):
+            c(u, w) = sum_K [ (beta v . grad u_K, w_K)_K
+                              - sum_{f in dK, v.n_K < 0} int_f beta (v.n_K) (u_K - u_ext) w_K ds ],
+        u_ext the neighbour's trace on interior facets, 0 on Dirichlet facets
+        and u_K on Neumann facets (no term).  kappa-free; CSR, float64."""
+        ref, d, npb = self.ref, self.d, self.np
+        v = np.asarray(vel, dtype=np.float64)[:d]
+        phi_q = ref.eval(ref.qpts)
+        gref_q = ref.grad(ref.qpts)
+        rows, cols, vals = [], [], []
+
+        def put(e, c, blk):
+            R, Cc = np.meshgrid(np.arange(e * npb, (e + 1) * npb), np.arange(c * npb, (c + 1) * npb),
+                                indexing="ij")
+            rows.append(R.ravel())
+            cols.append(Cc.ravel())
+            vals.append(blk.ravel())
+
+        nbr = {}
+        for (a, ia, b, ib) in self.topo.interior:
+            nbr[a, ia] = b
+            nbr[b, ib] = a
+        for e in range(self.N):
+            w = ref.qwts * self.det[e]
+            g = np.einsum("qnk,kj->qnj", gref_q, self.Jinv[e])
+            vg = g @ v                                         # [nq, np]: v . grad phi_j
+            put(e, e, beta * (phi_q * w[:, None]).T @ vg)
+            for i in range(d + 1):
+                pts, wts, nrm, _ = self.fq[e, i]
+                vn = float(np.dot(v, nrm))
+                if vn >= 0.0:
+                    continue
+                c = nbr.get((e, i), -1)
+                if c < 0 and self.face_bc[e, i] != 0:
+                    continue                                   # Neumann inflow: no jump
+                TK = ref.eval(self.xi_of(e, pts))
+                put(e, e, -beta * vn * (TK.T @ (wts[:, None] * TK)))
+                if c >= 0:
+                    TN = ref.eval(self.xi_of(c, pts))
+                    put(e, c, beta * vn * (TK.T @ (wts[:, None] * TN)))
+        n = self.N * npb
+        return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+
     def A(self, kappa=None):
         """Primal CDG operator A = sum_K kappa_K A^(K) (CSR, float64)."""
         kappa = np.ones(self.N) if kappa is None else np.asarray(kappa, dtype=np.float64)

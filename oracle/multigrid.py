@@ -48,7 +48,9 @@ class Hierarchy:
     element e of level l.
     """
 
-    def __init__(self, cdg, parents, kappa=None, coarsening="flux"):
+    def __init__(self, cdg, parents, kappa=None, coarsening="flux", A0=None):
+        """A0: a given level-0 operator (e.g. diffusion plus convection, or its
+        transpose) in place of cdg.A(kappa); primal coarsening only."""
         self.cdg = cdg
         self.d, self.p, self.np = cdg.d, cdg.p, cdg.np
         self.parents = [np.asarray(p, dtype=np.int64) for p in parents]
@@ -63,6 +65,9 @@ class Hierarchy:
         self._bases()
         self._transfers()
         self.coarsening = coarsening
+        if A0 is not None and coarsening != "primal":
+            raise ValueError("a given A0 is coarsened by the primal (Galerkin) rule only")
+        self.A0_given = None if A0 is None else sp.csr_matrix(A0)
         self._operators()
 
     # -------------------------------------------------------------- bases
@@ -135,7 +140,7 @@ class Hierarchy:
     # ---------------------------------------------------------- operators
     def _operators(self):
         cdg, k = self.cdg, self.kappa
-        A0 = cdg.A(k)
+        A0 = cdg.A(k) if self.A0_given is None else self.A0_given
         self.A = [A0]
         if self.coarsening == "flux":
             M = cdg.Mflux(k)
@@ -161,15 +166,22 @@ class Hierarchy:
             raise ValueError(self.coarsening)
         self.Dinv = [np.linalg.inv(block_diag_blocks(A, self.np)) for A in self.A[:-1]]
         self.Dinv_mat = [block_diag_matrix(D) for D in self.Dinv]
-        try:
-            self.coarse_chol = sla.cho_factor(self.A[-1].toarray(), lower=True)
-        except np.linalg.LinAlgError:
-            self.coarse_chol = None
+        AL = self.A[-1].toarray()
+        self.coarse_chol = self.coarse_lu = None
+        if np.allclose(AL, AL.T, rtol=0, atol=1e-14 * np.abs(AL).max()):
+            try:
+                self.coarse_chol = sla.cho_factor(AL, lower=True)
+            except np.linalg.LinAlgError:
+                pass
+        else:                                  # nonsymmetric (convection): LU
+            self.coarse_lu = sla.lu_factor(AL)
 
     # ------------------------------------------------------------ V-cycle
     def vcycle(self, b, nu1=2, nu2=2, omega=0.7, level=0):
         """One V(nu1, nu2) cycle for A_level x = b from x = 0."""
         if level == self.L:
+            if self.coarse_lu is not None:
+                return sla.lu_solve(self.coarse_lu, b)
             return sla.cho_solve(self.coarse_chol, b)
         A, Dinv = self.A[level], self.Dinv_mat[level]
         x = np.zeros_like(b)
