@@ -104,6 +104,11 @@ typedef struct cdgmg_options {
                           16 to 64 lanes, chosen by the level's mean row length */
   int restart;         /* GMRES restart length m (1..200); default 50; the setup then holds
                           2m + 1 FP64 work vectors (the Arnoldi basis V and Z = B V) */
+  double beta;         /* convection strength of beta v . grad u (Sec. 5, convection-diffusion),
+                          upwind DG fluxes; default 0 (Poisson).  Nonzero beta makes A
+                          nonsymmetric: it requires outer = CDGMG_OUTER_GMRES and primal
+                          coarsening (else setup fails with CDGMG_ERR_ARG) */
+  double velocity[3];  /* constant v (first dim entries used); default (1, 0, 0) */
 } cdgmg_options;
 
 typedef struct cdgmg_solve_info {

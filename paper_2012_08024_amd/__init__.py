@@ -47,7 +47,8 @@ class _Opts(ctypes.Structure):
                 ("nu2", ctypes.c_int), ("mg_precision", ctypes.c_int), ("outer", ctypes.c_int),
                 ("coarsening", ctypes.c_int), ("switch_mode", ctypes.c_int),
                 ("switch_seed", ctypes.c_uint64), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("profile", ctypes.c_int), ("kernel_variant", ctypes.c_int), ("restart", ctypes.c_int)]
+                ("profile", ctypes.c_int), ("kernel_variant", ctypes.c_int), ("restart", ctypes.c_int),
+                ("beta", ctypes.c_double), ("velocity", ctypes.c_double * 3)]
 
 
 class _Info(ctypes.Structure):
@@ -154,7 +155,11 @@ def default_options(**kw):
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(k)
-        setattr(o, k, v)
+        if k == "velocity":
+            v = (list(v) + [0.0, 0.0, 0.0])[:3]
+            o.velocity = (ctypes.c_double * 3)(*v)
+        else:
+            setattr(o, k, v)
     return o
 
 

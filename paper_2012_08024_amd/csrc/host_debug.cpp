@@ -62,8 +62,10 @@ extern "C" int cdgmg_debug_host_operator(const cdgmg_mesh* mesh, int p, const do
     o = *opts;
   else
     cdgmg_default_options(&o);
+  int rc = check_options(o);
+  if (rc) return rc;
   Problem P;
-  int rc = build_problem(*mesh, p, *hier, o, P);
+  rc = build_problem(*mesh, p, *hier, o, P);
   if (rc) return rc;
   const int np = P.np, np2 = np * np, W0 = P.nf + 1;
   const Level& H = P.lv[level];
@@ -92,6 +94,10 @@ extern "C" int cdgmg_debug_host_operator(const cdgmg_mesh* mesh, int p, const do
       } else {
         const double s = hf == 1 ? k[r] : (hf == 0 ? k[c] : 0.0);
         for (int ij = 0; ij < np2; ++ij) dst[ij] = s * ua[ij];
+      }
+      if (!P.UC.empty()) {
+        const double* uc = &P.UC[((size_t)r * W0 + w) * np2];
+        for (int ij = 0; ij < np2; ++ij) dst[ij] += uc[ij];
       }
     }
   // Galerkin products level by level, blocks stored row-major per (row, slot)

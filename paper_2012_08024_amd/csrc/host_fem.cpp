@@ -610,6 +610,66 @@ int build_problem(const cdgmg_mesh& m, int p, const cdgmg_hierarchy& h, const cd
     set_error("setup: singular element mass matrix");
     return CDGMG_ERR_MESH;
   }
+  // ---- upwind convection blocks of beta v . grad u (Sec. 5):
+  //   (beta v . grad u_K, w_K)_K - sum over inflow facets (v . n_K < 0) of
+  //   int_f beta (v . n_K) (u_K - u_ext) w_K,  u_ext = neighbour trace, 0 on
+  //   Dirichlet facets, u_K on Neumann facets (no term)
+  P.beta = o.beta;
+  if (o.beta != 0.0) {
+    P.UC.assign((size_t)N0 * W0 * nb2, 0.0);
+    const double* v = o.velocity;
+    parallel_for(N0, [&](int64_t e0, int64_t e1) {
+      std::vector<double> g(R.nq * np * d), wq(R.nq), TK(R.nfq * np), TN(R.nfq * np), tmp(nb2);
+      double xi[3], phi[32];
+      for (int64_t e = e0; e < e1; ++e) {
+        const int64_t r = iperm0[e];
+        Geo G = geometry(m, e);
+        for (int q = 0; q < R.nq; ++q) wq[q] = R.qw[q] * G.det;
+        double* own = &P.UC[(size_t)r * W0 * nb2];
+        for (int i = 0; i < np; ++i)
+          for (int j = 0; j < np; ++j) {
+            double s = 0.0;
+            for (int q = 0; q < R.nq; ++q) {
+              double vg = 0.0;
+              for (int c = 0; c < d; ++c) {
+                double gc = 0.0;
+                for (int a = 0; a < d; ++a) gc += gref[(q * np + j) * d + a] * G.Ji[a][c];
+                vg += v[c] * gc;
+              }
+              s += wq[q] * phiq[q * np + i] * vg;
+            }
+            own[i * np + j] = o.beta * s;
+          }
+        for (int i = 0; i < nf; ++i) {
+          const int32_t nb = T.nbr[e * nf + i];
+          if (nb < 0 && m.face_bc[e * nf + i] != 0) continue;
+          Facet F = facet(m, R, e, i);
+          double vn = 0.0;
+          for (int c = 0; c < d; ++c) vn += v[c] * F.n[c];
+          if (vn >= 0.0) continue;
+          Geo GN{};
+          if (nb >= 0) GN = geometry(m, nb);
+          for (int q = 0; q < R.nfq; ++q) {
+            to_ref(G, d, &F.x[q * d], xi);
+            R.eval(xi, phi);
+            for (int n = 0; n < np; ++n) TK[q * np + n] = phi[n];
+            if (nb >= 0) {
+              to_ref(GN, d, &F.x[q * d], xi);
+              R.eval(xi, phi);
+              for (int n = 0; n < np; ++n) TN[q * np + n] = phi[n];
+            }
+          }
+          matTmulM(np, TK.data(), F.w.data(), TK.data(), R.nfq, tmp.data());
+          for (int k = 0; k < nb2; ++k) own[k] += -o.beta * vn * tmp[k];
+          if (nb >= 0) {
+            matTmulM(np, TK.data(), F.w.data(), TN.data(), R.nfq, tmp.data());
+            double* off = &P.UC[((size_t)r * W0 + i + 1) * nb2];
+            for (int k = 0; k < nb2; ++k) off[k] = o.beta * vn * tmp[k];
+          }
+        }
+      }
+    });
+  }
   // reverse slots
   for (int64_t r = 0; r < N0; ++r) {
     const int64_t e = perm0[r];
@@ -850,6 +910,37 @@ int build_problem(const cdgmg_mesh& m, int p, const cdgmg_hierarchy& h, const cd
         c.plan_ptr[c.row_blk[I] + t + 1] = (int64_t)c.plan_e.size();
       }
     }
+  }
+  return CDGMG_OK;
+}
+
+// validation of the options shared by setup and the host operator check
+int check_options(const cdgmg_options& o) {
+  if (o.nu1 < 0 || o.nu2 < 0 || o.nu1 + o.nu2 == 0 || !(o.omega > 0) || !(o.tol > 0) || o.max_iter < 1 ||
+      !(o.gamma > 0)) {
+    set_error("setup: invalid options");
+    return CDGMG_ERR_ARG;
+  }
+  if (o.outer != CDGMG_OUTER_FCG && o.outer != CDGMG_OUTER_PCG && o.outer != CDGMG_OUTER_GMRES) {
+    set_error("setup: unknown outer solver");
+    return CDGMG_ERR_ARG;
+  }
+  if (o.outer == CDGMG_OUTER_GMRES && (o.restart < 1 || o.restart > 200)) {
+    set_error("setup: GMRES restart must lie in 1..200");
+    return CDGMG_ERR_ARG;
+  }
+  if (!std::isfinite(o.beta) || !std::isfinite(o.velocity[0]) || !std::isfinite(o.velocity[1]) ||
+      !std::isfinite(o.velocity[2])) {
+    set_error("setup: beta and velocity must be finite");
+    return CDGMG_ERR_ARG;
+  }
+  if (o.beta != 0.0 && (o.outer != CDGMG_OUTER_GMRES || o.coarsening != CDGMG_COARSEN_PRIMAL)) {
+    set_error("setup: convection (beta != 0) makes A nonsymmetric: it needs outer GMRES and primal coarsening");
+    return CDGMG_ERR_ARG;
+  }
+  if (o.coarsening != CDGMG_COARSEN_PRIMAL && o.coarsening != CDGMG_COARSEN_FLUX) {
+    set_error("setup: unknown coarsening");
+    return CDGMG_ERR_ARG;
   }
   return CDGMG_OK;
 }

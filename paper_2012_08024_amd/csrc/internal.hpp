@@ -130,11 +130,14 @@ struct Problem {
   std::vector<double> Mblk;           // [N0][np][np] element mass matrices
   std::vector<double> Gblk;           // [d][N0][nf+1][np][np] flux-form gradient (kappa-free)
   std::vector<double> nodes;          // [N0 caller order][np][d]
+  double beta = 0.0;                  // convection strength (0: none)
+  std::vector<double> UC;             // [N0][nf+1][np][np] upwind convection blocks (beta != 0)
   bool flux = false;
   std::vector<FluxPlan> fp;           // [L]: plan building level l+1 from level l
   std::vector<double> G0;             // [d][nG0][np][np] block-major G_0 in the FluxPlan[0] pattern
 };
 
+int check_options(const cdgmg_options& o);
 int build_problem(const cdgmg_mesh& m, int p, const cdgmg_hierarchy& h, const cdgmg_options& o,
                   Problem& P);
 void flux_g0(Problem& P);

@@ -5,14 +5,16 @@
 namespace cdg {
 
 // =============================================================== setup kernels
-// K9: A_0 = sum_e kappa_e A^(e) from the kappa-free hosted blocks.
-//   A(r, 0)  = kappa_r UA(r, 0) + sum_{w: neighbour c_w hosts} kappa_c UH(c, revslot)
-//   A(r, w)  = kappa_host UA(r, w)
+// K9: A_0 = sum_e kappa_e A^(e) from the kappa-free hosted blocks, plus the
+// kappa-free upwind convection blocks UC when present (UC may be null).
+//   A(r, 0)  = kappa_r UA(r, 0) + sum_{w: neighbour c_w hosts} kappa_c UH(c, revslot) + UC(r, 0)
+//   A(r, w)  = kappa_host UA(r, w) + UC(r, w)
 template <int NP>
 __global__ void k_assemble_A0(int64_t n, int W, const int32_t* __restrict__ cols, const int64_t* __restrict__ sblk,
                               const double* __restrict__ UA, const double* __restrict__ UH,
                               const int8_t* __restrict__ hostflag, const int8_t* __restrict__ revslot,
-                              const double* __restrict__ kappa, double* __restrict__ A) {
+                              const double* __restrict__ kappa, const double* __restrict__ UC,
+                              double* __restrict__ A) {
   constexpr int NP2 = NP * NP;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
@@ -25,7 +27,7 @@ __global__ void k_assemble_A0(int64_t n, int W, const int32_t* __restrict__ cols
     const double s = hf == 1 ? kr : (hf == 0 ? kappa[c] : 0.0);
     for (int ij = 0; ij < NP2; ++ij) {
       const int64_t o = blk_off(B, w, NP2, ij, lane);
-      A[o] = s * UA[o];
+      A[o] = s * UA[o] + (UC ? UC[o] : 0.0);
     }
   }
   for (int ij = 0; ij < NP2; ++ij) {
@@ -36,7 +38,32 @@ __global__ void k_assemble_A0(int64_t n, int W, const int32_t* __restrict__ cols
       const int rs = revslot[r * W + w];
       acc += kappa[c] * UH[blk_off(sblk[c / WAVE], rs, NP2, ij, c % WAVE)];
     }
+    if (UC) acc += UC[blk_off(B, 0, NP2, ij, lane)];
     A[blk_off(B, 0, NP2, ij, lane)] = acc;
+  }
+}
+
+// A_0^T in the same layout: out(r, 0) = A(r, 0)^T, out(r, w) = A(c, rs)^T for
+// the neighbour c = cols(r, w) whose slot rs = revslot(r, w) holds A(c, r);
+// slots without a neighbour (rs = 0) stay zero
+template <int NP>
+__global__ void k_transpose_A0(int64_t n, int W, const int64_t* __restrict__ sblk, const int32_t* __restrict__ cols,
+                               const int8_t* __restrict__ revslot, const double* __restrict__ A,
+                               double* __restrict__ out) {
+  constexpr int NP2 = NP * NP;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int lane = (int)(r % WAVE);
+  const int64_t B = sblk[r / WAVE];
+  for (int w = 0; w < W; ++w) {
+    const int rs = w == 0 ? 0 : revslot[r * W + w];
+    const int32_t c = w == 0 ? (int32_t)r : cols[B + (int64_t)WAVE * w + lane];
+    const bool has = w == 0 || rs > 0;
+    const int64_t Bc = sblk[c / WAVE];
+    for (int i = 0; i < NP; ++i)
+      for (int j = 0; j < NP; ++j)
+        out[blk_off(B, w, NP2, i * NP + j, lane)] =
+            has ? A[blk_off(Bc, rs, NP2, j * NP + i, (int)(c % WAVE))] : 0.0;
   }
 }
 
@@ -519,7 +546,7 @@ __global__ __launch_bounds__(TPB) void k_dense_gemv(int64_t n, int64_t ld, const
 //     x <- (1 - omega) x + omega (bt - At_off x),   bt = D^{-1} b,  At = D^{-1} A,
 // where the diagonal block of At is the identity and is not stored, and the
 // restricted residual L_e^T (b - A x)_e as Lt_e^T (bt - At x)_e with
-// Lt_e = D_e L_e.  The sweeps thus read neither D^{-1} nor the diagonal block.
+// Lt_e = D_e^T L_e.  The sweeps thus read neither D^{-1} nor the diagonal block.
 //
 // Level 0 (component-split): H wavefronts per 64-row slice, wavefront h owns
 // output components [h NI, (h+1) NI), NI = n_p / H (H = 1 is one thread per
@@ -827,8 +854,9 @@ __global__ void k_scale_wpr(int64_t nnzb, const int32_t* __restrict__ blk_row, c
   R[(o - r) * NP2 + (int64_t)i * K + (w - 1) * NP + j] = (T)acc;
 }
 
-// Lt_e = D_e L_e (D_e the diagonal block of A), per-row layout; one thread
-// per (row, i, j), rows fastest
+// Lt_e = D_e^T L_e (D_e the diagonal block of A), per-row layout, so that
+// Lt^T (D^{-1} r) = L^T r also for a nonsymmetric D; one thread per
+// (row, i, j), rows fastest
 template <typename T, int NP>
 __global__ void k_scale_L(int64_t n, const int64_t* __restrict__ sblk, const double* __restrict__ A,
                           const double* __restrict__ L, T* __restrict__ Lt) {
@@ -844,7 +872,7 @@ __global__ void k_scale_L(int64_t n, const int64_t* __restrict__ sblk, const dou
   const int64_t B = sblk[s];
   double acc = 0.0;
 #pragma unroll
-  for (int m = 0; m < NP; ++m) acc += A[blk_off(B, 0, NP2, i * NP + m, lane)] * L[row_off(r, NP2, m * NP + j)];
+  for (int m = 0; m < NP; ++m) acc += A[blk_off(B, 0, NP2, m * NP + i, lane)] * L[row_off(r, NP2, m * NP + j)];
   Lt[row_off(r, NP2, ij)] = (T)acc;
 }
 

@@ -136,6 +136,9 @@ struct cdgmg_handle {
   size_t bytes = 0;
   // level 0
   double *UA = nullptr, *UH = nullptr, *M = nullptr, *kappa = nullptr;
+  double* UC = nullptr;    // upwind convection blocks (beta != 0), operator layout
+  double* Atmp = nullptr;  // A_0^T staging (beta != 0)
+  bool transposed = false; // the levels hold A_l^T
   int8_t *hostflag = nullptr, *revslot = nullptr;
   // coarsest
   int64_t nd = 0, ld = 0;
@@ -440,6 +443,11 @@ int upload_problem(cdgmg_handle* h) {
   RETURN_IF(upload(h, &h->hostflag, P.hostflag));
   RETURN_IF(upload(h, &h->revslot, P.revslot));
   RETURN_IF(upload(h, &h->M, to_rows(P.Mblk, P.N0, np2)));
+  if (!P.UC.empty()) {
+    RETURN_IF(upload(h, &h->UC, to_sliced(P.UC, P.lv[0], h->W0, np2)));
+    RETURN_IF(dalloc(h, &h->Atmp, (size_t)h->lv[0].slots * np2));
+    std::vector<double>().swap(P.UC);
+  }
   RETURN_IF(dalloc(h, &h->kappa, P.N0));
   // coarsest dense
   h->nd = h->lv[P.L].n * np;
@@ -520,19 +528,33 @@ void prescale(cdgmg_handle* h) {
 }
 
 // kappa -> A_0 -> (D^{-1}, Galerkin) per level -> prescaled V-cycle operators
-// -> coarsest inverse
-int build_operators(cdgmg_handle* h, const double* kappa_dev) {
+// -> coarsest inverse.  kappa_dev null: rebuild from the stored kappa.
+// transposed: every level holds A_l^T (A_0^T, then the same Galerkin products,
+// since (L^T A L)^T = L^T A^T L), for the adjoint of a nonsymmetric operator.
+int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed = false) {
   const int np = h->np, np2 = np * np;
   DLevel& l0 = h->lv[0];
-  launch(h, -1, k_kappa_perm, dim3(grid_for(h->N0)), dim3(TPB), h->N0, (const int32_t*)l0.perm, kappa_dev,
-         h->kappa, h->err);
-  RETURN_IF(check_err(h, CDGMG_ERR_ARG, "setup: kappa must be positive and finite"));
+  if (kappa_dev) {
+    launch(h, -1, k_kappa_perm, dim3(grid_for(h->N0)), dim3(TPB), h->N0, (const int32_t*)l0.perm, kappa_dev,
+           h->kappa, h->err);
+    RETURN_IF(check_err(h, CDGMG_ERR_ARG, "setup: kappa must be positive and finite"));
+  }
   NP_DISPATCH(np, launch(h, -1, k_assemble_A0<NP>, dim3(grid_for(h->N0)), dim3(TPB), h->N0, h->W0,
                          (const int32_t*)l0.cols, (const int64_t*)l0.sblk, (const double*)h->UA,
                          (const double*)h->UH, (const int8_t*)h->hostflag, (const int8_t*)h->revslot,
-                         (const double*)h->kappa, l0.A64));
+                         (const double*)h->kappa, (const double*)h->UC, l0.A64));
+  if (transposed) {
+    NP_DISPATCH(np, launch(h, -1, k_transpose_A0<NP>, dim3(grid_for(h->N0)), dim3(TPB), h->N0, h->W0,
+                           (const int64_t*)l0.sblk, (const int32_t*)l0.cols, (const int8_t*)h->revslot,
+                           (const double*)l0.A64, h->Atmp));
+    HIPCHK(hipMemcpyAsync(l0.A64, h->Atmp, (size_t)l0.slots * np2 * sizeof(double), hipMemcpyDeviceToDevice,
+                          h->stream));
+  }
+  h->transposed = transposed;
   const bool flux = h->P.flux;
-  const int definite = flux ? 0 : 1;
+  // the Galerkin hierarchy of the symmetric Poisson operator is SPD: its
+  // pivots must be positive; otherwise they must be nonzero
+  const int definite = (flux || h->P.beta != 0.0) ? 0 : 1;
   const int tpb = std::min(1024, ((np2 + 63) / 64) * 64);
   if (flux)
     NP_DISPATCH(np, launch(h, -1, k_mass_kappa<NP>, dim3(grid_for(h->N0)), dim3(TPB), h->N0, (const double*)h->M,
@@ -1118,6 +1140,13 @@ int krylov(cdgmg_handle* h, cdgmg_solve_info* info) {
   return h->o.outer == CDGMG_OUTER_GMRES ? krylov_gmres(h, info) : krylov_cg(h, info);
 }
 
+// a nonsymmetric operator keeps one direction on the device at a time: the
+// adjoint solve rebuilds the transposed hierarchy, forward calls rebuild A
+int ensure_direction(cdgmg_handle* h, bool transposed) {
+  if (h->transposed == transposed) return CDGMG_OK;
+  return build_operators(h, nullptr, transposed);
+}
+
 int check_handle(cdgmg_handle* h) {
   if (!h) {
     set_error("null handle");
@@ -1152,6 +1181,8 @@ void cdgmg_default_options(cdgmg_options* o) {
   o->profile = 0;
   o->kernel_variant = 0;
   o->restart = 50;
+  o->beta = 0.0;
+  o->velocity[0] = 1.0;
 }
 
 int cdgmg_agglomerate(const cdgmg_mesh* mesh, int max_levels, int64_t coarse_dofs_max, int p, uint64_t seed,
@@ -1207,23 +1238,7 @@ int cdgmg_setup(const cdgmg_mesh* mesh, int p, const double* kappa_dev, const cd
     o = *opts;
   else
     cdgmg_default_options(&o);
-  if (o.nu1 < 0 || o.nu2 < 0 || o.nu1 + o.nu2 == 0 || !(o.omega > 0) || !(o.tol > 0) || o.max_iter < 1 ||
-      !(o.gamma > 0)) {
-    set_error("setup: invalid options");
-    return CDGMG_ERR_ARG;
-  }
-  if (o.outer != CDGMG_OUTER_FCG && o.outer != CDGMG_OUTER_PCG && o.outer != CDGMG_OUTER_GMRES) {
-    set_error("setup: unknown outer solver");
-    return CDGMG_ERR_ARG;
-  }
-  if (o.outer == CDGMG_OUTER_GMRES && (o.restart < 1 || o.restart > 200)) {
-    set_error("setup: GMRES restart must lie in 1..200");
-    return CDGMG_ERR_ARG;
-  }
-  if (o.coarsening != CDGMG_COARSEN_PRIMAL && o.coarsening != CDGMG_COARSEN_FLUX) {
-    set_error("setup: unknown coarsening");
-    return CDGMG_ERR_ARG;
-  }
+  RETURN_IF(check_options(o));
   cdgmg_handle* h = new (std::nothrow) cdgmg_handle();
   if (!h) return CDGMG_ERR_NOMEM;
   h->o = o;
@@ -1261,13 +1276,14 @@ int cdgmg_setup(const cdgmg_mesh* mesh, int p, const double* kappa_dev, const cd
 int cdgmg_update_kappa(cdgmg_handle* h, const double* kappa_dev) {
   RETURN_IF(check_handle(h));
   set_error("");
-  RETURN_IF(build_operators(h, kappa_dev));
+  RETURN_IF(build_operators(h, kappa_dev, false));
   return CDGMG_OK;
 }
 
 int cdgmg_solve(cdgmg_handle* h, const double* f_dev, double* u_dev, cdgmg_solve_info* info) {
   RETURN_IF(check_handle(h));
   set_error("");
+  RETURN_IF(ensure_direction(h, false));
   reset_profile(h);
   const int np = h->np;
   DLevel& d = h->lv[0];
@@ -1283,6 +1299,7 @@ int cdgmg_solve(cdgmg_handle* h, const double* f_dev, double* u_dev, cdgmg_solve
 int cdgmg_solve_rhs(cdgmg_handle* h, const double* b_dev, double* x_dev, cdgmg_solve_info* info) {
   RETURN_IF(check_handle(h));
   set_error("");
+  RETURN_IF(ensure_direction(h, false));
   reset_profile(h);
   const int np = h->np;
   DLevel& d = h->lv[0];
@@ -1296,7 +1313,24 @@ int cdgmg_solve_rhs(cdgmg_handle* h, const double* b_dev, double* x_dev, cdgmg_s
 }
 
 int cdgmg_solve_transpose(cdgmg_handle* h, const double* g_dev, double* lam_dev, cdgmg_solve_info* info) {
-  return cdgmg_solve_rhs(h, g_dev, lam_dev, info);
+  RETURN_IF(check_handle(h));
+  if (h->P.beta == 0.0) return cdgmg_solve_rhs(h, g_dev, lam_dev, info);  // A = A^T
+  set_error("");
+  // A^T lambda = g with the transposed hierarchy; the V-cycle on A_l^T with the
+  // pre- and post-sweep counts exchanged is the transpose of the forward one
+  RETURN_IF(ensure_direction(h, true));
+  reset_profile(h);
+  const int np = h->np;
+  DLevel& d = h->lv[0];
+  launch(h, -1, k_permute<double>, dim3(grid_for(h->N0 * np)), dim3(TPB), h->N0, np, (const int32_t*)d.perm,
+         g_dev, h->b, 0);
+  std::swap(h->o.nu1, h->o.nu2);
+  int rc = krylov(h, info);
+  std::swap(h->o.nu1, h->o.nu2);
+  launch(h, -1, k_out_dd, dim3(grid_for(h->N0 * np)), dim3(TPB), h->N0, np, (const int32_t*)d.perm,
+         (const double*)h->x, (const double*)h->xl, lam_dev);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return rc;
 }
 
 int cdgmg_grad_kappa(cdgmg_handle* h, const double* u_dev, const double* lam_dev, double* gk_dev) {
@@ -1332,6 +1366,7 @@ int cdgmg_apply_A(cdgmg_handle* h, int level, int precision, const void* x_dev, 
     set_error("apply_A: invalid level or precision");
     return CDGMG_ERR_ARG;
   }
+  RETURN_IF(ensure_direction(h, false));
   DLevel& d = h->lv[level];
   const int np = h->np;
   if (precision == 0) {
@@ -1359,6 +1394,7 @@ int cdgmg_apply_A(cdgmg_handle* h, int level, int precision, const void* x_dev, 
 
 int cdgmg_vcycle(cdgmg_handle* h, const double* r_dev, double* z_dev) {
   RETURN_IF(check_handle(h));
+  RETURN_IF(ensure_direction(h, false));
   DLevel& d = h->lv[0];
   const int np = h->np;
   launch(h, -1, k_permute<double>, dim3(grid_for(h->N0 * np)), dim3(TPB), h->N0, np, (const int32_t*)d.perm,
@@ -1387,6 +1423,7 @@ int cdgmg_export_operator(cdgmg_handle* h, int level, int64_t* nnzb, int64_t* ro
     set_error("export_operator: invalid argument");
     return CDGMG_ERR_ARG;
   }
+  RETURN_IF(ensure_direction(h, false));
   const Level& H = h->P.lv[level];
   const DLevel& D = h->lv[level];
   const int np = h->np, np2 = np * np, nf = h->P.nf;

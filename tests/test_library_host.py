@@ -172,3 +172,27 @@ def test_second_neighbour_count_matches_oracle_C(d, n, mode, seed):
         count += sum(1 for b in cols if b > a and b not in nbr[a])
     assert count == second_neighbour_pairs(m.e2v, hosted)
     assert count > 0
+
+
+@pytest.mark.parametrize("d,n,p", [(2, 9, 2), (3, 3, 1)])
+def test_host_level_operators_with_convection(d, n, p):
+    # upwind convection beta v . grad u (Sec. 5): level operators of A + C_v
+    m = mesh2d_jittered_delaunay(n, 1) if d == 2 else mesh3d_kuhn(n, 1)
+    parents, sizes = cm.agglomerate(m, 3, 5, p=p)
+    kappa = np.random.default_rng(7).uniform(0.5, 2.0, m.n_elem)
+    vel = (1.0, 0.4, -0.2)[:d]
+    cdg = CDG(m.coords, m.e2v, m.face_bc, p)
+    H = Hierarchy(cdg, parents, kappa=kappa, coarsening="primal", A0=cdg.A(kappa) + cdg.Cv(2.5, vel))
+    for l in range(len(sizes)):
+        A = cm.bsr_to_scipy(*cm.debug_host_operator(m, p, kappa, parents, sizes, l, beta=2.5, velocity=vel,
+                                                    outer=cm.OUTER_GMRES))
+        R = H.A[l]
+        assert abs(A - R).max() <= 1e-11 * abs(R).max(), (l, abs(A - R).max())
+
+
+def test_convection_option_checks():
+    m = mesh2d_jittered_delaunay(6, 1)
+    parents, sizes = cm.agglomerate(m, 2, 1, p=1)
+    with pytest.raises(cm.CdgmgError) as ei:  # CG needs a symmetric operator
+        cm.debug_host_operator(m, 1, np.ones(m.n_elem), parents, sizes, 0, beta=1.0)
+    assert ei.value.code == -1
