@@ -112,9 +112,10 @@ def main():
     ap.add_argument("--outer", choices=["fcg", "pcg", "gmres"], default="fcg",
                     help="outer Krylov solver (the metric is quoted with fcg)")
     ap.add_argument("--restart", type=int, default=50, help="GMRES restart length")
-    ap.add_argument("--study", choices=["coarsening", "switch"],
-                    help="instead of the benchmark: primal vs flux coarsening over mesh size and gamma, or "
-                         "consistent vs natural switch; prints one JSON line with the table")
+    ap.add_argument("--study", choices=["coarsening", "coarsening-paper", "switch", "switch-paper", "convection"],
+                    help="instead of the benchmark: primal vs flux coarsening over mesh size and gamma, "
+                         "consistent vs natural switch (workload or the paper's solver settings), or "
+                         "convection-diffusion under refinement; prints one JSON line with the table")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the solve is single-GPU; "
@@ -125,8 +126,12 @@ def main():
 
         from paper_2012_08024_amd import studies
         torch.cuda.set_device(0)
-        fn = studies.study_coarsening if args.study == "coarsening" else studies.study_switch
-        rows = fn(log=log)
+        kind, _, setting = args.study.partition("-")
+        if kind == "convection":
+            rows = studies.study_convection(log=log)
+        else:
+            fn = studies.study_coarsening if kind == "coarsening" else studies.study_switch
+            rows = fn(setting=setting or "workload", log=log)
         print(json.dumps({"study": args.study, "data": "synthetic", "rows": rows}), flush=True)
         return
 

@@ -10,17 +10,27 @@
   element that hosts two interior facets couples the two neighbours across
   them in C (second neighbours); the count of such pairs and the iteration
   counts are compared.
+* Convection-diffusion (Sec. 5): beta v . grad u with v = (1, 0), f = 1 and
+  zero Dirichlet data, GMRES iterations under refinement for a range of beta.
 
-Both run through the C ABI on the current GPU; the hierarchy is agglomerated
-until one element remains (Sec. 5) and the V-cycle runs in FP64, so that
-only the coarse operators differ between cases.
+All run through the C ABI on the current GPU with the V-cycle in FP64, so
+that only the operators differ between cases; the hierarchy is agglomerated
+until one element remains (Sec. 5).  Two solver settings:
+  "paper":    p = 1, V(0, 3) block Jacobi with damping 2/3, right-preconditioned
+              GMRES(50), tolerance 1e-8 (the settings of Sec. 5);
+  "workload": V(2, 2) with damping 0.7, FCG(1), tolerance 1e-10.
 """
 import time
 
 import numpy as np
 
-from . import (COARSEN_FLUX, COARSEN_PRIMAL, MG_FP64, SWITCH_CONSISTENT, SWITCH_NATURAL, CdgmgError, Solver,
-               agglomerate, n_basis, switch)
+from . import (COARSEN_FLUX, COARSEN_PRIMAL, MG_FP64, OUTER_FCG, OUTER_GMRES, SWITCH_CONSISTENT, SWITCH_NATURAL,
+               CdgmgError, Solver, agglomerate, n_basis, switch)
+
+SETTINGS = {
+    "paper": dict(nu1=0, nu2=3, omega=2.0 / 3.0, outer=OUTER_GMRES, restart=50, tol=1e-8),
+    "workload": dict(nu1=2, nu2=2, omega=0.7, outer=OUTER_FCG, tol=1e-10),
+}
 
 
 def face_neighbours(e2v):
@@ -56,12 +66,15 @@ def second_neighbour_pairs(e2v, hosted):
     return len(pairs)
 
 
-def _solve_case(mesh, p, parents, sizes, f_of_nodes, max_iter, **opts):
+def _solve_case(mesh, p, parents, sizes, f_of_nodes, max_iter, setting, **opts):
     import torch
     kappa = torch.ones(mesh.n_elem, dtype=torch.float64, device="cuda")
+    cfg = dict(SETTINGS[setting])
+    cfg.update(opts)
+    tol = cfg["tol"]
     row = {}
     try:
-        s = Solver(mesh, p, kappa, parents, sizes, mg_precision=MG_FP64, tol=1e-10, max_iter=max_iter, **opts)
+        s = Solver(mesh, p, kappa, parents, sizes, mg_precision=MG_FP64, max_iter=max_iter, **cfg)
     except CdgmgError as e:
         row.update(status="setup failed (%d)" % e.code)
         return row
@@ -75,7 +88,7 @@ def _solve_case(mesh, p, parents, sizes, f_of_nodes, max_iter, **opts):
         torch.cuda.synchronize()
         row.update(iterations=info.iterations, rel_residual=info.rel_residual,
                    solve_ms=(time.perf_counter() - t0) * 1e3,
-                   status="converged" if info.rel_residual <= 1e-10 else "not converged")
+                   status="converged" if info.rel_residual <= tol else "not converged")
     except CdgmgError as e:
         row.update(status="breakdown (%d)" % e.code)
     finally:
@@ -83,31 +96,38 @@ def _solve_case(mesh, p, parents, sizes, f_of_nodes, max_iter, **opts):
     return row
 
 
-def study_coarsening(ns=(8, 16, 32, 64, 128), ps=(1, 2), gammas=(1e1, 1e2, 1e3, 1e4), seed=1, max_iter=300,
-                     log=print):
-    """Primal vs flux coarsening on 2D jittered Delaunay meshes refined by 2."""
-    from workloads import mesh2d_jittered_delaunay, source_sine
+def study_coarsening(setting="workload", ns=(8, 16, 32, 64, 128), ps=None, gammas=(1e1, 1e2, 1e3, 1e4), seed=1,
+                     max_iter=300, log=print):
+    """Primal vs flux coarsening under refinement.  "workload": 2D jittered
+    Delaunay meshes, all boundaries Dirichlet, p = 1, 2.  "paper": the square
+    of Sec. 5.1 (uniform grid, here split into right triangles) with Neumann
+    sides x = 0, 1 and Dirichlet y = 0, 1, p = 1."""
+    from workloads import mesh2d_jittered_delaunay, mesh2d_square_neumann_sides, source_sine
+    if ps is None:
+        ps = (1,) if setting == "paper" else (1, 2)
     rows = []
     for p in ps:
         for n in ns:
-            mesh = mesh2d_jittered_delaunay(n, seed)
+            mesh = mesh2d_square_neumann_sides(n) if setting == "paper" else mesh2d_jittered_delaunay(n, seed)
             parents, sizes = agglomerate(mesh, 64, seed, p=p)
             for gamma in gammas:
                 for name, c in (("primal", COARSEN_PRIMAL), ("flux", COARSEN_FLUX)):
-                    row = dict(p=p, n=n, elements=int(mesh.n_elem), levels=len(sizes), gamma=gamma,
+                    row = dict(setting=setting, p=p, n=n, elements=int(mesh.n_elem), levels=len(sizes), gamma=gamma,
                                coarsening=name)
-                    row.update(_solve_case(mesh, p, parents, sizes, source_sine, max_iter, gamma=gamma,
+                    row.update(_solve_case(mesh, p, parents, sizes, source_sine, max_iter, setting, gamma=gamma,
                                            coarsening=c))
-                    log("coarsening p=%d n=%d gamma=%.0e %s: %s" % (p, n, gamma, name, row))
+                    log("coarsening %s p=%d n=%d gamma=%.0e %s: %s" % (setting, p, n, gamma, name, row))
                     rows.append(row)
     return rows
 
 
-def study_switch(cases=((2, 16, 2), (2, 32, 2), (2, 64, 2), (2, 128, 2), (3, 4, 1), (3, 8, 1), (3, 12, 1)),
-                 seed=1, natural_seed=0, max_iter=300, log=print):
+def study_switch(setting="workload", cases=None, seed=1, natural_seed=0, max_iter=300, log=print):
     """Consistent vs natural switch: second-neighbour pairs of C and
     iterations with primal and flux coarsening."""
     from workloads import mesh2d_jittered_delaunay, mesh3d_kuhn, source_sine
+    if cases is None:
+        p2 = 1 if setting == "paper" else 2
+        cases = ((2, 16, p2), (2, 32, p2), (2, 64, p2), (2, 128, p2), (3, 4, 1), (3, 8, 1), (3, 12, 1))
     rows = []
     for d, n, p in cases:
         mesh = mesh2d_jittered_delaunay(n, seed) if d == 2 else mesh3d_kuhn(n, seed)
@@ -116,10 +136,33 @@ def study_switch(cases=((2, 16, 2), (2, 32, 2), (2, 64, 2), (2, 128, 2), (3, 4, 
             hosted = switch(mesh, mode=mode, seed=natural_seed)
             pairs = second_neighbour_pairs(mesh.e2v, hosted)
             for cname, c in (("primal", COARSEN_PRIMAL), ("flux", COARSEN_FLUX)):
-                row = dict(d=d, n=n, p=p, n_p=n_basis(d, p), elements=int(mesh.n_elem), levels=len(sizes),
-                           switch=sname, second_neighbour_pairs=pairs, coarsening=cname)
-                row.update(_solve_case(mesh, p, parents, sizes, source_sine, max_iter, coarsening=c,
+                row = dict(setting=setting, d=d, n=n, p=p, n_p=n_basis(d, p), elements=int(mesh.n_elem),
+                           levels=len(sizes), switch=sname, second_neighbour_pairs=pairs, coarsening=cname)
+                row.update(_solve_case(mesh, p, parents, sizes, source_sine, max_iter, setting, coarsening=c,
                                        switch_mode=mode, switch_seed=natural_seed))
-                log("switch d=%d n=%d %s %s: %s" % (d, n, sname, cname, row))
+                log("switch %s d=%d n=%d %s %s: %s" % (setting, d, n, sname, cname, row))
                 rows.append(row)
+    return rows
+
+
+def study_convection(ns=(8, 16, 32, 64, 128), betas=(0.0, 0.1, 1.0, 10.0, 100.0), p=1, seed=1, max_iter=500,
+                     log=print):
+    """GMRES iterations for beta v . grad u - laplace u = 1 (v = (1, 0), zero
+    Dirichlet data) under refinement, the paper's settings (2D jittered
+    Delaunay meshes stand in for the airfoil mesh)."""
+    from workloads import mesh2d_jittered_delaunay
+
+    def ones(x):
+        return np.ones(x.shape[0])
+
+    rows = []
+    for n in ns:
+        mesh = mesh2d_jittered_delaunay(n, seed)
+        parents, sizes = agglomerate(mesh, 64, seed, p=p)
+        for beta in betas:
+            row = dict(setting="paper", p=p, n=n, elements=int(mesh.n_elem), levels=len(sizes), beta=beta)
+            row.update(_solve_case(mesh, p, parents, sizes, ones, max_iter, "paper", beta=beta, velocity=(1.0, 0.0),
+                                   coarsening=COARSEN_PRIMAL))
+            log("convection n=%d beta=%g: %s" % (n, beta, row))
+            rows.append(row)
     return rows

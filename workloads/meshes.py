@@ -63,6 +63,33 @@ def mesh2d_jittered_delaunay(n, seed, jitter=0.25, bc=0):
     return Mesh(P, e2v, face_bc)
 
 
+def mesh2d_square_neumann_sides(n):
+    """Uniform n x n grid of [0,1]^2, every square split by its (0,0)-(1,1)
+    diagonal (2 n^2 right triangles); Neumann facets (1) on x = 0 and x = 1,
+    Dirichlet (0) on y = 0 and y = 1."""
+    g = np.linspace(0.0, 1.0, n + 1)
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    P = np.stack([X.ravel(), Y.ravel()], axis=1)
+
+    def vid(i, j):
+        return i * (n + 1) + j
+
+    tris = []
+    for i in range(n):
+        for j in range(n):
+            a, b, c, d = vid(i, j), vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1)
+            tris += [(a, b, c), (a, c, d)]
+    e2v = _orient(P, np.asarray(tris, dtype=np.int32)).astype(np.int32)
+    face_bc = np.zeros(e2v.shape, dtype=np.int8)
+    for e in range(e2v.shape[0]):
+        for i in range(3):
+            f = [int(v) for k, v in enumerate(e2v[e]) if k != i]
+            xs = P[f, 0]
+            if np.all(xs == 0.0) or np.all(xs == 1.0):
+                face_bc[e, i] = 1
+    return Mesh(P, e2v, face_bc)
+
+
 def mesh3d_kuhn(n, seed, jitter=0.15, bc=0):
     """(n+1)^3 grid of [0,1]^3, interior vertices moved by U(+-jitter*h)^3,
     every cube split into the 6 Kuhn tetrahedra sharing its main diagonal."""
