@@ -42,7 +42,10 @@ from .switch import consistent_switch, natural_switch
 
 class CDG:
     def __init__(self, coords, e2v, face_bc, p, gamma=1e4, switch="consistent",
-                 switch_seed=None, host=None):
+                 switch_seed=None, host=None, subset=None):
+        """subset: element ids whose rows of A are wanted (``A_rows``); only
+        their element-local matrices and their neighbours' are formed, for
+        sampled checks on large meshes.  None: all (every global matrix)."""
         coords = np.asarray(coords, dtype=np.float64)
         e2v = np.asarray(e2v, dtype=np.int64)
         face_bc = np.asarray(face_bc)
@@ -60,6 +63,13 @@ class CDG:
             self.host = consistent_switch(topo.interior, self.N)
         else:
             self.host = natural_switch(topo.interior, self.N, switch_seed)
+        if subset is None:
+            self.need = None
+        else:
+            need = set(int(e) for e in subset)
+            for e in list(need):
+                need.update(int(c) for c in topo.nbr[e] if c >= 0)
+            self.need = sorted(need)
         self._geometry()
         self._assemble_local()
 
@@ -74,7 +84,8 @@ class CDG:
         self.vol = self.det / (1 if d == 1 else (2 if d == 2 else 6))
         # facets: quadrature points, weights, outward normal, measure
         self.fq = {}
-        for e in range(N):
+        elems = range(N) if self.need is None else sorted(set(self.need) | {e for (e, _) in self.topo.boundary})
+        for e in elems:
             for i in range(d + 1):
                 w = [X[e, k] for k in range(d + 1) if k != i]
                 if d == 2:
@@ -132,8 +143,8 @@ class CDG:
         phi_q = ref.eval(ref.qpts)                 # [nq, np]
         gref_q = ref.grad(ref.qpts)                # [nq, np, d]
         self.Mloc = np.zeros((self.N, npb, npb))
-        self.local = []                            # (dofs elems, A^(K), C^(K), G^c rows)
-        for e in range(self.N):
+        self.local = [None] * self.N               # (dofs elems, A^(K), C^(K), G^c rows)
+        for e in (range(self.N) if self.need is None else self.need):
             w = ref.qwts * self.det[e]
             M = (phi_q * w[:, None]).T @ phi_q
             self.Mloc[e] = M
@@ -178,10 +189,11 @@ class CDG:
                 for b, (Fb, nb_) in enumerate(Fs):
                     if a != b:
                         C -= np.dot(na, nb_) * (Fb.T @ Minv @ Fa)
-            self.local.append((elems, A, C, G))
+            self.local[e] = (elems, A, C, G)
 
     # --------------------------------------------------------- global matrices
     def _scatter(self, which, kappa):
+        assert self.need is None, "global matrices need all elements (subset=None)"
         npb = self.np
         rows, cols, vals = [], [], []
         for e, (elems, A, C, G) in enumerate(self.local):
@@ -194,6 +206,27 @@ class CDG:
         n = self.N * npb
         return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                              shape=(n, n))
+
+    def A_rows(self, elems, kappa=None):
+        """Rows of A = sum_K kappa_K A^(K) for the given elements, as
+        {e: {c: n_p x n_p block}}: the hosts whose stencil holds e are e and
+        its face neighbours."""
+        kappa = np.ones(self.N) if kappa is None else np.asarray(kappa, dtype=np.float64)
+        npb = self.np
+        out = {}
+        for e in elems:
+            e = int(e)
+            row = {}
+            for K in [e] + [int(c) for c in self.topo.nbr[e] if c >= 0]:
+                stencil, AK, _, _ = self.local[K]
+                if e not in stencil:
+                    continue
+                a = stencil.index(e)
+                for b, c in enumerate(stencil):
+                    blk = kappa[K] * AK[a * npb:(a + 1) * npb, b * npb:(b + 1) * npb]
+                    row[c] = row.get(c, 0.0) + blk
+            out[e] = row
+        return out
 
     def Cv(self, beta, vel):
         """Upwind DG convection matrix of beta v . grad u, v constant (the
@@ -253,6 +286,7 @@ class CDG:
 
     def G(self):
         """Flux-form gradient blocks, one CSR matrix per component (kappa-free)."""
+        assert self.need is None, "global matrices need all elements (subset=None)"
         npb = self.np
         out = []
         for c in range(self.d):

@@ -196,3 +196,27 @@ def test_convection_option_checks():
     with pytest.raises(cm.CdgmgError) as ei:  # CG needs a symmetric operator
         cm.debug_host_operator(m, 1, np.ones(m.n_elem), parents, sizes, 0, beta=1.0)
     assert ei.value.code == -1
+
+
+def test_full_size_agglomeration_and_switch():
+    # the 2D p=3 benchmark mesh (199 712 triangles): the library's hierarchy and
+    # consistent switch are bit-identical to the oracle's at full size
+    from workloads import CONFIGS, config_mesh
+    cfg = CONFIGS["c2"]
+    m, _ = config_mesh(cfg)
+    parents, sizes = cm.agglomerate(m, cfg["levels"], cfg["agg_seed"], p=cfg["p"])
+    topo = Topology(m.e2v, m.coords)
+    ref = build_hierarchy(m.e2v, topo.neighbor_pairs(), cfg["levels"], cfg["agg_seed"])
+    assert len(parents) == len(ref)
+    for a, b in zip(parents, ref):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+    got = cm.switch(m)
+    from oracle.switch import consistent_switch
+    host = consistent_switch(topo.interior, topo.n_elem)
+    flags = np.zeros_like(got)
+    for f, (a, ia, b, ib) in enumerate(topo.interior):
+        flags[(a, ia) if host[f] == a else (b, ib)] = 1
+    for (e, i) in topo.boundary:
+        if m.face_bc[e, i] == 0:
+            flags[e, i] = 1
+    assert np.array_equal(got, flags)

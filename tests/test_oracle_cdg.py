@@ -130,3 +130,22 @@ def test_second_neighbour_rule_of_C():
                 found.add((i, j))
     assert len(expected) > 0
     assert found == expected
+
+
+def test_sampled_rows_equal_the_full_operator():
+    # the subset mode used for sampled checks on large meshes forms the same
+    # rows as the full assembly
+    m = mesh2d_jittered_delaunay(9, 2)
+    kappa = np.random.default_rng(3).uniform(0.5, 2.0, m.n_elem)
+    full = CDG(m.coords, m.e2v, m.face_bc, 2)
+    A = full.A(kappa).tocsr()
+    sample = [0, 5, 17, 40, m.n_elem - 1]
+    part = CDG(m.coords, m.e2v, m.face_bc, 2, subset=sample)
+    rows = part.A_rows(sample, kappa)
+    npb = full.np
+    for e in sample:
+        dense = A[e * npb:(e + 1) * npb, :].toarray()
+        got = np.zeros_like(dense)
+        for c, blk in rows[e].items():
+            got[:, c * npb:(c + 1) * npb] = blk
+        assert np.abs(got - dense).max() <= 1e-14 * np.abs(dense).max()
