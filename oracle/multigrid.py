@@ -193,3 +193,43 @@ class Hierarchy:
         for _ in range(nu2):
             x = x + omega * (Dinv @ (b - A @ x))
         return x
+
+
+class HpHierarchy:
+    """hp-multigrid front end (Sec. 4, hp paragraph): p-multigrid from degree
+    p down to p = 1 on the fine mesh, then the agglomeration levels at p = 1.
+
+    Level 0 is the degree-p CDG operator A_0 with its block-Jacobi smoother.
+    The p = 1 space is embedded element by element: the nodal P1 basis of the
+    reference simplex evaluated at the degree-p nodes gives T (n_p x n_p1),
+    the same for every element (both bases are nodal on the same reference
+    element), and Tb = blockdiag(T).  The p = 1 operator is the Galerkin
+    projection Tb^T A_0 Tb, coarsened further by the agglomeration hierarchy
+    at p = 1 (primal coarsening)."""
+
+    def __init__(self, cdg, cdg1, parents, kappa=None):
+        from .refelem import RefElement
+        assert cdg1.p == 1 and cdg.p >= 1
+        self.cdg, self.cdg1 = cdg, cdg1
+        self.np, self.np1 = cdg.np, cdg1.np
+        self.kappa = np.ones(cdg.N) if kappa is None else np.asarray(kappa, dtype=np.float64)
+        self.T = RefElement(cdg.d, 1).eval(cdg.ref.nodes)          # [n_p, n_p1]
+        self.Tb = sp.kron(sp.identity(cdg.N, format="csr"), sp.csr_matrix(self.T), format="csr")
+        self.A0 = cdg.A(self.kappa).tocsr()
+        self.Dinv0 = block_diag_matrix(np.linalg.inv(block_diag_blocks(self.A0, self.np)))
+        A1 = (self.Tb.T @ self.A0 @ self.Tb).tocsr()
+        self.inner = Hierarchy(cdg1, parents, kappa=self.kappa, coarsening="primal", A0=A1)
+
+    def vcycle(self, b, nu1=2, nu2=2, omega=0.7):
+        """One V(nu1, nu2) cycle for A_0 x = b from x = 0; the coarse
+        correction is the p = 1 hierarchy's V-cycle."""
+        A, Dinv = self.A0, self.Dinv0
+        x = np.zeros_like(b)
+        for _ in range(nu1):
+            x = x + omega * (Dinv @ (b - A @ x))
+        r = b - A @ x
+        xc = self.inner.vcycle(self.Tb.T @ r, nu1, nu2, omega)
+        x = x + self.Tb @ xc
+        for _ in range(nu2):
+            x = x + omega * (Dinv @ (b - A @ x))
+        return x
