@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--outer", choices=["fcg", "pcg", "gmres"], default="fcg",
                     help="outer Krylov solver (the metric is quoted with fcg)")
     ap.add_argument("--restart", type=int, default=50, help="GMRES restart length")
+    ap.add_argument("--p-coarse", type=int, default=0, help="1: hp front end (p-multigrid to p = 1 first)")
+    ap.add_argument("--p-jump", type=int, default=0, help="with --p-coarse 1: 1 goes from p straight to p = 1")
     ap.add_argument("--study", choices=["coarsening", "coarsening-paper", "switch", "switch-paper", "convection"],
                     help="instead of the benchmark: primal vs flux coarsening over mesh size and gamma, "
                          "consistent vs natural switch (workload or the paper's solver settings), or "
@@ -153,8 +155,12 @@ def main():
     t0 = time.perf_counter()
     outer = {"fcg": cm.OUTER_FCG, "pcg": cm.OUTER_PCG, "gmres": cm.OUTER_GMRES}[args.outer]
     outer_name = {"fcg": "FCG(1)", "pcg": "PCG", "gmres": "GMRES(%d)" % args.restart}[args.outer]
+    hp_desc = ""
+    if args.p_coarse == 1 and cfg["p"] >= 2:
+        hp_desc = "p-multigrid over degrees %s, then " % (
+            "%d, 1" % cfg["p"] if args.p_jump else ", ".join(str(q) for q in range(cfg["p"], 0, -1)))
     s32 = cm.Solver(mesh, cfg["p"], kappa_t, parents, sizes, mg_precision=cm.MG_FP32, tol=cfg["tol"],
-                    outer=outer, restart=args.restart,
+                    outer=outer, restart=args.restart, p_coarse=args.p_coarse, p_jump=args.p_jump,
                     kernel_variant=args.kernel_variant)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
@@ -225,7 +231,7 @@ def main():
     if not args.no_fp64:
         s32_bytes = s32.device_bytes()
         s64 = cm.Solver(mesh, cfg["p"], kappa_t, parents, sizes, mg_precision=cm.MG_FP64, tol=cfg["tol"],
-                        outer=outer, restart=args.restart,
+                        outer=outer, restart=args.restart, p_coarse=args.p_coarse, p_jump=args.p_jump,
                         kernel_variant=args.kernel_variant)
         for _ in range(max(1, args.warmup)):
             u64, info64 = s64.solve(f)
@@ -264,12 +270,13 @@ def main():
         "dtype": "f32 (V-cycle) / f64 (outer FCG, residual)",
         "data": "synthetic",
         "config": {
-            "workload": "%s: %dD jittered %s mesh n=%d, %d elements, CDG p=%d, %d DOFs, kappa=%s, %d-level "
+            "p_levels": s32.p_levels,
+            "workload": "%s: %dD jittered %s mesh n=%d, %d elements, CDG p=%d, %d DOFs, kappa=%s, %s%d-level "
                         "greedy agglomeration (seed %d), V(%d,%d) damped block Jacobi omega=%.1f, "
                         "Galerkin coarse operators, %s, tol %.0e"
                         % (args.config, cfg["dim"], "Delaunay" if cfg["dim"] == 2 else "Kuhn-tet", cfg["n"],
-                           mesh.n_elem, cfg["p"], dofs, cfg["kappa"], len(sizes), cfg["agg_seed"], 2, 2, 0.7,
-                           outer_name, cfg["tol"]),
+                           mesh.n_elem, cfg["p"], dofs, cfg["kappa"], hp_desc, len(sizes), cfg["agg_seed"], 2, 2,
+                           0.7, outer_name, cfg["tol"]),
             "elements": int(mesh.n_elem), "dofs": int(dofs), "p": cfg["p"], "levels": [int(x) for x in sizes],
             "nnzb": [int(x) for x in nnzb],
             "operator_complexity": float(sum(nnzb) / nnzb[0]),

@@ -62,8 +62,9 @@ extern "C" {
 
 /* kernel classes timed when cdgmg_options.profile != 0 */
 #define CDGMG_K_SPMV 0           /* outer FP64 q = A_0 p with fused (p,q), (p,r) partial sums */
-#define CDGMG_K_SMOOTH0 1        /* level-0 damped block-Jacobi sweep (one kernel) */
-#define CDGMG_K_SMOOTH 2         /* first sweeps from zero and coarse-level sweeps */
+#define CDGMG_K_SMOOTH0 1        /* level-0 damped block-Jacobi sweep (one kernel); with
+                                    p_coarse = 1 only the degree-p level's */
+#define CDGMG_K_SMOOTH 2         /* first sweeps from zero and all other levels' sweeps */
 #define CDGMG_K_RESTRICT 3       /* residual + restriction, all levels */
 #define CDGMG_K_PROLONG 4        /* prolongation + correction, all levels */
 #define CDGMG_K_COARSE 5         /* coarsest solve */
@@ -109,6 +110,18 @@ typedef struct cdgmg_options {
                           nonsymmetric: it requires outer = CDGMG_OUTER_GMRES and primal
                           coarsening (else setup fails with CDGMG_ERR_ARG) */
   double velocity[3];  /* constant v (first dim entries used); default (1, 0, 0) */
+  int p_coarse;        /* hp front end (Sec. 4, hp paragraph): 1 runs p-multigrid on the input
+                          mesh from degree p down to p = 1 before the agglomeration levels,
+                          which then run at p = 1; 0 (default) agglomerates at p.  Each
+                          p-level embeds the next lower degree element by element by the
+                          nodal embedding T (n_p x n_p', the lower-degree nodal basis at the
+                          degree-p nodes) and its operator is T^T A T.  Needs primal
+                          coarsening and beta = 0 (else CDGMG_ERR_ARG); ignored for p = 1.
+                          The level queries (level_info, apply_A, export_operator) then
+                          number the p-levels first (degree p at level 0) and the p = 1
+                          agglomeration levels after them */
+  int p_jump;          /* with p_coarse = 1: 0 (default) lowers the degree by one per level
+                          (p, p - 1, ..., 1); 1 goes from p straight to p = 1 */
 } cdgmg_options;
 
 typedef struct cdgmg_solve_info {

@@ -13,7 +13,10 @@ for compact discontinuous Galerkin discretizations on unstructured meshes":
 * ``cdg``         CDG primal operator A, flux form M, G, C (Sec. 2.2-2.3)
 * ``agglomerate`` greedy agglomeration, Alg. 1 and Alg. 2 (Sec. 3.1-3.2)
 * ``multigrid``   agglomerate bases, transfers, flux/primal coarsening, the
-                  V-cycle with damped block Jacobi (Sec. 3.3-3.5, Sec. 4.1, Alg. 3)
+                  V-cycle with damped block Jacobi (Sec. 3.3-3.5, Sec. 4.1, Alg. 3);
+                  the hp front end, p-multigrid down to p = 1 by nodal
+                  embeddings before the agglomeration levels (Sec. 4, hp
+                  paragraph)
 * ``krylov``      PCG, flexible CG (FCG(1), Notay 2000) and right-preconditioned
                   GMRES(m) (Sec. 4) outer solvers
 * ``adjoint``     adjoint gradients dL/dkappa and dL/df of the solve

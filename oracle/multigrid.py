@@ -196,40 +196,53 @@ class Hierarchy:
 
 
 class HpHierarchy:
-    """hp-multigrid front end (Sec. 4, hp paragraph): p-multigrid from degree
-    p down to p = 1 on the fine mesh, then the agglomeration levels at p = 1.
+    """hp-multigrid front end (Sec. 4, hp paragraph): p-multigrid on the fine
+    mesh from degree p down to p = 1, then the agglomeration levels at p = 1.
 
-    Level 0 is the degree-p CDG operator A_0 with its block-Jacobi smoother.
-    The p = 1 space is embedded element by element: the nodal P1 basis of the
-    reference simplex evaluated at the degree-p nodes gives T (n_p x n_p1),
-    the same for every element (both bases are nodal on the same reference
-    element), and Tb = blockdiag(T).  The p = 1 operator is the Galerkin
-    projection Tb^T A_0 Tb, coarsened further by the agglomeration hierarchy
-    at p = 1 (primal coarsening)."""
+    cdgs lists the CDG discretisations of the p-levels, of strictly
+    decreasing degree and ending at p = 1: [p, p-1, ..., 1] for the standard
+    p-multigrid sequence that lowers the degree by one per level, or [p, 1]
+    for a single jump.  Level k carries the degree-p_k operator A_k with its
+    block-Jacobi smoother.  The degree-p_{k+1} space is embedded element by
+    element: the nodal basis of degree p_{k+1} on the reference simplex,
+    evaluated at the degree-p_k nodes, gives T_k (n_{p_k} x n_{p_{k+1}}), the
+    same for every element (both bases are nodal on the same reference
+    element), and Tb_k = blockdiag(T_k).  The next operator is the Galerkin
+    projection A_{k+1} = Tb_k^T A_k Tb_k; the p = 1 one is coarsened further
+    by the agglomeration hierarchy at p = 1 (primal coarsening)."""
 
-    def __init__(self, cdg, cdg1, parents, kappa=None):
+    def __init__(self, cdgs, parents, kappa=None):
         from .refelem import RefElement
-        assert cdg1.p == 1 and cdg.p >= 1
-        self.cdg, self.cdg1 = cdg, cdg1
-        self.np, self.np1 = cdg.np, cdg1.np
+        degs = [c.p for c in cdgs]
+        assert degs[-1] == 1 and all(a > b for a, b in zip(degs, degs[1:]))
+        self.cdgs = list(cdgs)
+        cdg = cdgs[0]
         self.kappa = np.ones(cdg.N) if kappa is None else np.asarray(kappa, dtype=np.float64)
-        self.T = RefElement(cdg.d, 1).eval(cdg.ref.nodes)          # [n_p, n_p1]
-        self.Tb = sp.kron(sp.identity(cdg.N, format="csr"), sp.csr_matrix(self.T), format="csr")
-        self.A0 = cdg.A(self.kappa).tocsr()
-        self.Dinv0 = block_diag_matrix(np.linalg.inv(block_diag_blocks(self.A0, self.np)))
-        A1 = (self.Tb.T @ self.A0 @ self.Tb).tocsr()
-        self.inner = Hierarchy(cdg1, parents, kappa=self.kappa, coarsening="primal", A0=A1)
+        N = cdg.N
+        self.T, self.Tb, self.A, self.Dinv = [], [], [], []
+        A = cdg.A(self.kappa).tocsr()
+        for k in range(len(cdgs) - 1):
+            T = RefElement(cdg.d, degs[k + 1]).eval(cdgs[k].ref.nodes)      # [n_pk, n_pk+1]
+            Tb = sp.kron(sp.identity(N, format="csr"), sp.csr_matrix(T), format="csr")
+            self.A.append(A)
+            self.Dinv.append(block_diag_matrix(np.linalg.inv(block_diag_blocks(A, cdgs[k].np))))
+            self.T.append(T)
+            self.Tb.append(Tb)
+            A = (Tb.T @ A @ Tb).tocsr()
+        self.A0 = self.A[0] if self.A else A
+        self.inner = Hierarchy(cdgs[-1], parents, kappa=self.kappa, coarsening="primal", A0=A)
 
-    def vcycle(self, b, nu1=2, nu2=2, omega=0.7):
-        """One V(nu1, nu2) cycle for A_0 x = b from x = 0; the coarse
-        correction is the p = 1 hierarchy's V-cycle."""
-        A, Dinv = self.A0, self.Dinv0
+    def vcycle(self, b, nu1=2, nu2=2, omega=0.7, k=0):
+        """One V(nu1, nu2) cycle for A_k x = b from x = 0; below the last
+        p-level the coarse correction is the p = 1 hierarchy's V-cycle."""
+        if k == len(self.A):
+            return self.inner.vcycle(b, nu1, nu2, omega)
+        A, Dinv, Tb = self.A[k], self.Dinv[k], self.Tb[k]
         x = np.zeros_like(b)
         for _ in range(nu1):
             x = x + omega * (Dinv @ (b - A @ x))
         r = b - A @ x
-        xc = self.inner.vcycle(self.Tb.T @ r, nu1, nu2, omega)
-        x = x + self.Tb @ xc
+        x = x + Tb @ self.vcycle(Tb.T @ r, nu1, nu2, omega, k + 1)
         for _ in range(nu2):
             x = x + omega * (Dinv @ (b - A @ x))
         return x

@@ -48,7 +48,8 @@ class _Opts(ctypes.Structure):
                 ("coarsening", ctypes.c_int), ("switch_mode", ctypes.c_int),
                 ("switch_seed", ctypes.c_uint64), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("profile", ctypes.c_int), ("kernel_variant", ctypes.c_int), ("restart", ctypes.c_int),
-                ("beta", ctypes.c_double), ("velocity", ctypes.c_double * 3)]
+                ("beta", ctypes.c_double), ("velocity", ctypes.c_double * 3), ("p_coarse", ctypes.c_int),
+                ("p_jump", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -216,6 +217,12 @@ class Solver:
         self.np = n_basis(self.hm.dim, p)
         self.n_elem = self.hm.n_elem
         self.opts = default_options(**options)
+        # degree of each p-level (hp front end: p down to 1, by one or in one
+        # step); the agglomeration levels after them run at the last degree
+        if self.opts.p_coarse == 1 and p >= 2:
+            self.p_levels = [p, 1] if self.opts.p_jump else list(range(p, 0, -1))
+        else:
+            self.p_levels = [p]
         sizes = np.ascontiguousarray(sizes, dtype=np.int32)
         par = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.int32) for x in parents])
                                    if len(parents) else np.zeros(0, dtype=np.int32))
@@ -301,9 +308,13 @@ class Solver:
         dt = torch.float64 if precision == 0 else torch.float32
         ne, _ = self.level_info()
         x = self._dev(x, dt).reshape(-1)
-        y = torch.empty(int(ne[level]) * self.np, dtype=dt, device="cuda")
+        y = torch.empty(int(ne[level]) * self.level_np(level), dtype=dt, device="cuda")
         _check(lib.cdgmg_apply_A(self.handle, level, precision, x.data_ptr(), y.data_ptr()))
         return y
+
+    def level_np(self, level):
+        """Block size n_p of the operator at a level."""
+        return n_basis(self.hm.dim, self.p_levels[min(level, len(self.p_levels) - 1)])
 
     def vcycle(self, r):
         r = self._dev(r).reshape(-1)
@@ -318,7 +329,8 @@ class Solver:
         _check(lib.cdgmg_export_operator(self.handle, level, ctypes.byref(nnzb), None, None, None))
         rp = np.zeros(int(ne[level]) + 1, dtype=np.int64)
         cols = np.zeros(nnzb.value, dtype=np.int32)
-        blocks = np.zeros((nnzb.value, self.np, self.np))
+        npl = self.level_np(level)
+        blocks = np.zeros((nnzb.value, npl, npl))
         _check(lib.cdgmg_export_operator(self.handle, level, ctypes.byref(nnzb), _ptr(rp), _ptr(cols),
                                          _ptr(blocks)))
         return rp, cols, blocks

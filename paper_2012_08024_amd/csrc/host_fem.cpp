@@ -942,6 +942,14 @@ int check_options(const cdgmg_options& o) {
     set_error("setup: unknown coarsening");
     return CDGMG_ERR_ARG;
   }
+  if ((o.p_coarse != 0 && o.p_coarse != 1) || (o.p_jump != 0 && o.p_jump != 1)) {
+    set_error("setup: p_coarse and p_jump must be 0 or 1");
+    return CDGMG_ERR_ARG;
+  }
+  if (o.p_coarse == 1 && (o.coarsening != CDGMG_COARSEN_PRIMAL || o.beta != 0.0)) {
+    set_error("setup: the hp front end needs primal coarsening and beta = 0");
+    return CDGMG_ERR_ARG;
+  }
   return CDGMG_OK;
 }
 

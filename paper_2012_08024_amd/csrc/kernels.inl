@@ -803,6 +803,104 @@ __global__ __launch_bounds__(TPB) void k_restrict_grp(int64_t n, const int32_t* 
   }
 }
 
+// ------------------------------------------------------------------
+// hp front end: the lower-degree space embedded element by element by the
+// constant nodal embedding T (n_p0 x n_p1, row-major).  Level-0 blocks of the
+// lower-degree operator are T^T A_0(r, w) T in the same sliced pattern (both
+// patterns hold W = n_f + 1 slots per slice), one thread per (slice, slot, k,
+// l, lane).
+template <int NP0, int NP1>
+__global__ void k_galerkin_p(int64_t ns, int W, const double* __restrict__ A0, const double* __restrict__ Tm,
+                             double* __restrict__ A1) {
+  constexpr int N0 = NP0 * NP0, N1 = NP1 * NP1;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = (int)(idx % WAVE);
+  int64_t rest = idx / WAVE;
+  const int kl = (int)(rest % N1);
+  rest /= N1;
+  const int w = (int)(rest % W);
+  const int64_t s = rest / W;
+  if (s >= ns) return;
+  const int k = kl / NP1, l = kl % NP1;
+  const int64_t slot = s * W + w;  // the slot's block index in both layouts
+  const double* a = A0 + slot * WAVE * N0 + lane;
+  double acc = 0.0;
+  for (int i = 0; i < NP0; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < NP0; ++j) t += a[(i * NP0 + j) * WAVE] * Tm[j * NP1 + l];
+    acc += Tm[i * NP1 + k] * t;
+  }
+  A1[slot * WAVE * N1 + (int64_t)kl * WAVE + lane] = acc;
+}
+
+// Lt_e = D_e^T T (n_p0 x n_p1) per row, per-row layout with blocks of n_p0 n_p1
+template <typename T, int NP0, int NP1>
+__global__ void k_scale_L_rect(int64_t n, const int64_t* __restrict__ sblk, const double* __restrict__ A,
+                               const double* __restrict__ Tm, T* __restrict__ Lt) {
+  constexpr int N0 = NP0 * NP0, NR = NP0 * NP1;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = (int)(idx % WAVE);
+  const int64_t rest = idx / WAVE;
+  const int ij = (int)(rest % NR);
+  const int64_t s = rest / NR;
+  const int64_t r = s * WAVE + lane;
+  if (r >= n) return;
+  const int i = ij / NP1, j = ij % NP1;
+  const int64_t B = sblk[s];
+  double acc = 0.0;
+#pragma unroll
+  for (int m = 0; m < NP0; ++m) acc += A[blk_off(B, 0, N0, m * NP0 + i, lane)] * Tm[m * NP1 + j];
+  Lt[s * WAVE * NR + (int64_t)ij * WAVE + lane] = (T)acc;
+}
+
+// level-0 residual + restriction to the lower-degree space, FP64 output for
+// the lower hierarchy: t_r = Lt_r^T (bt - At x)_r, Lt_r = D_r^T T
+template <typename T, int NP0, int NP1, int H, int NF>
+__global__ __launch_bounds__(WAVE * H) void k_restrict0_rect(int64_t n, const int32_t* __restrict__ cols,
+                                                             const T* __restrict__ At, const T* __restrict__ bt,
+                                                             const T* __restrict__ x, const T* __restrict__ Lt,
+                                                             double* __restrict__ t_out) {
+  constexpr int NI = NP0 / H, NR = NP0 * NP1;
+  __shared__ T sres[NP0][WAVE];
+  const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
+  const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
+  const bool valid = r < n;
+  if (valid) {
+    T acc[NI];
+    hs_scaled_residual<T, NP0, H, NF>(r, lane, h, cols, At, bt, x, acc);
+#pragma unroll
+    for (int t = 0; t < NI; ++t) sres[h * NI + t][lane] = acc[t];
+  }
+  __syncthreads();
+  if (!valid) return;
+  const T* Lr = Lt + (int64_t)blockIdx.x * WAVE * NR + lane;
+  for (int j = h; j < NP1; j += H) {
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < NP0; ++i) s += Lr[(i * NP1 + j) * WAVE] * sres[i][lane];
+    t_out[r * NP1 + j] = (double)s;
+  }
+}
+
+// prolongation from the lower-degree space: x_r += T z_r
+template <typename T, int NP0, int NP1>
+__global__ __launch_bounds__(TPB) void k_prolong_rect(int64_t n, const T* __restrict__ Tm, const T* __restrict__ z,
+                                                      T* __restrict__ x) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  T zv[NP1];
+#pragma unroll
+  for (int k = 0; k < NP1; ++k) zv[k] = z[r * NP1 + k];
+#pragma unroll
+  for (int i = 0; i < NP0; ++i) {
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < NP1; ++k) s += Tm[i * NP1 + k] * zv[k];
+    x[r * NP0 + i] += s;
+  }
+}
+
 // ----------------------------------------------------------- prescaling (setup)
 // At_off(r, w) = D_r^{-1} A(r, w), w >= 1, into the level-0 sliced layout
 // without slot 0; one thread per output entry (slice, slot, i, j, lane),

@@ -70,6 +70,28 @@ constexpr bool l0_pair(int np, int nf) {
     default: break;                                                                                         \
   }
 
+// hp front end: (n_p at degree q, n_p at the next lower degree) pairs
+#define HP_DISPATCH(np0, np1, ...)                                                   \
+  if ((np0) == 6 && (np1) == 3) {                                                    \
+    constexpr int NP0 = 6, NP1 = 3;                                                  \
+    __VA_ARGS__;                                                                     \
+  } else if ((np0) == 10 && (np1) == 3) {                                            \
+    constexpr int NP0 = 10, NP1 = 3;                                                 \
+    __VA_ARGS__;                                                                     \
+  } else if ((np0) == 10 && (np1) == 4) {                                            \
+    constexpr int NP0 = 10, NP1 = 4;                                                 \
+    __VA_ARGS__;                                                                     \
+  } else if ((np0) == 20 && (np1) == 4) {                                            \
+    constexpr int NP0 = 20, NP1 = 4;                                                 \
+    __VA_ARGS__;                                                                     \
+  } else if ((np0) == 10 && (np1) == 6) {                                            \
+    constexpr int NP0 = 10, NP1 = 6;                                                 \
+    __VA_ARGS__;                                                                     \
+  } else if ((np0) == 20 && (np1) == 10) {                                           \
+    constexpr int NP0 = 20, NP1 = 10;                                                \
+    __VA_ARGS__;                                                                     \
+  }
+
 // lanes per row of the coarse-level kernels
 #define G_DISPATCH(gv, ...)                                  \
   switch (gv) {                                              \
@@ -137,6 +159,13 @@ struct cdgmg_handle {
   // level 0
   double *UA = nullptr, *UH = nullptr, *M = nullptr, *kappa = nullptr;
   double* UC = nullptr;    // upwind convection blocks (beta != 0), operator layout
+  // hp front end: the lower-degree hierarchy below level 0 (owned), the nodal
+  // embedding T [np][np1] in FP64 and in the multigrid precision
+  cdgmg_handle* inner = nullptr;
+  bool given_A0 = false;   // this level 0 is set by the owner (T^T A_0 T), not assembled from kappa
+  int np1 = 0;
+  double* Tp64 = nullptr;
+  void* Tpm = nullptr;
   double* Atmp = nullptr;  // A_0^T staging (beta != 0)
   bool transposed = false; // the levels hold A_l^T
   int8_t *hostflag = nullptr, *revslot = nullptr;
@@ -362,6 +391,19 @@ int upload_problem(cdgmg_handle* h) {
     RETURN_IF(dalloc(h, &D.A64, (size_t)D.slots * np2));
     HIPCHK(hipMemsetAsync(D.A64, 0, (size_t)D.slots * np2 * sizeof(double), h->stream));
     const size_t rowblk = (size_t)D.ns * SLICE * np2;
+    if (l == 0 && h->inner) {  // hp front end: level 0 restricts to the lower degree
+      const size_t rect = (size_t)D.ns * SLICE * np * h->np1;
+      RETURN_IF(dalloc(h, &D.D64, rowblk));
+      void* tmp;
+      RETURN_IF(dalloc(h, (char**)&tmp, rect * (fp32 ? sizeof(float) : sizeof(double))));
+      D.Lt = tmp;
+      if (fp32) {
+        RETURN_IF(dalloc(h, (char**)&tmp, rowblk * sizeof(float)));
+        D.Dm = tmp;
+      } else {
+        D.Dm = D.D64;
+      }
+    }
     if (l < P.L) {
       RETURN_IF(dalloc(h, &D.D64, rowblk));
       std::vector<double> Lr = to_rows(H.Lblk, H.n, np2);
@@ -383,7 +425,7 @@ int upload_problem(cdgmg_handle* h) {
       }
       RETURN_IF(upload(h, &D.parent, H.parent));
     }
-    if (l == 0 && P.L > 0) {
+    if (l == 0 && (P.L > 0 || h->inner)) {
       const size_t na = (size_t)(D.slots - SLICE * D.ns) * np2;
       void* tmp;
       RETURN_IF(dalloc(h, (char**)&tmp, na * (fp32 ? sizeof(float) : sizeof(double))));
@@ -449,21 +491,23 @@ int upload_problem(cdgmg_handle* h) {
     std::vector<double>().swap(P.UC);
   }
   RETURN_IF(dalloc(h, &h->kappa, P.N0));
-  // coarsest dense
-  h->nd = h->lv[P.L].n * np;
-  if (h->nd > 12000) {
-    set_error("setup: coarsest level has " + std::to_string(h->nd) + " unknowns (limit 12000); use more levels");
-    return CDGMG_ERR_ARG;
-  }
-  h->ld = (h->nd + GJB - 1) / GJB * GJB;
-  RETURN_IF(dalloc(h, &h->dense, (size_t)h->ld * h->ld));
-  RETURN_IF(dalloc(h, &h->gjP, (size_t)GJB * GJB));
-  if (fp32) {
-    float* tmp;
-    RETURN_IF(dalloc(h, &tmp, (size_t)h->nd * h->ld));
-    h->AinvP = tmp;
-  } else {
-    h->AinvP = h->dense;
+  if (!h->inner) {
+    // coarsest dense
+    h->nd = h->lv[P.L].n * np;
+    if (h->nd > 12000) {
+      set_error("setup: coarsest level has " + std::to_string(h->nd) + " unknowns (limit 12000); use more levels");
+      return CDGMG_ERR_ARG;
+    }
+    h->ld = (h->nd + GJB - 1) / GJB * GJB;
+    RETURN_IF(dalloc(h, &h->dense, (size_t)h->ld * h->ld));
+    RETURN_IF(dalloc(h, &h->gjP, (size_t)GJB * GJB));
+    if (fp32) {
+      float* tmp;
+      RETURN_IF(dalloc(h, &tmp, (size_t)h->nd * h->ld));
+      h->AinvP = tmp;
+    } else {
+      h->AinvP = h->dense;
+    }
   }
   // outer vectors
   const size_t m = (size_t)h->lv[0].ns * SLICE * np;
@@ -505,6 +549,44 @@ int upload_problem(cdgmg_handle* h) {
   return CDGMG_OK;
 }
 
+// hp front end, level 0 at degree p: D^{-1}, the next p-level's operator
+// T^T A_0 T, the whole lower-degree hierarchy, and the prescaled level-0 operators
+// (D^{-1} A_0 off-diagonal, D^{-1}, D^T T)
+template <typename T, int NP0, int NP1>
+void prescale_hp(cdgmg_handle* h) {
+  constexpr int NP2 = NP0 * NP0;
+  DLevel& D = h->lv[0];
+  launch(h, -1, k_scale_sliced<T, NP0>, dim3(grid_for(D.ns * (h->W0 - 1) * NP2 * WAVE)), dim3(TPB), D.n, h->W0,
+         (const int64_t*)D.sblk, (const double*)D.A64, (const double*)D.D64, (T*)D.At);
+  launch(h, -1, k_scale_L_rect<T, NP0, NP1>, dim3(grid_for(D.ns * NP0 * NP1 * WAVE)), dim3(TPB), D.n,
+         (const int64_t*)D.sblk, (const double*)D.A64, (const double*)h->Tp64, (T*)D.Lt);
+  if ((void*)D.Dm != (void*)D.D64) {
+    const int64_t nb = D.ns * SLICE * NP2;
+    launch(h, -1, k_cast<double, T>, dim3(grid_for(nb)), dim3(TPB), nb, (const double*)D.D64, (T*)D.Dm);
+  }
+}
+
+int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed);
+
+int build_hp(cdgmg_handle* h) {
+  DLevel& l0 = h->lv[0];
+  cdgmg_handle* in = h->inner;
+  NP_DISPATCH(h->np, launch(h, -1, k_diag_inverse<NP>, dim3(grid_for(l0.n)), dim3(TPB), l0.n,
+                            (const int64_t*)l0.sblk, (const double*)l0.A64, l0.D64, h->err, 1));
+  RETURN_IF(check_err(h, CDGMG_ERR_SINGULAR, "setup: a diagonal block is not positive definite"));
+  const int64_t tot = l0.ns * h->W0 * (int64_t)h->np1 * h->np1 * WAVE;
+  HP_DISPATCH(h->np, h->np1, launch(h, -1, k_galerkin_p<NP0, NP1>, dim3(grid_for(tot)), dim3(TPB), l0.ns, h->W0,
+                                    (const double*)l0.A64, (const double*)h->Tp64, in->lv[0].A64));
+  RETURN_IF(build_operators(in, nullptr, false));
+  if (h->o.mg_precision == CDGMG_MG_FP32) {
+    HP_DISPATCH(h->np, h->np1, prescale_hp<float, NP0, NP1>(h));
+  } else {
+    HP_DISPATCH(h->np, h->np1, prescale_hp<double, NP0, NP1>(h));
+  }
+  HIPCHK(hipGetLastError());
+  return CDGMG_OK;
+}
+
 template <typename T, int NP>
 void prescale(cdgmg_handle* h) {
   constexpr int NP2 = NP * NP;
@@ -531,7 +613,7 @@ void prescale(cdgmg_handle* h) {
 // -> coarsest inverse.  kappa_dev null: rebuild from the stored kappa.
 // transposed: every level holds A_l^T (A_0^T, then the same Galerkin products,
 // since (L^T A L)^T = L^T A^T L), for the adjoint of a nonsymmetric operator.
-int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed = false) {
+int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed) {
   const int np = h->np, np2 = np * np;
   DLevel& l0 = h->lv[0];
   if (kappa_dev) {
@@ -539,10 +621,12 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed = 
            h->kappa, h->err);
     RETURN_IF(check_err(h, CDGMG_ERR_ARG, "setup: kappa must be positive and finite"));
   }
-  NP_DISPATCH(np, launch(h, -1, k_assemble_A0<NP>, dim3(grid_for(h->N0)), dim3(TPB), h->N0, h->W0,
-                         (const int32_t*)l0.cols, (const int64_t*)l0.sblk, (const double*)h->UA,
-                         (const double*)h->UH, (const int8_t*)h->hostflag, (const int8_t*)h->revslot,
-                         (const double*)h->kappa, (const double*)h->UC, l0.A64));
+  if (!h->given_A0)
+    NP_DISPATCH(np, launch(h, -1, k_assemble_A0<NP>, dim3(grid_for(h->N0)), dim3(TPB), h->N0, h->W0,
+                           (const int32_t*)l0.cols, (const int64_t*)l0.sblk, (const double*)h->UA,
+                           (const double*)h->UH, (const int8_t*)h->hostflag, (const int8_t*)h->revslot,
+                           (const double*)h->kappa, (const double*)h->UC, l0.A64));
+  if (h->inner) return build_hp(h);
   if (transposed) {
     NP_DISPATCH(np, launch(h, -1, k_transpose_A0<NP>, dim3(grid_for(h->N0)), dim3(TPB), h->N0, h->W0,
                            (const int64_t*)l0.sblk, (const int32_t*)l0.cols, (const int8_t*)h->revslot,
@@ -635,7 +719,7 @@ template <typename T, int NP>
 void smooth_sweeps(cdgmg_handle* h, int l, int count, T** x, T** xb, const double* dv = nullptr) {
   DLevel& d = h->lv[l];
   const T omega = (T)h->o.omega;
-  const int cls = l == 0 ? CDGMG_K_SMOOTH0 : CDGMG_K_SMOOTH;
+  const int cls = l == 0 && !h->given_A0 ? CDGMG_K_SMOOTH0 : CDGMG_K_SMOOTH;
   for (int s = 0; s < count; ++s) {
     if (l == 0) {
       const bool dot = dv && s == count - 1;
@@ -670,6 +754,38 @@ void dot_t(cdgmg_handle* h, const T* z, const double* dv, int* nparts) {
 // few wavefronts over the compute units
 inline int row_tpb(const cdgmg_handle* h, int l) { return h->lv[l].n < 100000 ? WAVE : TPB; }
 
+void* vcycle(cdgmg_handle* h, const double* r64, const double* dv, int* nparts);
+
+// hp front end: the degree-p level 0 smooths, restricts to the lower-degree
+// space (D^T T)^T (D^{-1} r), calls the lower hierarchy's V-cycle and prolongs
+// x += T z (Sec. 4, hp paragraph)
+template <typename T, int NP>
+T* vcycle_hp(cdgmg_handle* h, const double* r64, const double* dv, int* nparts, T* x, T* xb) {
+  DLevel& d = h->lv[0];
+  const T omega = (T)h->o.omega;
+  const int nu1 = h->o.nu1, nu2 = h->o.nu2;
+  const T w1 = nu1 > 0 ? omega : T(0);
+  cdgmg_handle* in = h->inner;
+  L0_DISPATCH(h, launch(h, CDGMG_K_SMOOTH, k_entry0<T, NP, H>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n, r64,
+                        (const T*)d.Dm, w1, (T*)d.b, x));
+  smooth_sweeps<T, NP>(h, 0, nu1 > 1 ? nu1 - 1 : 0, &x, &xb);
+  HP_DISPATCH(NP, h->np1, L0_DISPATCH(h, launch(h, CDGMG_K_RESTRICT, k_restrict0_rect<T, NP, NP1, H, NF>,
+                                                dim3((unsigned)d.ns), dim3(WAVE * H), d.n, (const int32_t*)d.cols,
+                                                (const T*)d.At, (const T*)d.b, (const T*)x, (const T*)d.Lt,
+                                                in->t1)));
+  void* zin = vcycle(in, in->t1, nullptr, nullptr);
+  HP_DISPATCH(NP, h->np1, launch(h, CDGMG_K_PROLONG, k_prolong_rect<T, NP0, NP1>, dim3(grid_for(d.n)), dim3(TPB),
+                                 d.n, (const T*)h->Tpm, (const T*)zin, x));
+  smooth_sweeps<T, NP>(h, 0, nu2, &x, &xb, dv);
+  if (dv) {
+    if (nu2 > 0)
+      *nparts = (int)d.ns;
+    else
+      dot_t<T>(h, x, dv, nparts);
+  }
+  return x;
+}
+
 // One V-cycle z = B r (Sec. 4): on each level the first pre-smoothing sweep
 // starts from zero and is fused with forming D^{-1} b; residual and
 // restriction are fused; the coarsest level applies the dense inverse.
@@ -686,6 +802,7 @@ T* vcycle_t(cdgmg_handle* h, const double* r64, const double* dv, int* nparts) {
     xs[l] = (T*)h->lv[l].x;
     xbs[l] = (T*)h->lv[l].xb;
   }
+  if (h->inner) return vcycle_hp<T, NP>(h, r64, dv, nparts, xs[0], xbs[0]);
   if (L == 0) {
     DLevel& d = h->lv[0];
     launch(h, CDGMG_K_VECTOR, k_cast<double, T>, dim3(grid_for(d.n * NP)), dim3(TPB), d.n * NP, r64, (T*)d.b);
@@ -793,6 +910,7 @@ int true_residual(cdgmg_handle* h, double* rr) {
 void reset_profile(cdgmg_handle* h) {
   h->evs.clear();
   h->pool_next = 0;
+  if (h->inner) reset_profile(h->inner);
 }
 
 void collect_profile(cdgmg_handle* h, cdgmg_solve_info* info) {
@@ -803,13 +921,14 @@ void collect_profile(cdgmg_handle* h, cdgmg_solve_info* info) {
   }
   if (!h->o.profile) return;
   (void)hipStreamSynchronize(h->stream);
-  for (auto& e : h->evs) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
-      info->kernel_ms[e.cls] += ms;
-      info->kernel_launches[e.cls] += 1;
+  for (cdgmg_handle* g = h; g; g = g->inner)
+    for (auto& e : g->evs) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+        info->kernel_ms[e.cls] += ms;
+        info->kernel_launches[e.cls] += 1;
+      }
     }
-  }
 }
 
 // solve A x = b with h->b set (internal order); result in x_hi + x_lo.
@@ -1147,6 +1266,66 @@ int ensure_direction(cdgmg_handle* h, bool transposed) {
   return build_operators(h, nullptr, transposed);
 }
 
+// hp front end: the next p-level (degree p - 1, or 1 with p_jump) on the
+// same mesh and hierarchy; its level-0 operator is set from this level 0.
+// Below degree 2 the inner handle holds the p = 1 agglomeration hierarchy,
+// above it recurses.  This handle keeps its level 0 only.
+int upload_embedding(cdgmg_handle* h);
+
+int setup_inner(cdgmg_handle* h, const cdgmg_mesh& mesh, const cdgmg_hierarchy& hier) {
+  cdgmg_handle* in = new (std::nothrow) cdgmg_handle();
+  if (!in) return CDGMG_ERR_NOMEM;
+  h->inner = in;
+  const int q = h->o.p_jump ? 1 : h->P.p - 1;
+  in->o = h->o;
+  in->o.kernel_variant = 0;
+  in->o.outer = CDGMG_OUTER_FCG;  // only its V-cycle runs: no Krylov work vectors
+  in->stream = h->stream;
+  in->given_A0 = true;
+  int rc;
+  try {
+    rc = build_problem(mesh, q, hier, in->o, in->P);
+  } catch (const std::exception& e) {
+    set_error(std::string("setup: ") + e.what());
+    rc = CDGMG_ERR_NOMEM;
+  }
+  if (rc) return rc;
+  in->H0 = pick_h0(in->P.np, 0);
+  const Level &a = h->P.lv[0], &b = in->P.lv[0];
+  if (a.perm != b.perm || a.cols != b.cols || a.slice_blk != b.slice_blk) {
+    set_error("setup: the lower-degree level does not share the level-0 order and pattern");
+    return CDGMG_ERR_HIERARCHY;
+  }
+  h->np1 = in->P.np;
+  h->P.L = 0;
+  h->P.lv.resize(1);
+  if (q >= 2) RETURN_IF(setup_inner(in, mesh, hier));
+  RETURN_IF(upload_problem(in));
+  if (in->inner) RETURN_IF(upload_embedding(in));
+  return CDGMG_OK;
+}
+
+// the embedding T[i][k] = lower-degree nodal basis k at the degree-p node i
+int upload_embedding(cdgmg_handle* h) {
+  const RefElem &R = h->P.ref, &R1 = h->inner->P.ref;
+  const int np = R.np, np1 = R1.np, d = R.d;
+  std::vector<double> T((size_t)np * np1);
+  double phi[32];
+  for (int i = 0; i < np; ++i) {
+    R1.eval(&R.nodes[(size_t)i * d], phi);
+    for (int k = 0; k < np1; ++k) T[(size_t)i * np1 + k] = phi[k];
+  }
+  RETURN_IF(upload(h, &h->Tp64, T));
+  if (h->o.mg_precision == CDGMG_MG_FP32) {
+    float* tf;
+    RETURN_IF(upload(h, &tf, std::vector<float>(T.begin(), T.end())));
+    h->Tpm = tf;
+  } else {
+    h->Tpm = h->Tp64;
+  }
+  return CDGMG_OK;
+}
+
 int check_handle(cdgmg_handle* h) {
   if (!h) {
     set_error("null handle");
@@ -1183,6 +1362,8 @@ void cdgmg_default_options(cdgmg_options* o) {
   o->restart = 50;
   o->beta = 0.0;
   o->velocity[0] = 1.0;
+  o->p_coarse = 0;
+  o->p_jump = 0;
 }
 
 int cdgmg_agglomerate(const cdgmg_mesh* mesh, int max_levels, int64_t coarse_dofs_max, int p, uint64_t seed,
@@ -1257,8 +1438,10 @@ int cdgmg_setup(const cdgmg_mesh* mesh, int p, const double* kappa_dev, const cd
       rc = CDGMG_ERR_ARG;
     }
   }
+  if (!rc && o.p_coarse == 1 && p >= 2) rc = setup_inner(h, *mesh, *hier);
   if (!rc) rc = upload_problem(h);
-  if (!rc) rc = build_operators(h, kappa_dev);
+  if (!rc && h->inner) rc = upload_embedding(h);
+  if (!rc) rc = build_operators(h, kappa_dev, false);
   if (!rc && hipStreamSynchronize(h->stream) != hipSuccess) {
     set_error("setup: device error");
     rc = CDGMG_ERR_DEVICE;
@@ -1361,6 +1544,7 @@ int cdgmg_apply_mass(cdgmg_handle* h, const double* x_dev, double* y_dev) {
 
 int cdgmg_apply_A(cdgmg_handle* h, int level, int precision, const void* x_dev, void* y_dev) {
   RETURN_IF(check_handle(h));
+  if (h->inner && level >= 1) return cdgmg_apply_A(h->inner, level - 1, precision, x_dev, y_dev);
   if (level < 0 || level > h->L || (precision != 0 && precision != 1) ||
       (precision == 1 && h->o.mg_precision != CDGMG_MG_FP32)) {
     set_error("apply_A: invalid level or precision");
@@ -1408,6 +1592,14 @@ int cdgmg_vcycle(cdgmg_handle* h, const double* r_dev, double* z_dev) {
 
 int cdgmg_level_info(cdgmg_handle* h, int* n_levels, int64_t* n_elem, int64_t* nnzb) {
   RETURN_IF(check_handle(h));
+  if (h->inner) {  // level 0 at degree p, then the lower-degree levels
+    int ni = 0;
+    RETURN_IF(cdgmg_level_info(h->inner, &ni, n_elem ? n_elem + 1 : nullptr, nnzb ? nnzb + 1 : nullptr));
+    if (n_levels) *n_levels = ni + 1;
+    if (n_elem) n_elem[0] = h->lv[0].n;
+    if (nnzb) nnzb[0] = h->lv[0].nnzb;
+    return CDGMG_OK;
+  }
   if (n_levels) *n_levels = h->L + 1;
   for (int l = 0; l <= h->L; ++l) {
     if (n_elem) n_elem[l] = h->lv[l].n;
@@ -1419,6 +1611,7 @@ int cdgmg_level_info(cdgmg_handle* h, int* n_levels, int64_t* n_elem, int64_t* n
 int cdgmg_export_operator(cdgmg_handle* h, int level, int64_t* nnzb, int64_t* row_ptr, int32_t* cols,
                           double* blocks) {
   RETURN_IF(check_handle(h));
+  if (h->inner && level >= 1) return cdgmg_export_operator(h->inner, level - 1, nnzb, row_ptr, cols, blocks);
   if (level < 0 || level > h->L || !nnzb) {
     set_error("export_operator: invalid argument");
     return CDGMG_ERR_ARG;
@@ -1471,17 +1664,20 @@ int cdgmg_node_coords(cdgmg_handle* h, double* xyz) {
 int cdgmg_set_profile(cdgmg_handle* h, int on) {
   RETURN_IF(check_handle(h));
   h->o.profile = on ? 1 : 0;
+  if (h->inner) return cdgmg_set_profile(h->inner, on);
   return CDGMG_OK;
 }
 
 int cdgmg_device_bytes(cdgmg_handle* h, size_t* bytes) {
   RETURN_IF(check_handle(h));
-  *bytes = h->bytes;
+  *bytes = 0;
+  for (const cdgmg_handle* g = h; g; g = g->inner) *bytes += g->bytes;
   return CDGMG_OK;
 }
 
 int cdgmg_destroy(cdgmg_handle* h) {
   if (!h) return CDGMG_OK;
+  if (h->inner) cdgmg_destroy(h->inner);
   if (h->stream || !h->allocs.empty()) (void)hipStreamSynchronize(h->stream);
   for (void* p : h->allocs) (void)hipFree(p);
   for (auto e : h->pool) (void)hipEventDestroy(e);
