@@ -42,6 +42,18 @@ struct DevEll {
   const int64_t* sblk;    // [nslices + 1]
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2:
+// block b runs on XCD b % 8.  Rows follow the mesh order (neighbours mostly
+// lie in nearby slices), so a kernel with one block per slice gives XCD k the
+// k-th contiguous run of slices, and the neighbour gathers of its rows hit its
+// own L2.  A bijection of [0, gridDim.x).
+constexpr int NXCD = 8;
+__device__ __forceinline__ int64_t xcd_slice() {
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  const int64_t q = nb / NXCD, rem = nb % NXCD, k = b % NXCD;
+  return k * q + (k < rem ? k : rem) + b / NXCD;
+}
+
 __device__ __forceinline__ int64_t blk_off(int64_t B, int w, int np2, int ij, int lane) {
   return (B + (int64_t)WAVE * w) * np2 + (int64_t)ij * WAVE + lane;
 }

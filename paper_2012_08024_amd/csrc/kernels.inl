@@ -589,7 +589,7 @@ __global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* _
                                                      double* __restrict__ part) {
   constexpr int NI = NP / H;
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
-  const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
+  const int64_t sl = xcd_slice(), r = sl * WAVE + lane;
   double d = 0.0;
   if (r < n) {
     T acc[NI];
@@ -605,7 +605,7 @@ __global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* _
   if constexpr (DOT) {
     __shared__ double sh[H];
     d = block_sum(d, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = d;
+    if (threadIdx.x == 0) part[sl] = d;
   }
 }
 
@@ -617,7 +617,7 @@ __global__ __launch_bounds__(WAVE * H) void k_restrict0(int64_t n, const int32_t
   constexpr int NP2 = NP * NP, NI = NP / H;
   __shared__ T sres[NP][WAVE];
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
-  const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
+  const int64_t sl = xcd_slice(), r = sl * WAVE + lane;
   const bool valid = r < n;
   if (valid) {
     T acc[NI];
@@ -627,7 +627,7 @@ __global__ __launch_bounds__(WAVE * H) void k_restrict0(int64_t n, const int32_t
   }
   __syncthreads();
   if (!valid) return;
-  const T* Lr = Lt + (int64_t)blockIdx.x * WAVE * NP2 + lane;
+  const T* Lr = Lt + sl * WAVE * NP2 + lane;
 #pragma unroll
   for (int t = 0; t < NI; ++t) {
     const int j = h * NI + t;
@@ -645,12 +645,12 @@ __global__ __launch_bounds__(WAVE * H) void k_entry0(int64_t n, const double* __
                                                      T* __restrict__ x) {
   constexpr int NP2 = NP * NP, NI = NP / H;
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
-  const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
+  const int64_t sl = xcd_slice(), r = sl * WAVE + lane;
   if (r >= n) return;
   T v[NP];
 #pragma unroll
   for (int j = 0; j < NP; ++j) v[j] = (T)src[r * NP + j];
-  const T* D = Dinv + (int64_t)blockIdx.x * WAVE * NP2 + lane;
+  const T* D = Dinv + sl * WAVE * NP2 + lane;
 #pragma unroll
   for (int t = 0; t < NI; ++t) {
     const int i = h * NI + t;
@@ -864,7 +864,7 @@ __global__ __launch_bounds__(WAVE * H) void k_restrict0_rect(int64_t n, const in
   constexpr int NI = NP0 / H, NR = NP0 * NP1;
   __shared__ T sres[NP0][WAVE];
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
-  const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
+  const int64_t sl = xcd_slice(), r = sl * WAVE + lane;
   const bool valid = r < n;
   if (valid) {
     T acc[NI];
@@ -874,7 +874,7 @@ __global__ __launch_bounds__(WAVE * H) void k_restrict0_rect(int64_t n, const in
   }
   __syncthreads();
   if (!valid) return;
-  const T* Lr = Lt + (int64_t)blockIdx.x * WAVE * NR + lane;
+  const T* Lr = Lt + sl * WAVE * NR + lane;
   for (int j = h; j < NP1; j += H) {
     T s = 0;
 #pragma unroll
@@ -1215,7 +1215,7 @@ __global__ __launch_bounds__(WAVE * H) void k_spmv_dots_hs(int64_t n, const int3
   constexpr int NP2 = NP * NP, NI = NP / H;
   __shared__ double sh[H];
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
-  const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
+  const int64_t sl = xcd_slice(), r = sl * WAVE + lane;
   double pq = 0.0, pr = 0.0;
   if (r < n) {
     constexpr int W = NF + 1;
@@ -1257,9 +1257,9 @@ __global__ __launch_bounds__(WAVE * H) void k_spmv_dots_hs(int64_t n, const int3
   }
   if constexpr (DOTS) {
     pq = block_sum(pq, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = pq;
+    if (threadIdx.x == 0) part[sl] = pq;
     pr = block_sum(pr, sh);
-    if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = pr;
+    if (threadIdx.x == 0) part[gridDim.x + sl] = pr;
   }
 }
 
@@ -1274,7 +1274,7 @@ __global__ __launch_bounds__(WAVE * H) void k_residual2_hs(int64_t n, const int3
   constexpr int NP2 = NP * NP, NI = NP / H;
   __shared__ double sh[H];
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
-  const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
+  const int64_t sl = xcd_slice(), r = sl * WAVE + lane;
   double rr = 0.0;
   if (r < n) {
     constexpr int W = NF + 1;
@@ -1315,7 +1315,7 @@ __global__ __launch_bounds__(WAVE * H) void k_residual2_hs(int64_t n, const int3
     }
   }
   rr = block_sum(rr, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = rr;
+  if (threadIdx.x == 0) part[sl] = rr;
 }
 
 // out[perm[r]] = xh[r] + xl[r]
