@@ -325,10 +325,10 @@ def main():
         result["copy_probe_gbs"] = 2 * nbytes * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
         # read-only stream of the same 1 GiB (torch's sum)
         acc = torch.zeros((), dtype=torch.float32, device="cuda")
-        torch.sum(src, out=acc)
+        torch.sum(src, dim=0, out=acc)
         e0.record()
         for _ in range(10):
-            torch.sum(src, out=acc)
+            torch.sum(src, dim=0, out=acc)
         e1.record()
         torch.cuda.synchronize()
         result["read_probe_gbs"] = nbytes * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9

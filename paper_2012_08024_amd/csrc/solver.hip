@@ -479,12 +479,14 @@ int upload_problem(cdgmg_handle* h) {
     // padding entries past n n_p stay zero (the dense coarsest product reads them)
     for (void* v : {D.b, D.x, D.xb, D.t}) HIPCHK(hipMemsetAsync(v, 0, vb, h->stream));
   }
-  // level-0 kappa-free blocks
-  RETURN_IF(upload(h, &h->UA, to_sliced(P.UA, P.lv[0], h->W0, np2)));
-  RETURN_IF(upload(h, &h->UH, to_sliced(P.UH, P.lv[0], h->W0, np2)));
-  RETURN_IF(upload(h, &h->hostflag, P.hostflag));
-  RETURN_IF(upload(h, &h->revslot, P.revslot));
-  RETURN_IF(upload(h, &h->M, to_rows(P.Mblk, P.N0, np2)));
+  // level-0 kappa-free blocks (a level 0 set by its owner needs none of them)
+  if (!h->given_A0) {
+    RETURN_IF(upload(h, &h->UA, to_sliced(P.UA, P.lv[0], h->W0, np2)));
+    RETURN_IF(upload(h, &h->UH, to_sliced(P.UH, P.lv[0], h->W0, np2)));
+    RETURN_IF(upload(h, &h->hostflag, P.hostflag));
+    RETURN_IF(upload(h, &h->revslot, P.revslot));
+    RETURN_IF(upload(h, &h->M, to_rows(P.Mblk, P.N0, np2)));
+  }
   if (!P.UC.empty()) {
     RETURN_IF(upload(h, &h->UC, to_sliced(P.UC, P.lv[0], h->W0, np2)));
     RETURN_IF(dalloc(h, &h->Atmp, (size_t)h->lv[0].slots * np2));
@@ -509,9 +511,11 @@ int upload_problem(cdgmg_handle* h) {
       h->AinvP = h->dense;
     }
   }
-  // outer vectors
+  // outer vectors; a lower hp level runs only its V-cycle and level products,
+  // which use t1 and t2
   const size_t m = (size_t)h->lv[0].ns * SLICE * np;
   for (double** v : {&h->b, &h->x, &h->xl, &h->r, &h->p, &h->q, &h->t1, &h->t2}) {
+    if (h->given_A0 && v != &h->t1 && v != &h->t2) continue;
     RETURN_IF(dalloc(h, v, m));
     HIPCHK(hipMemsetAsync(*v, 0, m * sizeof(double), h->stream));
   }
