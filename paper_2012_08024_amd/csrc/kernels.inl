@@ -25,19 +25,29 @@ __global__ void k_assemble_A0(int64_t n, int W, const int32_t* __restrict__ cols
     const int hf = hostflag[r * W + w];
     const int32_t c = cols[B + (int64_t)WAVE * w + lane];
     const double s = hf == 1 ? kr : (hf == 0 ? kappa[c] : 0.0);
+#pragma unroll 10
     for (int ij = 0; ij < NP2; ++ij) {
       const int64_t o = blk_off(B, w, NP2, ij, lane);
       A[o] = s * UA[o] + (UC ? UC[o] : 0.0);
     }
   }
+  // the neighbours that host a shared facet add kappa_c UH(c, revslot) to the
+  // diagonal block: their block offsets and kappa first, then the entries
+  constexpr int WM = 5;  // at most n_f + 1 = 5 slots (tetrahedra)
+  int64_t ho[WM - 1];
+  double hk[WM - 1];
+  int nh = 0;
+  for (int w = 1; w < W; ++w) {
+    if (hostflag[r * W + w] != 0) continue;
+    const int32_t c = cols[B + (int64_t)WAVE * w + lane];
+    ho[nh] = blk_off(sblk[c / WAVE], revslot[r * W + w], NP2, 0, c % WAVE);
+    hk[nh] = kappa[c];
+    ++nh;
+  }
+#pragma unroll 10
   for (int ij = 0; ij < NP2; ++ij) {
     double acc = kr * UA[blk_off(B, 0, NP2, ij, lane)];
-    for (int w = 1; w < W; ++w) {
-      if (hostflag[r * W + w] != 0) continue;
-      const int32_t c = cols[B + (int64_t)WAVE * w + lane];
-      const int rs = revslot[r * W + w];
-      acc += kappa[c] * UH[blk_off(sblk[c / WAVE], rs, NP2, ij, c % WAVE)];
-    }
+    for (int t = 0; t < nh; ++t) acc += hk[t] * UH[ho[t] + (int64_t)ij * WAVE];
     if (UC) acc += UC[blk_off(B, 0, NP2, ij, lane)];
     A[blk_off(B, 0, NP2, ij, lane)] = acc;
   }
@@ -314,49 +324,49 @@ __global__ void k_dense_init(int64_t nd, int64_t ld, double* __restrict__ dense)
   dense[idx] = (i == j && i >= nd) ? 1.0 : 0.0;
 }
 
-// P = A_KK^{-1} by unblocked Gauss-Jordan in LDS (one workgroup of 256);
+// P = A_KK^{-1} by unblocked Gauss-Jordan (one workgroup of 256, the block in
+// registers);
 // writes P into A_KK and into Pout; err = 1 on a non-positive (definite) or
 // zero pivot
 __global__ __launch_bounds__(256) void k_gj_pivot(int64_t ld, int K, double* __restrict__ dense,
                                                   double* __restrict__ Pout, int* __restrict__ err, int definite) {
-  __shared__ double S[GJB][GJB + 1];
-  __shared__ double rowk[GJB], colk[GJB];
-  const int tid = threadIdx.x;
+  // thread (i0, j) keeps rows i0 + 4 m, m < 16, of column j in registers; per
+  // step only the pivot row and column go through LDS, double-buffered by the
+  // step's parity so that one barrier per step suffices
+  constexpr int RM = GJB / 4;
+  __shared__ double rowk[2][GJB], colk[2][GJB];
+  const int tid = threadIdx.x, j = tid % GJB, i0 = tid / GJB;
   double* Akk = dense + (int64_t)K * GJB * ld + (int64_t)K * GJB;
-  for (int e = tid; e < GJB * GJB; e += 256) S[e / GJB][e % GJB] = Akk[(int64_t)(e / GJB) * ld + e % GJB];
-  __syncthreads();
+  double v[RM];
+#pragma unroll
+  for (int m = 0; m < RM; ++m) v[m] = Akk[(int64_t)(i0 + 4 * m) * ld + j];
   bool bad = false;
+#pragma unroll
   for (int k = 0; k < GJB; ++k) {
-    const double p = S[k][k];
-    if (tid < GJB) {
-      rowk[tid] = S[k][tid];
-      colk[tid] = S[tid][k];
-    }
+    const int b = k & 1;
+    if (i0 == k % 4) rowk[b][j] = v[k / 4];
+    if (j == k)
+#pragma unroll
+      for (int m = 0; m < RM; ++m) colk[b][i0 + 4 * m] = v[m];
     __syncthreads();
+    const double p = rowk[b][k];
     if (tid == 0 && (definite ? !(p > 0.0) : !(p != 0.0 && p == p))) bad = true;
     const double ip = 1.0 / p;
-    // 16 elements per thread, unrolled so that their LDS reads overlap
-    double v[GJB * GJB / 256];
+    const double rj = rowk[b][j];
 #pragma unroll
-    for (int m = 0; m < GJB * GJB / 256; ++m) {
-      const int e = tid + 256 * m;
-      const int i = e / GJB, j = e % GJB;
-      const double sij = S[i][j], ci = colk[i], rj = rowk[j];
-      const double gen = sij - ci * rj * ip;
+    for (int m = 0; m < RM; ++m) {
+      const int i = i0 + 4 * m;
+      const double ci = colk[b][i];
+      const double gen = v[m] - ci * rj * ip;
       v[m] = (i == k) ? ((j == k) ? ip : rj * ip) : ((j == k) ? -ci * ip : gen);
     }
-#pragma unroll
-    for (int m = 0; m < GJB * GJB / 256; ++m) {
-      const int e = tid + 256 * m;
-      S[e / GJB][e % GJB] = v[m];
-    }
-    __syncthreads();
   }
   if (tid == 0 && bad) *err = 1;
-  for (int e = tid; e < GJB * GJB; e += 256) {
-    const double v = S[e / GJB][e % GJB];
-    Akk[(int64_t)(e / GJB) * ld + e % GJB] = v;
-    Pout[e] = v;
+#pragma unroll
+  for (int m = 0; m < RM; ++m) {
+    const int i = i0 + 4 * m;
+    Akk[(int64_t)i * ld + j] = v[m];
+    Pout[i * GJB + j] = v[m];
   }
 }
 
