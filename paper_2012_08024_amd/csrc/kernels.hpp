@@ -8,6 +8,12 @@
 // Per-row blocks (D^{-1}, transfer blocks L_e, mass blocks) use the same layout
 // with W = 1: (64 s) n_p^2 + (i n_p + j) 64 + lane.  Vectors are row-major
 // [row][n_p].  Slot 0 of every row is its diagonal block.
+//
+// Cache use: the FP32 level-0 V-cycle operator (240 MB at 2D p = 3, 2e5
+// elements) is read four times per cycle and nearly fits the 256 MB
+// last-level cache.  The streams read once per cycle or per outer iteration
+// (the FP64 outer operator, level-0 D^{-1}, transfer blocks) use
+// non-temporal loads so that they do not push it out.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

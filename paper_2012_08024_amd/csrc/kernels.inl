@@ -507,7 +507,7 @@ __global__ __launch_bounds__(TPB) void k_prolong(int64_t n, const int32_t* __res
   for (int i = 0; i < NP; ++i) {
     T s = 0;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) s += Lr[(i * NP + j) * WAVE] * cv[j];
+    for (int j = 0; j < NP; ++j) s += __builtin_nontemporal_load(Lr + (i * NP + j) * WAVE) * cv[j];
     x[r * NP + i] += s;
   }
 }
@@ -643,7 +643,7 @@ __global__ __launch_bounds__(WAVE * H) void k_restrict0(int64_t n, const int32_t
     const int j = h * NI + t;
     T s = 0;
 #pragma unroll
-    for (int i = 0; i < NP; ++i) s += Lr[(i * NP + j) * WAVE] * sres[i][lane];
+    for (int i = 0; i < NP; ++i) s += __builtin_nontemporal_load(Lr + (i * NP + j) * WAVE) * sres[i][lane];
     t_out[r * NP + j] = s;
   }
 }
@@ -666,7 +666,7 @@ __global__ __launch_bounds__(WAVE * H) void k_entry0(int64_t n, const double* __
     const int i = h * NI + t;
     T s = 0;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) s += D[(i * NP + j) * WAVE] * v[j];
+    for (int j = 0; j < NP; ++j) s += __builtin_nontemporal_load(D + (i * NP + j) * WAVE) * v[j];
     bt[r * NP + i] = s;
     x[r * NP + i] = omega * s;
   }
@@ -888,7 +888,7 @@ __global__ __launch_bounds__(WAVE * H) void k_restrict0_rect(int64_t n, const in
   for (int j = h; j < NP1; j += H) {
     T s = 0;
 #pragma unroll
-    for (int i = 0; i < NP0; ++i) s += Lr[(i * NP1 + j) * WAVE] * sres[i][lane];
+    for (int i = 0; i < NP0; ++i) s += __builtin_nontemporal_load(Lr + (i * NP1 + j) * WAVE) * sres[i][lane];
     t_out[r * NP1 + j] = (double)s;
   }
 }
@@ -1248,9 +1248,9 @@ __global__ __launch_bounds__(WAVE * H) void k_spmv_dots_hs(int64_t n, const int3
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
           if constexpr (COMP)
-            dot2_acc(Ab[(t * NP + j) * WAVE], xv[j], s[t], c[t]);
+            dot2_acc(__builtin_nontemporal_load(Ab + (t * NP + j) * WAVE), xv[j], s[t], c[t]);
           else
-            s[t] = __builtin_fma(Ab[(t * NP + j) * WAVE], xv[j], s[t]);
+            s[t] = __builtin_fma(__builtin_nontemporal_load(Ab + (t * NP + j) * WAVE), xv[j], s[t]);
         }
     }
 #pragma unroll
@@ -1312,7 +1312,7 @@ __global__ __launch_bounds__(WAVE * H) void k_residual2_hs(int64_t n, const int3
       for (int t = 0; t < NI; ++t)
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
-          const double a = Ab[(t * NP + j) * WAVE];
+          const double a = __builtin_nontemporal_load(Ab + (t * NP + j) * WAVE);
           dot2_acc(-a, hv[j], s[t], c[t]);
           c[t] = __builtin_fma(-a, lv[j], c[t]);
         }
