@@ -60,6 +60,16 @@ __device__ __forceinline__ int64_t xcd_slice() {
   return k * q + (k < rem ? k : rem) + b / NXCD;
 }
 
+// Passes over the level-0 V-cycle operator alternate their direction (rev):
+// the operator is slightly larger than what the last-level cache keeps of it,
+// and a pass that starts where the previous one ended finds that end still
+// cached, where a pass in the same direction would find its start evicted.
+// The order of rows does not change a Jacobi sweep's result.
+__device__ __forceinline__ int64_t slice_order(int rev) {
+  const int64_t s = xcd_slice();
+  return rev ? (int64_t)gridDim.x - 1 - s : s;
+}
+
 __device__ __forceinline__ int64_t blk_off(int64_t B, int w, int np2, int ij, int lane) {
   return (B + (int64_t)WAVE * w) * np2 + (int64_t)ij * WAVE + lane;
 }

@@ -596,10 +596,10 @@ template <typename T, int NP, int H, int NF, bool DOT>
 __global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* __restrict__ cols, const T* __restrict__ At,
                                                      const T* __restrict__ bt, const T* __restrict__ xin, T omega,
                                                      T* __restrict__ xout, const double* __restrict__ dv,
-                                                     double* __restrict__ part) {
+                                                     double* __restrict__ part, int rev) {
   constexpr int NI = NP / H;
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
-  const int64_t sl = xcd_slice(), r = sl * WAVE + lane;
+  const int64_t sl = slice_order(rev), r = sl * WAVE + lane;
   double d = 0.0;
   if (r < n) {
     T acc[NI];
@@ -623,11 +623,11 @@ __global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* _
 template <typename T, int NP, int H, int NF>
 __global__ __launch_bounds__(WAVE * H) void k_restrict0(int64_t n, const int32_t* __restrict__ cols, const T* __restrict__ At,
                                                         const T* __restrict__ bt, const T* __restrict__ x,
-                                                        const T* __restrict__ Lt, T* __restrict__ t_out) {
+                                                        const T* __restrict__ Lt, T* __restrict__ t_out, int rev) {
   constexpr int NP2 = NP * NP, NI = NP / H;
   __shared__ T sres[NP][WAVE];
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
-  const int64_t sl = xcd_slice(), r = sl * WAVE + lane;
+  const int64_t sl = slice_order(rev), r = sl * WAVE + lane;
   const bool valid = r < n;
   if (valid) {
     T acc[NI];
@@ -870,11 +870,11 @@ template <typename T, int NP0, int NP1, int H, int NF>
 __global__ __launch_bounds__(WAVE * H) void k_restrict0_rect(int64_t n, const int32_t* __restrict__ cols,
                                                              const T* __restrict__ At, const T* __restrict__ bt,
                                                              const T* __restrict__ x, const T* __restrict__ Lt,
-                                                             double* __restrict__ t_out) {
+                                                             double* __restrict__ t_out, int rev) {
   constexpr int NI = NP0 / H, NR = NP0 * NP1;
   __shared__ T sres[NP0][WAVE];
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
-  const int64_t sl = xcd_slice(), r = sl * WAVE + lane;
+  const int64_t sl = slice_order(rev), r = sl * WAVE + lane;
   const bool valid = r < n;
   if (valid) {
     T acc[NI];
@@ -1139,11 +1139,11 @@ __global__ __launch_bounds__(TPB) void k_update_xr2(int64_t m, const double* __r
     const double y = (a * p[i]);
     const double ey = __builtin_fma(a, p[i], -y);
     double hi, e;
-    two_sum(xh[i], y, hi, e);
-    const double lo = (xl[i] + (e + ey));
+    two_sum(__builtin_nontemporal_load(xh + i), y, hi, e);
+    const double lo = (__builtin_nontemporal_load(xl + i) + (e + ey));
     const double nh = (hi + lo);
-    xh[i] = nh;
-    xl[i] = (lo - (nh - hi));
+    __builtin_nontemporal_store(nh, xh + i);
+    __builtin_nontemporal_store((lo - (nh - hi)), xl + i);
     const double ri = r[i] - a * q[i];
     r[i] = ri;
     rr += ri * ri;
@@ -1348,7 +1348,7 @@ __global__ void k_update_p(int64_t m, const T* __restrict__ z, double* __restric
                            double sign, int first) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
-  const double zi = (double)z[i];
+  const double zi = (double)__builtin_nontemporal_load(z + i);
   p[i] = first ? zi : zi + sign * s[SC_BETA] * p[i];
 }
 
@@ -1373,7 +1373,7 @@ __global__ __launch_bounds__(TPB) void k_update_xr(int64_t m, const double* __re
   const double a = s[SC_ALPHA];
   double rr = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-    x[i] += a * p[i];
+    __builtin_nontemporal_store(__builtin_nontemporal_load(x + i) + a * p[i], x + i);
     const double ri = r[i] - a * q[i];
     r[i] = ri;
     rr += ri * ri;

@@ -164,6 +164,9 @@ struct cdgmg_handle {
   cdgmg_handle* inner = nullptr;
   bool given_A0 = false;   // this level 0 is set by the owner (T^T A_0 T), not assembled from kappa
   int np1 = 0;
+  // level-0 passes over the V-cycle operator so far; their parity sets the
+  // direction of the next one
+  uint64_t at_pass = 0;
   double* Tp64 = nullptr;
   void* Tpm = nullptr;
   double* Atmp = nullptr;  // A_0^T staging (beta != 0)
@@ -727,14 +730,15 @@ void smooth_sweeps(cdgmg_handle* h, int l, int count, T** x, T** xb, const doubl
   for (int s = 0; s < count; ++s) {
     if (l == 0) {
       const bool dot = dv && s == count - 1;
+      const int rev = h->at_pass++ & 1;
       if (dot) {
         L0_DISPATCH(h, launch(h, cls, k_sweep0<T, NP, H, NF, true>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
                               (const int32_t*)d.cols, (const T*)d.At, (const T*)d.b, (const T*)*x, omega, *xb, dv,
-                              h->part));
+                              h->part, rev));
       } else {
         L0_DISPATCH(h, launch(h, cls, k_sweep0<T, NP, H, NF, false>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
                               (const int32_t*)d.cols, (const T*)d.At, (const T*)d.b, (const T*)*x, omega, *xb,
-                              (const double*)nullptr, (double*)nullptr));
+                              (const double*)nullptr, (double*)nullptr, rev));
       }
     } else {
       G_DISPATCH(d.grp_s, launch(h, cls, k_sweep_grp<T, NP, G>, dim3(grid_for(d.n * G)), dim3(TPB), d.n,
@@ -773,10 +777,11 @@ T* vcycle_hp(cdgmg_handle* h, const double* r64, const double* dv, int* nparts, 
   L0_DISPATCH(h, launch(h, CDGMG_K_SMOOTH, k_entry0<T, NP, H>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n, r64,
                         (const T*)d.Dm, w1, (T*)d.b, x));
   smooth_sweeps<T, NP>(h, 0, nu1 > 1 ? nu1 - 1 : 0, &x, &xb);
+  const int rev = h->at_pass++ & 1;
   HP_DISPATCH(NP, h->np1, L0_DISPATCH(h, launch(h, CDGMG_K_RESTRICT, k_restrict0_rect<T, NP, NP1, H, NF>,
                                                 dim3((unsigned)d.ns), dim3(WAVE * H), d.n, (const int32_t*)d.cols,
                                                 (const T*)d.At, (const T*)d.b, (const T*)x, (const T*)d.Lt,
-                                                in->t1)));
+                                                in->t1, rev)));
   void* zin = vcycle(in, in->t1, nullptr, nullptr);
   HP_DISPATCH(NP, h->np1, launch(h, CDGMG_K_PROLONG, k_prolong_rect<T, NP0, NP1>, dim3(grid_for(d.n)), dim3(TPB),
                                  d.n, (const T*)h->Tpm, (const T*)zin, x));
@@ -828,9 +833,10 @@ T* vcycle_t(cdgmg_handle* h, const double* r64, const double* dv, int* nparts) {
     }
     smooth_sweeps<T, NP>(h, l, nu1 > 1 ? nu1 - 1 : 0, &xs[l], &xbs[l]);
     if (l == 0) {
+      const int rev = h->at_pass++ & 1;
       L0_DISPATCH(h, launch(h, CDGMG_K_RESTRICT, k_restrict0<T, NP, H, NF>, dim3((unsigned)d.ns), dim3(WAVE * H),
                             d.n, (const int32_t*)d.cols, (const T*)d.At, (const T*)d.b, (const T*)xs[0],
-                            (const T*)d.Lt, (T*)d.t));
+                            (const T*)d.Lt, (T*)d.t, rev));
     } else {
       G_DISPATCH(d.grp_r, launch(h, CDGMG_K_RESTRICT, k_restrict_grp<T, NP, G>, dim3(grid_for(d.n * G)), dim3(TPB),
                              d.n, (const int32_t*)d.wcols, (const int64_t*)d.woff, (const T*)d.R, (const T*)d.b,
