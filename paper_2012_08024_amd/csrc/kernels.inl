@@ -1382,11 +1382,6 @@ __global__ __launch_bounds__(TPB) void k_update_xr(int64_t m, const double* __re
   if (threadIdx.x == 0) part[blockIdx.x] = rr;
 }
 
-// r = b - y
-__global__ void k_sub(int64_t m, const double* __restrict__ b, const double* __restrict__ y, double* __restrict__ r) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) r[i] = b[i] - y[i];
-}
 
 // g_e = -[ lam_e^T UA(e,0) u_e + sum_{hosted w} ( lam_e^T UA(e,w) u_c + u_e^T UA(e,w) lam_c
 //          + lam_c^T UH(e,w) u_c ) ]   (caller-order output)
