@@ -96,6 +96,40 @@ def spmv_bytes(nnzb0, n0, npb):
     return nnzb0 * npb * npb * 8 + 4 * nnzb0 + 3 * n0 * npb * 8
 
 
+def iteration_bytes(sizes, nnzb, npb, nu1=2, nu2=2, s=4):
+    """Algorithmic bytes of one FCG(1) iteration with a V(nu1, nu2) cycle in
+    precision s (bytes) and the FP64 outer loop, per level: what each kernel
+    must read and write once (operator blocks, indices, vectors), nothing for
+    re-reads.  The first pre-sweep of every level is fused with forming
+    D^{-1} b (no operator read); the last post-sweep of level 0 also reads q
+    for the fused (z, q) dot."""
+    L = len(sizes) - 1
+    n = [int(x) for x in sizes]
+    nz = [int(x) for x in nnzb]
+    p2 = npb * npb
+    out = {}
+    for l in range(L + 1):
+        if l == L:  # coarsest: children sums, then the dense inverse product
+            ld = -(-n[l] * npb // 64) * 64
+            b = n[l - 1] * npb * s + 4 * n[l] + n[l] * npb * s if l > 0 else n[l] * npb * 8
+            b += n[l] * npb * ld * s + ld * s + n[l] * npb * s
+            out["level%d" % l] = b
+            break
+        off = nz[l] - n[l]
+        sweep = off * p2 * s + 4 * off + 3 * n[l] * npb * s + (0 if l == 0 else 8 * n[l])
+        entry = (n[l] * npb * 8 if l == 0 else n[l - 1] * npb * s + 4 * n[l]) + n[l] * p2 * s + 2 * n[l] * npb * s
+        restrict = sweep + n[l] * p2 * s
+        prolong = n[l] * p2 * s + 2 * n[l] * npb * s + 4 * n[l] + n[l + 1] * npb * s
+        b = entry + (nu1 - 1) * sweep + restrict + prolong + nu2 * sweep
+        if l == 0:
+            b += n[0] * npb * 8  # q read by the last post-sweep's dot
+        out["level%d" % l] = b
+    m = n[0] * npb
+    out["outer"] = (m * s + 2 * m * 8) + spmv_bytes(nz[0], n[0], npb) + 6 * m * 8
+    out["total"] = sum(out.values())
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +242,7 @@ def main():
     achieved = sb / (avg_smooth_ms * 1e-3) / 1e9
     spb = spmv_bytes(int(nnzb[0]), mesh.n_elem, npb)
     spmv_gbs = spb / (avg_spmv_ms * 1e-3) / 1e9
+    itb = iteration_bytes(sizes, nnzb, npb) if len(nnzb) == len(sizes) else None
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "traffic_%s.json" % args.config)
     if os.path.exists(tpath):
@@ -305,6 +340,9 @@ def main():
         "outer_spmv_roofline": {"kernel": "outer q = A_0 p with dots (k_spmv_dots_hs<%d,H>, FP64)" % npb, "achieved": spmv_gbs,
                                 "frac": spmv_gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": spb,
                                 "avg_launch_ms": avg_spmv_ms},
+        "algorithmic_bytes_per_iteration": itb,
+        "achieved_gbs_per_iteration": (itb["total"] / (ms_per_step * 1e-3 / max(info.iterations, 1)) / 1e9
+                                       if itb else None),
         "cpu_baseline": cpu,
     }
     s32.close()
