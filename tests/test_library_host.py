@@ -220,3 +220,41 @@ def test_full_size_agglomeration_and_switch():
         if m.face_bc[e, i] == 0:
             flags[e, i] = 1
     assert np.array_equal(got, flags)
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    # a copy of the package without libcdgmg.so must not import (no fallback)
+    import shutil
+    import subprocess
+    import sys
+    dst = tmp_path / "paper_2012_08024_amd"
+    shutil.copytree(PKG, dst, ignore=shutil.ignore_patterns("*.so", "__pycache__", "csrc"))
+    assert not list(dst.glob("*.so"))
+    r = subprocess.run([sys.executable, "-c", "import paper_2012_08024_amd"], cwd=str(tmp_path),
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0 and "ImportError" in r.stderr and "libcdgmg.so" in r.stderr
+
+
+@pytest.mark.parametrize("case", ["size0", "parent_range", "empty_aggregate", "increasing"])
+def test_hierarchy_validation(case):
+    # malformed hierarchies are refused by the host half of setup with
+    # CDGMG_ERR_HIERARCHY (-3)
+    m = mesh2d_jittered_delaunay(6, 1)
+    parents, sizes = cm.agglomerate(m, 3, 1, p=1)
+    parents = [np.array(x, dtype=np.int32) for x in parents]
+    sizes = np.array(sizes, dtype=np.int32)
+    if case == "size0":
+        sizes = sizes.copy()
+        sizes[0] += 1
+    elif case == "parent_range":
+        parents[0] = parents[0].copy()
+        parents[0][3] = sizes[1]
+    elif case == "empty_aggregate":
+        parents[0] = parents[0].copy()
+        parents[0][parents[0] == parents[0].max()] = 0
+    else:
+        sizes = sizes.copy()
+        sizes[1] = sizes[0] + 1
+    with pytest.raises(cm.CdgmgError) as ei:
+        cm.debug_host_operator(m, 1, np.ones(m.n_elem), parents, sizes, 0)
+    assert ei.value.code == -3
