@@ -1,0 +1,65 @@
+"""The 3D p=3 workload at full size (384 000 Kuhn tetrahedra, n_p = 20,
+7 680 000 DOFs, 6 levels, a coefficient with 10^3 jumps across 32 spheres)
+in the configuration the benchmark times: sampled rows of the GPU-built
+level-0 product A_0 x against the oracle row by row, and properties that
+hold at any size for the V-cycle (n_p = 20 runs four wavefronts per slice)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2012_08024_amd as cm  # noqa: E402
+from oracle.cdg import CDG  # noqa: E402
+from oracle.mesh import Topology  # noqa: E402
+from workloads import CONFIGS, config_mesh  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def c5():
+    cfg = CONFIGS["c5"]
+    mesh, kappa = config_mesh(cfg)
+    parents, sizes = cm.agglomerate(mesh, cfg["levels"], cfg["agg_seed"], p=cfg["p"])
+    print("c5 full size", list(sizes), flush=True)
+    solver = cm.Solver(mesh, cfg["p"], kappa, parents, sizes, mg_precision=cm.MG_FP32, tol=cfg["tol"])
+    print("c5 setup done", flush=True)
+    yield cfg, mesh, kappa, solver
+    solver.close()
+
+
+def test_sampled_rows_of_A0_x_match_oracle(c5):
+    cfg, mesh, kappa, solver = c5
+    npb = solver.np
+    rng = np.random.default_rng(23)
+    x = rng.standard_normal(mesh.n_elem * npb)
+    y = solver.apply_A(0, x, 0).cpu().numpy()
+    boundary = np.array(sorted({e for (e, _) in Topology(mesh.e2v, mesh.coords).boundary}))
+    # elements inside the spheres and outside them, on the boundary, and the ends
+    hi = np.flatnonzero(kappa > 10.0)
+    lo = np.flatnonzero(kappa <= 10.0)
+    sample = sorted(set(rng.choice(hi, 12, replace=False).tolist()) | set(rng.choice(lo, 12, replace=False).tolist())
+                    | set(rng.choice(boundary, 6, replace=False).tolist()) | {0, mesh.n_elem - 1})
+    cdg = CDG(mesh.coords, mesh.e2v, mesh.face_bc, cfg["p"], subset=sample)
+    rows = cdg.A_rows(sample, kappa)
+    X = x.reshape(-1, npb)
+    for e in sample:
+        ref = np.zeros(npb)
+        mag = np.zeros(npb)
+        for c, blk in rows[e].items():
+            ref += blk @ X[c]
+            mag += np.abs(blk) @ np.abs(X[c])
+        got = y[e * npb:(e + 1) * npb]
+        assert np.abs(got - ref).max() <= 1e-13 * mag.max(), e
+
+
+def test_vcycle_is_symmetric_and_positive_at_full_size(c5):
+    cfg, mesh, kappa, solver = c5
+    n = mesh.n_elem * solver.np
+    rng = np.random.default_rng(6)
+    x, y = rng.standard_normal(n), rng.standard_normal(n)
+    Bx, By = solver.vcycle(x).cpu().numpy(), solver.vcycle(y).cpu().numpy()
+    assert abs(x @ By - y @ Bx) <= 1e-5 * np.linalg.norm(x) * np.linalg.norm(By)
+    assert x @ Bx > 0 and y @ By > 0
