@@ -154,8 +154,8 @@ def main():
                          "convection-diffusion under refinement; prints one JSON line with the table")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the solve is single-GPU; "
-              "multi-GPU domain decomposition is a design note, not built)", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU only (multi-GPU domain decomposition is "
+              "designed, not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.study:
         import torch
