@@ -322,3 +322,28 @@ def test_compensated_outer_loop_reaches_below_fp64_floor():
     ref = spl.spsolve(A.tocsc(), b)
     assert np.linalg.norm(u.cpu().numpy() - ref) <= 1e-9 * np.linalg.norm(ref)
     solver.close()
+
+
+from hypothesis import given, settings, strategies as st  # noqa: E402
+
+
+@settings(max_examples=15, deadline=None)
+@given(d=st.sampled_from([2, 3]), n=st.integers(2, 8), p=st.integers(1, 3), levels=st.integers(1, 5),
+       seed=st.integers(0, 10**6), nu=st.sampled_from([(2, 2), (0, 3), (1, 1), (3, 1)]),
+       omega=st.sampled_from([0.5, 2.0 / 3.0, 0.7]))
+def test_vcycle_fp64_random_cases(d, n, p, levels, seed, nu, omega):
+    # the FP64 V-cycle against the oracle's on random meshes, hierarchies and
+    # cycle settings (sizes from below one slice to several slices)
+    n = n if d == 3 else 2 * n
+    mesh = mesh2d_jittered_delaunay(n, seed % 97) if d == 2 else mesh3d_kuhn(n, seed % 97)
+    parents, sizes = cm.agglomerate(mesh, levels, seed, p=p)
+    kappa = np.random.default_rng(seed).uniform(0.5, 2.0, mesh.n_elem)
+    print("case random", d, n, p, list(sizes), nu, omega, flush=True)
+    solver = cm.Solver(mesh, p, kappa, parents, sizes, mg_precision=cm.MG_FP64, nu1=nu[0], nu2=nu[1], omega=omega)
+    cdg = CDG(mesh.coords, mesh.e2v, mesh.face_bc, p)
+    H = Hierarchy(cdg, parents, kappa=kappa, coarsening="primal")
+    r = np.random.default_rng(seed + 1).standard_normal(H.A[0].shape[0])
+    z = solver.vcycle(r).cpu().numpy()
+    ref = H.vcycle(r, nu[0], nu[1], omega)
+    assert np.linalg.norm(z - ref) <= 1e-11 * np.linalg.norm(ref)
+    solver.close()

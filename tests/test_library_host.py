@@ -258,3 +258,25 @@ def test_hierarchy_validation(case):
     with pytest.raises(cm.CdgmgError) as ei:
         cm.debug_host_operator(m, 1, np.ones(m.n_elem), parents, sizes, 0)
     assert ei.value.code == -3
+
+
+try:
+    from hypothesis import given, settings, strategies as st
+except ImportError:  # pragma: no cover
+    given = None
+
+if given is not None:
+    @settings(max_examples=25, deadline=None)
+    @given(d=st.sampled_from([2, 3]), n=st.integers(2, 9), mesh_seed=st.integers(0, 50),
+           seed=st.integers(0, 2**63 - 1), levels=st.integers(1, 6), p=st.integers(1, 3))
+    def test_agglomeration_bit_exact_random(d, n, mesh_seed, seed, levels, p):
+        # the library's greedy agglomeration (Alg. 1/2) reproduces the oracle's
+        # maps exactly on random meshes, seeds and level counts
+        n = n if d == 3 else 3 * n
+        m = mesh2d_jittered_delaunay(n, mesh_seed) if d == 2 else mesh3d_kuhn(n, mesh_seed)
+        parents, sizes = cm.agglomerate(m, levels, seed, p=p)
+        topo = Topology(m.e2v, m.coords)
+        ref = build_hierarchy(m.e2v, topo.neighbor_pairs(), levels, seed, n_p=cm.n_basis(d, p))
+        assert len(parents) == len(ref)
+        for a, b in zip(parents, ref):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
