@@ -324,7 +324,7 @@ def test_compensated_outer_loop_reaches_below_fp64_floor():
     solver.close()
 
 
-from hypothesis import given, settings, strategies as st  # noqa: E402
+from hypothesis import assume, given, settings, strategies as st  # noqa: E402
 
 
 @settings(max_examples=15, deadline=None)
@@ -334,9 +334,10 @@ from hypothesis import given, settings, strategies as st  # noqa: E402
 def test_vcycle_fp64_random_cases(d, n, p, levels, seed, nu, omega):
     # the FP64 V-cycle against the oracle's on random meshes, hierarchies and
     # cycle settings (sizes from below one slice to several slices)
-    n = n if d == 3 else 2 * n
+    n = 2 + n % 4 if d == 3 else 2 * n  # up to 750 tetrahedra or 512 triangles
     mesh = mesh2d_jittered_delaunay(n, seed % 97) if d == 2 else mesh3d_kuhn(n, seed % 97)
     parents, sizes = cm.agglomerate(mesh, levels, seed, p=p)
+    assume(int(sizes[-1]) * cm.n_basis(d, p) <= 3000)  # the oracle's dense coarsest solve stays quick
     kappa = np.random.default_rng(seed).uniform(0.5, 2.0, mesh.n_elem)
     print("case random", d, n, p, list(sizes), nu, omega, flush=True)
     solver = cm.Solver(mesh, p, kappa, parents, sizes, mg_precision=cm.MG_FP64, nu1=nu[0], nu2=nu[1], omega=omega)
