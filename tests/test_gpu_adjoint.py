@@ -28,7 +28,7 @@ def _loss_and_grads(solver, kappa_np, f_np, ut):
     u = cga.solve(solver, kappa, f)
     L = cga.mass_misfit(solver, u, ut)
     L.backward()
-    return u.detach(), float(L), kappa.grad.detach(), f.grad.detach()
+    return u.detach(), float(L.detach()), kappa.grad.detach(), f.grad.detach()
 
 
 def test_gradients_match_oracle_small():
