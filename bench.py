@@ -148,7 +148,8 @@ def main():
     ap.add_argument("--restart", type=int, default=50, help="GMRES restart length")
     ap.add_argument("--p-coarse", type=int, default=0, help="1: hp front end (p-multigrid to p = 1 first)")
     ap.add_argument("--p-jump", type=int, default=0, help="with --p-coarse 1: 1 goes from p straight to p = 1")
-    ap.add_argument("--study", choices=["coarsening", "coarsening-paper", "switch", "switch-paper", "convection"],
+    ap.add_argument("--study", choices=["coarsening", "coarsening-paper", "switch", "switch-paper", "convection",
+                                        "size"],
                     help="instead of the benchmark: primal vs flux coarsening over mesh size and gamma, "
                          "consistent vs natural switch (workload or the paper's solver settings), or "
                          "convection-diffusion under refinement; prints one JSON line with the table")
@@ -165,6 +166,8 @@ def main():
         kind, _, setting = args.study.partition("-")
         if kind == "convection":
             rows = studies.study_convection(log=log)
+        elif kind == "size":
+            rows = studies.study_size(log=log)
         else:
             fn = studies.study_coarsening if kind == "coarsening" else studies.study_switch
             rows = fn(setting=setting or "workload", log=log)

@@ -12,6 +12,10 @@
   counts are compared.
 * Convection-diffusion (Sec. 5): beta v . grad u with v = (1, 0), f = 1 and
   zero Dirichlet data, GMRES iterations under refinement for a range of beta.
+* Size (not a claim of the paper): the benchmark's solve (2D p = 3, V(2,2)
+  FP32 in FP64 FCG(1), tol 1e-10) on meshes from 2e4 to 1.6e6 triangles,
+  agglomerated until n_l n_p <= 2000: throughput and the level-0 sweep's
+  rate as the V-cycle operator grows past the last-level cache.
 
 All run through the C ABI on the current GPU with the V-cycle in FP64, so
 that only the operators differ between cases; the hierarchy is agglomerated
@@ -142,6 +146,49 @@ def study_switch(setting="workload", cases=None, seed=1, natural_seed=0, max_ite
                                        switch_mode=mode, switch_seed=natural_seed))
                 log("switch %s d=%d n=%d %s %s: %s" % (setting, d, n, sname, cname, row))
                 rows.append(row)
+    return rows
+
+
+def study_size(ns=(100, 158, 224, 316, 448, 632, 894), p=3, seed=2, agg_seed=12, steps=3, log=print):
+    """DOFs/s, iterations and the level-0 sweep's algorithmic bytes per
+    second against the mesh size (2D jittered Delaunay, kappa = 1, sine
+    source, FP32 V-cycle in FP64 FCG(1) to 1e-10)."""
+    import torch
+    from workloads import mesh2d_jittered_delaunay, source_sine
+    from . import MG_FP32
+    rows = []
+    for n in ns:
+        mesh = mesh2d_jittered_delaunay(n, seed)
+        parents, sizes = agglomerate(mesh, 50, agg_seed, p=p, coarse_dofs=2000)
+        log("size n=%d: mesh and hierarchy %s" % (n, list(sizes)))
+        s = Solver(mesh, p, torch.ones(mesh.n_elem, dtype=torch.float64, device="cuda"), parents, sizes,
+                   mg_precision=MG_FP32, **SETTINGS["workload"])
+        try:
+            ne, nnzb = s.level_info()
+            f = torch.tensor(source_sine(s.node_coords().reshape(-1, 2)), device="cuda")
+            s.solve(f)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                _, info = s.solve(f)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            s.set_profile(True)
+            _, pinfo = s.solve(f)
+            s.set_profile(False)
+            npb = n_basis(2, p)
+            off = int(nnzb[0]) - mesh.n_elem
+            sweep_bytes = off * npb * npb * 4 + 4 * off + 3 * mesh.n_elem * npb * 4
+            sweep_us = 1e3 * pinfo.kernel_ms["smooth0"] / max(pinfo.kernel_launches["smooth0"], 1)
+            row = dict(n=n, elements=int(mesh.n_elem), dofs=int(mesh.n_elem * npb), levels=len(sizes),
+                       iterations=info.iterations, rel_residual=info.rel_residual, solve_ms=ms,
+                       dofs_per_s=mesh.n_elem * npb / (ms * 1e-3), vcycle_operator_mb=off * npb * npb * 4 / 1e6,
+                       sweep_us=sweep_us, sweep_gbs=sweep_bytes / (sweep_us * 1e-6) / 1e9,
+                       device_gb=s.device_bytes() / 1e9)
+        finally:
+            s.close()
+        log("size n=%d: %s" % (n, row))
+        rows.append(row)
     return rows
 
 
