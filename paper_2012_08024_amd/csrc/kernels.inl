@@ -719,7 +719,7 @@ __device__ __forceinline__ T group_allsum(T v) {
 template <typename T, int NP, int G>
 __device__ __forceinline__ void grp_scaled_residual(int64_t r, int g, const int32_t* __restrict__ wcols,
                                                     const int64_t* __restrict__ woff, const T* __restrict__ R,
-                                                    const T* __restrict__ bt, const T* __restrict__ x, T* res) {
+                                                    const T* __restrict__ x, T* res) {
   // U strip columns per lane per chunk: all their loads are issued before the
   // first product, so a chunk costs one memory latency
   constexpr int U = G >= 32 ? 2 : 64 / G;
@@ -769,7 +769,7 @@ __global__ __launch_bounds__(TPB) void k_sweep_grp(int64_t n, const int32_t* __r
   const int g = (int)(gid % G);
   if (r >= n) return;
   T sum[NP];
-  grp_scaled_residual<T, NP, G>(r, g, wcols, woff, R, bt, xin, sum);
+  grp_scaled_residual<T, NP, G>(r, g, wcols, woff, R, xin, sum);
 #pragma unroll
   for (int m = 0; m < (NP + G - 1) / G; ++m) {
     const int i = g + m * G;
@@ -797,7 +797,7 @@ __global__ __launch_bounds__(TPB) void k_restrict_grp(int64_t n, const int32_t* 
   const int g = (int)(gid % G);
   if (r >= n) return;
   T res[NP];
-  grp_scaled_residual<T, NP, G>(r, g, wcols, woff, R, bt, x, res);
+  grp_scaled_residual<T, NP, G>(r, g, wcols, woff, R, x, res);
 #pragma unroll
   for (int i = 0; i < NP; ++i) res[i] = bt[r * NP + i] - x[r * NP + i] - res[i];
   const T* Lr = Lt + (r / WAVE) * WAVE * NP2 + (r % WAVE);

@@ -778,7 +778,7 @@ T* vcycle_hp(cdgmg_handle* h, const double* r64, const double* dv, int* nparts, 
                         (const T*)d.Dm, w1, (T*)d.b, x));
   smooth_sweeps<T, NP>(h, 0, nu1 > 1 ? nu1 - 1 : 0, &x, &xb);
   const int rev = h->at_pass++ & 1;
-  HP_DISPATCH(NP, h->np1, L0_DISPATCH(h, launch(h, CDGMG_K_RESTRICT, k_restrict0_rect<T, NP, NP1, H, NF>,
+  HP_DISPATCH(NP, h->np1, L0_DISPATCH(h, launch(h, CDGMG_K_RESTRICT, k_restrict0_rect<T, NP0, NP1, H, NF>,
                                                 dim3((unsigned)d.ns), dim3(WAVE * H), d.n, (const int32_t*)d.cols,
                                                 (const T*)d.At, (const T*)d.b, (const T*)x, (const T*)d.Lt,
                                                 in->t1, rev)));
