@@ -305,7 +305,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (V-cycle) / f64 (outer FCG, residual)",
+        "dtype": "f32+f64",
+        "dtype_detail": "V-cycle in f32; outer FCG (operator product, vectors, dots, true residual) in f64",
         "data": "synthetic",
         "config": {
             "p_levels": s32.p_levels,
