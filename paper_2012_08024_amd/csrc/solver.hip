@@ -114,7 +114,7 @@ struct DLevel {
   // V-cycle operators in the multigrid precision T (FP64 mode: Dm = D64, Lm = L64)
   void* At = nullptr;  // level 0: off-diagonal blocks of D^{-1} A, sliced without slot 0
   void* Dm = nullptr;  // D^{-1}
-  void* Lt = nullptr;  // D L_e (D the diagonal block of A)
+  void* Lt = nullptr;  // D^T L_e (D the diagonal block of A)
   void* Lm = nullptr;  // L_e
   int32_t* parent = nullptr;
   int32_t* child_start = nullptr;
@@ -448,7 +448,7 @@ int upload_problem(cdgmg_handle* h) {
       D.R = tmp;
       // lanes per row by the mean strip width (measured on n_p = 10 strips of
       // 53 columns: the sweep is fastest with 32 lanes on large levels and 16
-      // on smaller ones, the restriction, which also reads D L_e, with 16)
+      // on smaller ones, the restriction, which also reads D^T L_e, with 16)
       const double kmean = (double)(H.nnzb - H.n) * np / std::max<int64_t>(H.n, 1);
       if (kmean <= 96) {
         D.grp_s = H.n >= 16384 ? 32 : 16;
@@ -678,7 +678,7 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed) {
   }
   RETURN_IF(check_err(h, CDGMG_ERR_SINGULAR, flux ? "setup: a diagonal or mass block is singular"
                                                   : "setup: a diagonal block is not positive definite"));
-  // prescaled V-cycle operators D^{-1} A (off-diagonal), D L_e, and D^{-1} in the
+  // prescaled V-cycle operators D^{-1} A (off-diagonal), D^T L_e, and D^{-1} in the
   // multigrid precision
   if (h->o.mg_precision == CDGMG_MG_FP32) {
     NP_DISPATCH(np, prescale<float, NP>(h));
