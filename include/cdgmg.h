@@ -15,8 +15,10 @@
  *     last error on the calling thread is returned by cdgmg_last_error().
  *   - Host arrays passed in are read during the call only; nothing is retained.
  *   - Device arrays (suffix _dev) are caller-owned device memory, read or
- *     written on the stream given at setup.  The library owns the device
- *     memory it allocates at setup and frees it in cdgmg_destroy.
+ *     written on the stream given at setup.  The library allocates no device
+ *     memory: cdgmg_setup lays every device array of the handle out in one
+ *     caller-owned workspace of cdgmg_workspace_size bytes, which the handle
+ *     borrows until cdgmg_destroy returns (the caller frees it afterwards).
  *   - Per-element vectors are float64 [n_elem][n_p] in the caller's element
  *     order; n_p = C(p+d, d).  Level-0 coefficients are nodal values at the
  *     equispaced nodes of each simplex, ordered (with x = v0 + sum_k xi_k (v_k - v0)):
@@ -101,8 +103,8 @@ typedef struct cdgmg_options {
   int kernel_variant;  /* wavefronts per 64-row slice of the level-0 V-cycle kernels and of the
                           outer FP64 product: 0 auto (1 up to n_p = 10, 4 for n_p = 20), or
                           1, 2, 4, 5 where it divides n_p (else setup fails with
-                          CDGMG_ERR_ARG); coarse levels always give each row a group of
-                          16 to 64 lanes, chosen by the level's mean row length */
+                          CDGMG_ERR_ARG); coarse levels give each row a group of lanes
+                          (coarse_group) */
   int restart;         /* GMRES restart length m (1..200); default 50; the setup then holds
                           2m + 1 FP64 work vectors (the Arnoldi basis V and Z = B V) */
   double beta;         /* convection strength of beta v . grad u (Sec. 5, convection-diffusion),
@@ -122,11 +124,26 @@ typedef struct cdgmg_options {
                           agglomeration levels after them */
   int p_jump;          /* with p_coarse = 1: 0 (default) lowers the degree by one per level
                           (p, p - 1, ..., 1); 1 goes from p straight to p = 1 */
+  int coarse_group;    /* lanes per row of the damped block-Jacobi sweep and of the residual +
+                          restriction on levels 1 .. L-1: 0 (default) chooses by the level's
+                          mean row length and size, or 8, 16, 32, 64 for every such level
+                          (else CDGMG_ERR_ARG).  Results do not depend on it beyond rounding
+                          order */
+  int row_threads;     /* workgroup size of the thread-per-row transfer kernels (prolongation
+                          and correction, coarse-level entry): 0 (default) 64 on levels below
+                          100 000 rows and 256 above, or 64 or 256 on every level */
 } cdgmg_options;
 
 typedef struct cdgmg_solve_info {
   int iterations;
-  double rel_residual;         /* true FP64 residual at exit */
+  double rel_residual;         /* ||b - A (x_hi + x_lo)|| / ||b|| at exit, accumulated in
+                                  double-double (compensated) arithmetic for the iterate the
+                                  solve keeps as an unevaluated sum x_hi + x_lo.  The FP64
+                                  vector returned is x_hi + x_lo rounded once; a residual
+                                  formed from it in plain FP64 carries the rounding noise
+                                  eps || |A| |u| || / ||b|| of one product (about 4e-10 for
+                                  2D p = 3 at h = 1/316, growing like h^-2), which can exceed
+                                  tol */
   double conv_factor;          /* (||r_k|| / ||r_0||)^(1/k) of the recursive residual */
   double solve_ms;             /* host wall time of the call, device-synchronised */
   double kernel_ms[CDGMG_NK];  /* summed HIP-event time per kernel class (profile != 0) */
@@ -169,54 +186,106 @@ int cdgmg_agglomerate(const cdgmg_mesh* mesh, int max_levels, int64_t coarse_dof
  * by (lower element, higher element)). */
 int cdgmg_switch(const cdgmg_mesh* mesh, int mode, uint64_t seed, int8_t* hosted_out);
 
-/* Build the solver: CDG operator of degree p (1..3) for the given mesh and
- * element coefficients kappa_dev (device float64 [n_elem], > 0), the
- * hierarchy's transfers and coarse operators, block inverses and the
- * coarsest factor.  Device work runs on `stream` (hipStream_t, NULL = default).
- * Errors: ARG (p, options, kappa), MESH (non-positive volume, non-manifold
- * facet), HIERARCHY (map out of range / empty aggregate), SINGULAR
- * (a diagonal block or the coarsest matrix is not positive definite),
- * DEVICE / NOMEM. */
-int cdgmg_setup(const cdgmg_mesh* mesh, int p, const double* kappa_dev,
-                const cdgmg_hierarchy* hier, const cdgmg_options* opts, void* stream,
-                cdgmg_handle** out);
+/* Device bytes cdgmg_setup needs for this mesh, degree, hierarchy and options,
+ * in *bytes.  Runs the host half of setup (topology, switch, kappa-free element
+ * blocks of the primal form eq. (primal_form), agglomerate bases and transfers
+ * of Sec. 3.3-3.4, Galerkin / flux coarsening plans of Sec. 3.5 and 4.1) and
+ * lays the device arrays out without touching the device; no GPU is needed.
+ * Errors as cdgmg_setup (ARG, MESH, HIERARCHY, NOMEM). */
+int cdgmg_workspace_size(const cdgmg_mesh* mesh, int p, const cdgmg_hierarchy* hier,
+                         const cdgmg_options* opts, size_t* bytes);
 
-/* Re-assemble A_0 = sum_e kappa_e A^(e) for new coefficients and rebuild the
- * coarse operators, block inverses and coarsest factor on the device. */
+/* Build the solver of eq. (poisson) in the CDG discretisation of Sec. 2
+ * (primal form eq. (primal_form), degree p = 1..3) on the given mesh with
+ * element coefficients kappa_dev (device float64 [n_elem], > 0 and finite),
+ * the hierarchy's transfers (Sec. 3.4), coarse operators (Sec. 3.5 / 4.1),
+ * inverted diagonal blocks for the block-Jacobi smoother and the inverse of
+ * the coarsest operator (Alg. 3).  workspace_dev: caller-owned device memory
+ * of workspace_bytes >= cdgmg_workspace_size(...) bytes, aligned to 256
+ * bytes; the handle keeps every device array in it and borrows it until
+ * cdgmg_destroy returns.  Device work runs on `stream` (hipStream_t, NULL =
+ * default); setup returns after it has finished.
+ * Errors: ARG (p, options, kappa, workspace null, misaligned or too small: the
+ * message names the size needed), MESH (non-positive volume, a facet shared
+ * by more than two elements), HIERARCHY (map out of range / empty aggregate),
+ * SINGULAR (a diagonal block or the coarsest matrix is not positive definite,
+ * or with flux coarsening or convection, singular), DEVICE, NOMEM (host). */
+int cdgmg_setup(const cdgmg_mesh* mesh, int p, const double* kappa_dev,
+                const cdgmg_hierarchy* hier, const cdgmg_options* opts, void* workspace_dev,
+                size_t workspace_bytes, void* stream, cdgmg_handle** out);
+
+/* Re-assemble A_0 = sum_e kappa_e A^(e) (eq. (primal_form) with the element
+ * coefficient kappa_e on element e's terms) for new coefficients kappa_dev
+ * (device float64 [n_elem], > 0 and finite) and rebuild the coarse operators
+ * (Sec. 3.5 / 4.1), inverted diagonal blocks and the coarsest inverse on the
+ * device, in the workspace.  Errors: ARG (kappa), SINGULAR, DEVICE.  Returns
+ * after the device work is enqueued (errors found on the device are
+ * reported after a synchronisation inside the call). */
 int cdgmg_update_kappa(cdgmg_handle* h, const double* kappa_dev);
 
-/* Solve A u = M_0 f (f nodal source values, M_0 the block mass matrix) from
- * u = 0.  Returns CDGMG_NOT_CONVERGED if max_iter is reached (info filled),
- * CDGMG_ERR_NAN if the residual is not finite.  info may be NULL. */
+/* Solve A u = M_0 f (eq. (primal_form); f nodal source values [n_elem][n_p],
+ * M_0 the block mass matrix) from u = 0 with the outer Krylov method
+ * preconditioned by one V-cycle of Alg. 3 per iteration, until the relative
+ * residual of info.rel_residual reaches tol.  u_dev [n_elem][n_p] receives
+ * x_hi + x_lo rounded once.  Returns CDGMG_NOT_CONVERGED (a warning: u and
+ * info hold the last iterate) if max_iter is reached, CDGMG_ERR_NAN if the
+ * residual is not finite.  info may be NULL.  Synchronises once per outer
+ * iteration and returns after the device work has finished. */
 int cdgmg_solve(cdgmg_handle* h, const double* f_dev, double* u_dev, cdgmg_solve_info* info);
 
-/* Solve A x = b for a given right-hand side vector b (a residual-space vector). */
+/* Solve A x = b for a given right-hand side vector b_dev [n_elem][n_p] (a
+ * residual-space vector, as M_0 f) into x_dev; otherwise as cdgmg_solve. */
 int cdgmg_solve_rhs(cdgmg_handle* h, const double* b_dev, double* x_dev, cdgmg_solve_info* info);
 
-/* Adjoint solve A^T lambda = g through the same hierarchy (A is symmetric, so
- * this is cdgmg_solve_rhs with g). */
+/* Adjoint solve A^T lambda = g through the same hierarchy: lambda_dev, g_dev
+ * [n_elem][n_p].  For the Poisson operator A is symmetric and this is
+ * cdgmg_solve_rhs with g; with convection (beta != 0) the levels are rebuilt
+ * from A_0^T and the V-cycle runs with the sweep counts exchanged, its
+ * transpose.  Returns as cdgmg_solve. */
 int cdgmg_solve_transpose(cdgmg_handle* h, const double* g_dev, double* lam_dev,
                           cdgmg_solve_info* info);
 
-/* gk_dev[e] = -lambda^T (dA/dkappa_e) u, the kappa-free operator hosted by e
- * applied over its stencil (element e and its neighbours across hosted facets). */
+/* gk_dev[e] = -lambda^T (dA/dkappa_e) u (float64 [n_elem]) for u_dev and
+ * lam_dev [n_elem][n_p]: dA/dkappa_e is the kappa-free part of eq.
+ * (primal_form) hosted by e (its volume term, the terms of the facets it
+ * hosts by the switch of Sec. 2.2, and its Dirichlet penalty), applied over
+ * its stencil, element e and its neighbours across hosted facets.  With
+ * lambda = A^{-T} dL/du this is dL/dkappa_e of a loss L(u).  Enqueued only. */
 int cdgmg_grad_kappa(cdgmg_handle* h, const double* u_dev, const double* lam_dev, double* gk_dev);
 
-/* y = M_0 x (block mass matrix of the input mesh). */
+/* y = M_0 x (block mass matrix of the degree-p nodal basis on the input mesh,
+ * the matrix of eq. (primal_form)'s right-hand side), x_dev and y_dev
+ * [n_elem][n_p], distinct.  Enqueued only. */
 int cdgmg_apply_mass(cdgmg_handle* h, const double* x_dev, double* y_dev);
 
-/* y = A_level x for testing.  precision: 0 = float64 vectors and operator,
- * 1 = float32 vectors and the FP32 operator copy.  Level-l vectors are
- * [n_l][n_p] in the hierarchy's numbering of level l (level 0: caller order);
- * coarse coefficients refer to the orthonormal modal basis of each aggregate. */
+/* y = A_level x for testing: A_0 of eq. (primal_form), A_l (l >= 1) the
+ * coarse operator of Sec. 3.5 or Sec. 4.1.  precision: 0 = float64 vectors,
+ * 1 = float32 vectors (products in float32 with the FP64 operator rounded;
+ * only with the FP32 V-cycle), else CDGMG_ERR_ARG.  Level-l vectors are
+ * [n_l][n_p] in the hierarchy's numbering of level l (level 0: caller
+ * order); coarse coefficients refer to the orthonormal modal basis of each
+ * aggregate (Sec. 3.3).  Enqueued only. */
 int cdgmg_apply_A(cdgmg_handle* h, int level, int precision, const void* x_dev, void* y_dev);
 
-/* One V-cycle z = B r (FP64 in/out; runs in the configured precision). */
+/* One V-cycle z = B r of Alg. 3 (damped block Jacobi, nu1 pre- and nu2
+ * post-sweeps, residual restriction and prolongation of Sec. 3.4, the
+ * coarsest level solved directly), r_dev and z_dev float64 [n_elem][n_p];
+ * runs in the configured precision.  Enqueued only. */
 int cdgmg_vcycle(cdgmg_handle* h, const double* r_dev, double* z_dev);
 
 /* Level statistics: n_levels, and per level (host arrays of n_levels entries,
  * each may be NULL) element count and stored n_p x n_p blocks of A_l. */
 int cdgmg_level_info(cdgmg_handle* h, int* n_levels, int64_t* n_elem, int64_t* nnzb);
+
+/* Launch configuration chosen at setup (test support).  Host arrays of n_levels
+ * entries, each may be NULL: lanes_sweep[l] and lanes_restrict[l], lanes per row
+ * of the sweep and of the residual + restriction on levels 1 .. L-1 (0 on
+ * level 0 and on the coarsest level, which use other kernels); row_threads[l],
+ * workgroup size of the thread-per-row transfer kernels of level l (the
+ * prolongation into level l and, for l >= 1, the entry of level l).
+ * wavefronts: wavefronts per 64-row slice of the level-0 kernels. */
+int cdgmg_launch_info(cdgmg_handle* h, int* n_levels, int32_t* lanes_sweep, int32_t* lanes_restrict,
+                      int32_t* row_threads, int* wavefronts);
 
 /* Copy operator A_level to the host as block CSR in the hierarchy's numbering:
  * row_ptr [n_l+1], cols [nnzb], blocks [nnzb][n_p][n_p] (row-major, FP64).
@@ -230,7 +299,7 @@ int cdgmg_node_coords(cdgmg_handle* h, double* xyz);
 /* Switch HIP-event timing of kernel classes on or off for later solves. */
 int cdgmg_set_profile(cdgmg_handle* h, int on);
 
-/* Device memory held by the handle, in bytes. */
+/* Bytes of the workspace the handle uses (cdgmg_workspace_size of its setup). */
 int cdgmg_device_bytes(cdgmg_handle* h, size_t* bytes);
 
 /* Test support, host only: build the setup data of cdgmg_setup on the host
@@ -241,7 +310,8 @@ int cdgmg_debug_host_operator(const cdgmg_mesh* mesh, int p, const double* kappa
                               const cdgmg_hierarchy* hier, const cdgmg_options* opts, int level,
                               int64_t* nnzb, int64_t* row_ptr, int32_t* cols, double* blocks);
 
-/* Free the handle and its device memory (synchronises its stream). */
+/* Free the handle's host state after its stream has finished; the workspace
+ * is the caller's to free afterwards. */
 int cdgmg_destroy(cdgmg_handle* h);
 
 #ifdef __cplusplus

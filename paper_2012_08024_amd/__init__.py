@@ -49,7 +49,7 @@ class _Opts(ctypes.Structure):
                 ("switch_seed", ctypes.c_uint64), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("profile", ctypes.c_int), ("kernel_variant", ctypes.c_int), ("restart", ctypes.c_int),
                 ("beta", ctypes.c_double), ("velocity", ctypes.c_double * 3), ("p_coarse", ctypes.c_int),
-                ("p_jump", ctypes.c_int)]
+                ("p_jump", ctypes.c_int), ("coarse_group", ctypes.c_int), ("row_threads", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -66,7 +66,8 @@ _SIGS = {
     "cdgmg_default_options": ([_vp], None),
     "cdgmg_agglomerate": ([_vp, _i, _i64, _i, _u64, _vp, _vp, _vp], _i),
     "cdgmg_switch": ([_vp, _i, _u64, _vp], _i),
-    "cdgmg_setup": ([_vp, _i, _vp, _vp, _vp, _vp, _vp], _i),
+    "cdgmg_workspace_size": ([_vp, _i, _vp, _vp, _vp], _i),
+    "cdgmg_setup": ([_vp, _i, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp], _i),
     "cdgmg_update_kappa": ([_vp, _vp], _i),
     "cdgmg_solve": ([_vp, _vp, _vp, _vp], _i),
     "cdgmg_solve_rhs": ([_vp, _vp, _vp, _vp], _i),
@@ -76,6 +77,7 @@ _SIGS = {
     "cdgmg_apply_A": ([_vp, _i, _i, _vp, _vp], _i),
     "cdgmg_vcycle": ([_vp, _vp, _vp], _i),
     "cdgmg_level_info": ([_vp, _vp, _vp, _vp], _i),
+    "cdgmg_launch_info": ([_vp, _vp, _vp, _vp, _vp, _vp], _i),
     "cdgmg_export_operator": ([_vp, _i, _vp, _vp, _vp, _vp], _i),
     "cdgmg_node_coords": ([_vp, _vp], _i),
     "cdgmg_device_bytes": ([_vp, _vp], _i),
@@ -164,6 +166,24 @@ def default_options(**kw):
     return o
 
 
+def _hierarchy(parents, sizes):
+    sizes = np.ascontiguousarray(sizes, dtype=np.int32)
+    par = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.int32) for x in parents])
+                               if len(parents) else np.zeros(0, dtype=np.int32))
+    return _Hier(len(sizes), _ptr(sizes).value, _ptr(par).value), (sizes, par)
+
+
+def workspace_size(mesh, p, parents, sizes, options=None, **kw):
+    """Device bytes cdgmg_setup needs (runs the host half of setup; no GPU)."""
+    hm = mesh if isinstance(mesh, HostMesh) else HostMesh.of(mesh)
+    hier, keep = _hierarchy(parents, sizes)
+    opts = options if options is not None else default_options(**kw)
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.cdgmg_workspace_size(ctypes.byref(hm.c), p, ctypes.byref(hier), ctypes.byref(opts),
+                                    ctypes.byref(nbytes)))
+    return nbytes.value
+
+
 def debug_host_operator(mesh, p, kappa, parents, sizes, level, **options):
     """A_level formed on the host from the library's setup data (CPU test support).
     Returns (row_ptr, cols, blocks) in hierarchy numbering."""
@@ -230,9 +250,13 @@ class Solver:
         hier = _Hier(len(sizes), _ptr(sizes).value, _ptr(par).value)
         kappa = self._dev(kappa)
         self.handle = ctypes.c_void_p()
+        # the device memory of the handle: one torch-owned workspace
+        nbytes = workspace_size(self.hm, p, parents, sizes, self.opts)
+        self.workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
         stream = torch.cuda.current_stream().cuda_stream
         _check(lib.cdgmg_setup(ctypes.byref(self.hm.c), p, kappa.data_ptr(), ctypes.byref(hier),
-                               ctypes.byref(self.opts), ctypes.c_void_p(stream), ctypes.byref(self.handle)))
+                               ctypes.byref(self.opts), self.workspace.data_ptr(), nbytes,
+                               ctypes.c_void_p(stream), ctypes.byref(self.handle)))
         self._kappa = kappa.detach().clone()
 
     def _dev(self, a, dtype=None):
@@ -303,6 +327,18 @@ class Solver:
         _check(lib.cdgmg_level_info(self.handle, ctypes.byref(nl), _ptr(ne), _ptr(nz)))
         return ne, nz
 
+    def launch_info(self):
+        """Launch configuration per level: dict of int arrays lanes_sweep,
+        lanes_restrict, row_threads, and the level-0 wavefronts per slice."""
+        nl = ctypes.c_int(0)
+        _check(lib.cdgmg_launch_info(self.handle, ctypes.byref(nl), None, None, None, None))
+        ls = np.zeros(nl.value, dtype=np.int32)
+        lr = np.zeros(nl.value, dtype=np.int32)
+        rt = np.zeros(nl.value, dtype=np.int32)
+        wf = ctypes.c_int(0)
+        _check(lib.cdgmg_launch_info(self.handle, ctypes.byref(nl), _ptr(ls), _ptr(lr), _ptr(rt), ctypes.byref(wf)))
+        return {"lanes_sweep": ls, "lanes_restrict": lr, "row_threads": rt, "wavefronts": wf.value}
+
     def apply_A(self, level, x, precision=0):
         torch = self.torch
         dt = torch.float64 if precision == 0 else torch.float32
@@ -352,6 +388,7 @@ class Solver:
         if self.handle:
             lib.cdgmg_destroy(self.handle)
             self.handle = ctypes.c_void_p()
+        self.workspace = None
 
     def __del__(self):
         try:

@@ -24,18 +24,30 @@ def _run(cmd):
     subprocess.run(cmd, check=True)
 
 
+def _run_all(cmds):
+    """Run the compile commands concurrently; fail if any fails."""
+    procs = []
+    for cmd in cmds:
+        print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
+    failed = [cmd for cmd, pr in procs if pr.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
+
+
 def build(verbose=True):
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    for src in HOST_SRC:
-        obj = os.path.join(BUILD, src + ".o")
-        _run(["g++", "-O3", "-fPIC", "-std=c++17", "-pthread", "-Wall", "-c",
-              os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+    objs, cmds = [], []
     for src in DEV_SRC:
         obj = os.path.join(BUILD, src + ".o")
-        _run([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj])
+        cmds.append([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    for src in HOST_SRC:
+        obj = os.path.join(BUILD, src + ".o")
+        cmds.append(["g++", "-O3", "-fPIC", "-std=c++17", "-pthread", "-Wall", "-c",
+                     os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    _run_all(cmds)
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lpthread"])
     os.replace(tmp, LIB)

@@ -950,6 +950,15 @@ int check_options(const cdgmg_options& o) {
     set_error("setup: the hp front end needs primal coarsening and beta = 0");
     return CDGMG_ERR_ARG;
   }
+  if (o.coarse_group != 0 && o.coarse_group != 8 && o.coarse_group != 16 && o.coarse_group != 32 &&
+      o.coarse_group != 64) {
+    set_error("setup: coarse_group must be 0, 8, 16, 32 or 64");
+    return CDGMG_ERR_ARG;
+  }
+  if (o.row_threads != 0 && o.row_threads != 64 && o.row_threads != 256) {
+    set_error("setup: row_threads must be 0, 64 or 256");
+    return CDGMG_ERR_ARG;
+  }
   return CDGMG_OK;
 }
 

@@ -64,8 +64,17 @@ int build_topology(const cdgmg_mesh& m, Topology& t) {
                           : J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
                                 J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
                                 J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-    if (!(det > 0.0)) {
-      set_error("mesh: element " + std::to_string(e) + " has non-positive volume");
+    // degenerate too: a volume below 1e-12 of the cube of the longest edge
+    // makes the element's mass matrix singular in FP64
+    double h2 = 0.0;
+    for (int k = 0; k < d; ++k) {
+      double l2 = 0.0;
+      for (int c = 0; c < d; ++c) l2 += J[c][k] * J[c][k];
+      h2 = std::max(h2, l2);
+    }
+    const double hd = d == 2 ? h2 : h2 * std::sqrt(h2);
+    if (!(det > 1e-12 * hd)) {
+      set_error("mesh: element " + std::to_string(e) + " has non-positive or near-zero volume");
       return CDGMG_ERR_MESH;
     }
   }

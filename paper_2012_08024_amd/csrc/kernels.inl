@@ -324,12 +324,26 @@ __global__ void k_dense_init(int64_t nd, int64_t ld, double* __restrict__ dense)
   dense[idx] = (i == j && i >= nd) ? 1.0 : 0.0;
 }
 
+// diag0 <- the diagonal of the matrix before elimination
+__global__ void k_dense_diag(int64_t ld, const double* __restrict__ dense, double* __restrict__ diag0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ld) diag0[i] = dense[i * ld + i];
+}
+
+// Definite mode: a pivot is the diagonal entry of a Schur complement of an
+// SPD matrix, at least lambda_min; one at or below GJ_SING times the original
+// diagonal entry marks a matrix that is singular in FP64 (condition above
+// about 1e11), such as the operator with only Neumann boundaries, whose kernel
+// holds the constants.
+constexpr double GJ_SING = 1e-11;
+
 // P = A_KK^{-1} by unblocked Gauss-Jordan (one workgroup of 256, the block in
 // registers);
-// writes P into A_KK and into Pout; err = 1 on a non-positive (definite) or
-// zero pivot
+// writes P into A_KK and into Pout; err = 1 on a pivot at or below
+// GJ_SING diag0 (definite) or a zero pivot
 __global__ __launch_bounds__(256) void k_gj_pivot(int64_t ld, int K, double* __restrict__ dense,
-                                                  double* __restrict__ Pout, int* __restrict__ err, int definite) {
+                                                  double* __restrict__ Pout, const double* __restrict__ diag0,
+                                                  int* __restrict__ err, int definite) {
   // thread (i0, j) keeps rows i0 + 4 m, m < 16, of column j in registers; per
   // step only the pivot row and column go through LDS, double-buffered by the
   // step's parity so that one barrier per step suffices
@@ -350,7 +364,7 @@ __global__ __launch_bounds__(256) void k_gj_pivot(int64_t ld, int K, double* __r
       for (int m = 0; m < RM; ++m) colk[b][i0 + 4 * m] = v[m];
     __syncthreads();
     const double p = rowk[b][k];
-    if (tid == 0 && (definite ? !(p > 0.0) : !(p != 0.0 && p == p))) bad = true;
+    if (tid == 0 && (definite ? !(p > GJ_SING * diag0[(int64_t)K * GJB + k]) : !(p != 0.0 && p == p))) bad = true;
     const double ip = 1.0 / p;
     const double rj = rowk[b][j];
 #pragma unroll

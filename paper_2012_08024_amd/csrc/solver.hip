@@ -144,6 +144,18 @@ struct ProfEv {
   hipEvent_t a, b;
 };
 
+// Device memory of a handle: every array is carved, in setup order, out of one
+// caller-owned workspace (offsets rounded up to WS_ALIGN bytes).  A counting
+// workspace only sums the sizes (cdgmg_workspace_size, or a workspace found too
+// small): its pointers are stand-ins that nothing dereferences, and no copy or
+// fill is issued through them.
+constexpr size_t WS_ALIGN = 256;
+struct Workspace {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  bool counting = true;
+};
+
 }  // namespace
 
 struct cdgmg_handle {
@@ -154,8 +166,9 @@ struct cdgmg_handle {
   int H0 = 1;  // wavefronts per slice of the level-0 kernels
   int64_t N0 = 0;
   std::vector<DLevel> lv;
-  std::vector<void*> allocs;
-  size_t bytes = 0;
+  Workspace own_ws;
+  Workspace* ws = &own_ws;  // a lower hp level carves from its owner's workspace
+  bool pinned = true;       // host readback buffers in pinned (hipHostMalloc) memory
   // level 0
   double *UA = nullptr, *UH = nullptr, *M = nullptr, *kappa = nullptr;
   double* UC = nullptr;    // upwind convection blocks (beta != 0), operator layout
@@ -175,6 +188,7 @@ struct cdgmg_handle {
   // coarsest
   int64_t nd = 0, ld = 0;
   double *dense = nullptr, *gjP = nullptr;  // coarsest operator -> its inverse (ld x ld, FP64); pivot block
+  double* gjD = nullptr;                     // its diagonal before elimination
   void* AinvP = nullptr;  // A_L^{-1} in the multigrid precision, leading dimension ld
   // outer vectors (internal order, FP64)
   double *b = nullptr, *x = nullptr, *xl = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *t1 = nullptr,
@@ -198,26 +212,54 @@ struct cdgmg_handle {
 
 namespace {
 
+// the next count elements of the workspace; once the workspace is exhausted
+// it turns into a counting one, so that setup can report the size it needs
 template <typename T>
 int dalloc(cdgmg_handle* h, T** ptr, size_t count) {
-  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) {
-    set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
-    return CDGMG_ERR_NOMEM;
-  }
-  h->allocs.push_back(p);
-  h->bytes += bytes;
-  *ptr = (T*)p;
+  Workspace& w = *h->ws;
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  const size_t off = (w.used + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN;
+  w.used = off + bytes;
+  if (w.used > w.cap) w.counting = true;
+  *ptr = (T*)((w.counting ? (char*)WS_ALIGN : w.base) + off);
   return CDGMG_OK;
 }
 
 template <typename T>
 int upload(cdgmg_handle* h, T** ptr, const std::vector<T>& v) {
   RETURN_IF(dalloc(h, ptr, v.size()));
-  if (!v.empty()) HIPCHK(hipMemcpyAsync(*ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
+  if (!v.empty() && !h->ws->counting)
+    HIPCHK(hipMemcpyAsync(*ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
   return CDGMG_OK;
+}
+
+int dzero(cdgmg_handle* h, void* ptr, size_t bytes) {
+  if (!h->ws->counting) HIPCHK(hipMemsetAsync(ptr, 0, bytes, h->stream));
+  return CDGMG_OK;
+}
+
+// host buffer the device results are copied back to (pinned unless the handle
+// must not allocate pinned memory); released by host_free
+template <typename T>
+int host_alloc(cdgmg_handle* h, T** ptr, size_t count) {
+  *ptr = nullptr;
+  if (h->ws->counting) return CDGMG_OK;
+  if (h->pinned) {
+    HIPCHK(hipHostMalloc((void**)ptr, std::max<size_t>(count, 1) * sizeof(T)));
+  } else {
+    *ptr = new (std::nothrow) T[std::max<size_t>(count, 1)]();
+    if (!*ptr) return CDGMG_ERR_NOMEM;
+  }
+  return CDGMG_OK;
+}
+
+template <typename T>
+void host_free(const cdgmg_handle* h, T* ptr) {
+  if (!ptr) return;
+  if (h->pinned)
+    (void)hipHostFree(ptr);
+  else
+    delete[] ptr;
 }
 
 inline unsigned grid_for(int64_t n, int tpb = TPB) { return (unsigned)((n + tpb - 1) / tpb); }
@@ -392,7 +434,7 @@ int upload_problem(cdgmg_handle* h) {
     RETURN_IF(upload(h, &D.sblk, H.slice_blk));
     RETURN_IF(upload(h, &D.perm, H.perm));
     RETURN_IF(dalloc(h, &D.A64, (size_t)D.slots * np2));
-    HIPCHK(hipMemsetAsync(D.A64, 0, (size_t)D.slots * np2 * sizeof(double), h->stream));
+    RETURN_IF(dzero(h, D.A64, (size_t)D.slots * np2 * sizeof(double)));
     const size_t rowblk = (size_t)D.ns * SLICE * np2;
     if (l == 0 && h->inner) {  // hp front end: level 0 restricts to the lower degree
       const size_t rect = (size_t)D.ns * SLICE * np * h->np1;
@@ -432,7 +474,7 @@ int upload_problem(cdgmg_handle* h) {
       const size_t na = (size_t)(D.slots - SLICE * D.ns) * np2;
       void* tmp;
       RETURN_IF(dalloc(h, (char**)&tmp, na * (fp32 ? sizeof(float) : sizeof(double))));
-      HIPCHK(hipMemsetAsync(tmp, 0, na * (fp32 ? sizeof(float) : sizeof(double)), h->stream));
+      RETURN_IF(dzero(h, tmp, na * (fp32 ? sizeof(float) : sizeof(double))));
       D.At = tmp;
     }
     if (l >= 1 && l < P.L) {
@@ -450,7 +492,9 @@ int upload_problem(cdgmg_handle* h) {
       // 53 columns: the sweep is fastest with 32 lanes on large levels and 16
       // on smaller ones, the restriction, which also reads D^T L_e, with 16)
       const double kmean = (double)(H.nnzb - H.n) * np / std::max<int64_t>(H.n, 1);
-      if (kmean <= 96) {
+      if (h->o.coarse_group) {
+        D.grp_s = D.grp_r = h->o.coarse_group;
+      } else if (kmean <= 96) {
         D.grp_s = H.n >= 16384 ? 32 : 16;
         D.grp_r = 16;
       } else {
@@ -480,7 +524,7 @@ int upload_problem(cdgmg_handle* h) {
     RETURN_IF(dalloc(h, &tmp, vb / sizeof(double)));
     D.t = tmp;
     // padding entries past n n_p stay zero (the dense coarsest product reads them)
-    for (void* v : {D.b, D.x, D.xb, D.t}) HIPCHK(hipMemsetAsync(v, 0, vb, h->stream));
+    for (void* v : {D.b, D.x, D.xb, D.t}) RETURN_IF(dzero(h, v, vb));
   }
   // level-0 kappa-free blocks (a level 0 set by its owner needs none of them)
   if (!h->given_A0) {
@@ -506,6 +550,7 @@ int upload_problem(cdgmg_handle* h) {
     h->ld = (h->nd + GJB - 1) / GJB * GJB;
     RETURN_IF(dalloc(h, &h->dense, (size_t)h->ld * h->ld));
     RETURN_IF(dalloc(h, &h->gjP, (size_t)GJB * GJB));
+    RETURN_IF(dalloc(h, &h->gjD, (size_t)h->ld));
     if (fp32) {
       float* tmp;
       RETURN_IF(dalloc(h, &tmp, (size_t)h->nd * h->ld));
@@ -520,7 +565,7 @@ int upload_problem(cdgmg_handle* h) {
   for (double** v : {&h->b, &h->x, &h->xl, &h->r, &h->p, &h->q, &h->t1, &h->t2}) {
     if (h->given_A0 && v != &h->t1 && v != &h->t2) continue;
     RETURN_IF(dalloc(h, v, m));
-    HIPCHK(hipMemsetAsync(*v, 0, m * sizeof(double), h->stream));
+    RETURN_IF(dzero(h, *v, m * sizeof(double)));
   }
   if (h->o.outer == CDGMG_OUTER_GMRES) {
     const int R = h->o.restart;
@@ -530,19 +575,18 @@ int upload_problem(cdgmg_handle* h) {
     RETURN_IF(dalloc(h, &h->gmH, 3 * (size_t)(R + 1)));
     RETURN_IF(dalloc(h, &h->gmPart, (size_t)(R + 1) * 1024));
     RETURN_IF(dalloc(h, &h->gmY, (size_t)R));
-    HIPCHK(hipMemsetAsync(h->gmV, 0, (size_t)(R + 1) * m * sizeof(double), h->stream));
-    HIPCHK(hipMemsetAsync(h->gmZ, 0, (size_t)R * m * sizeof(double), h->stream));
-    HIPCHK(hipHostMalloc((void**)&h->hgmH, 3 * (size_t)(R + 1) * sizeof(double)));
-    HIPCHK(hipHostMalloc((void**)&h->hgmY, (size_t)R * sizeof(double)));
+    RETURN_IF(dzero(h, h->gmV, (size_t)(R + 1) * m * sizeof(double)));
+    RETURN_IF(dzero(h, h->gmZ, (size_t)R * m * sizeof(double)));
+    RETURN_IF(host_alloc(h, &h->hgmH, 3 * (size_t)(R + 1)));
+    RETURN_IF(host_alloc(h, &h->hgmY, (size_t)R));
   }
   RETURN_IF(dalloc(h, &h->scal, SC_N));
   h->nparts = (int)std::max<int64_t>(1024, (P.N0 + SLICE - 1) / SLICE + 1);
   RETURN_IF(dalloc(h, &h->part, 2 * (size_t)h->nparts));
   RETURN_IF(dalloc(h, &h->err, 1));
-  HIPCHK(hipMemsetAsync(h->err, 0, sizeof(int), h->stream));
-  HIPCHK(hipHostMalloc((void**)&h->hscal, SC_N * sizeof(double)));
-  HIPCHK(hipHostMalloc((void**)&h->herr, sizeof(int)));
-  *h->herr = 0;
+  RETURN_IF(dzero(h, h->err, sizeof(int)));
+  RETURN_IF(host_alloc(h, &h->hscal, SC_N));
+  RETURN_IF(host_alloc(h, &h->herr, 1));
   if (P.flux) RETURN_IF(upload_flux(h));
   // release large host copies that the device now holds
   std::vector<double>().swap(P.UA);
@@ -691,9 +735,11 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed) {
   launch(h, -1, k_dense_init, dim3(grid_for(ld * ld)), dim3(TPB), nd, ld, h->dense);
   NP_DISPATCH(np, launch(h, -1, k_dense_scatter<NP>, dim3(grid_for(cl.n)), dim3(TPB), cl.n, ld,
                          (const int32_t*)cl.cols, (const int64_t*)cl.sblk, (const double*)cl.A64, h->dense));
+  launch(h, -1, k_dense_diag, dim3(grid_for(ld)), dim3(TPB), ld, (const double*)h->dense, h->gjD);
   const int nbk = (int)(ld / GJB);
   for (int K = 0; K < nbk; ++K) {
-    launch(h, -1, k_gj_pivot, dim3(1), dim3(256), ld, K, h->dense, h->gjP, h->err, definite);
+    launch(h, -1, k_gj_pivot, dim3(1), dim3(256), ld, K, h->dense, h->gjP, (const double*)h->gjD, h->err,
+           definite);
     if (nbk > 1) {
       launch(h, -1, k_gj_row, dim3(nbk), dim3(256), ld, K, h->dense, (const double*)h->gjP);
       launch(h, -1, k_gj_update, dim3(nbk, nbk), dim3(256), ld, K, h->dense);
@@ -760,7 +806,10 @@ void dot_t(cdgmg_handle* h, const T* z, const double* dv, int* nparts) {
 
 // thread-per-row kernels: one-wavefront workgroups on small levels spread the
 // few wavefronts over the compute units
-inline int row_tpb(const cdgmg_handle* h, int l) { return h->lv[l].n < 100000 ? WAVE : TPB; }
+inline int row_tpb(const cdgmg_handle* h, int l) {
+  if (h->o.row_threads) return h->o.row_threads;
+  return h->lv[l].n < 100000 ? WAVE : TPB;
+}
 
 void* vcycle(cdgmg_handle* h, const double* r64, const double* dv, int* nparts);
 
@@ -1291,6 +1340,8 @@ int setup_inner(cdgmg_handle* h, const cdgmg_mesh& mesh, const cdgmg_hierarchy& 
   in->o.kernel_variant = 0;
   in->o.outer = CDGMG_OUTER_FCG;  // only its V-cycle runs: no Krylov work vectors
   in->stream = h->stream;
+  in->ws = h->ws;
+  in->pinned = h->pinned;
   in->given_A0 = true;
   int rc;
   try {
@@ -1344,6 +1395,71 @@ int check_handle(cdgmg_handle* h) {
   return CDGMG_OK;
 }
 
+// Host half of setup and the layout of the device arrays in the workspace:
+// the problem (topology, switch, kappa-free element blocks, bases, transfers,
+// Galerkin and flux plans), then every device array carved from ws, host data
+// copied into it.  ws null: a counting workspace (no device call is made).
+// On error *out is null and the partial handle is freed.
+int prepare(const cdgmg_mesh* mesh, int p, const cdgmg_hierarchy* hier, const cdgmg_options* opts,
+            const Workspace* ws, hipStream_t stream, cdgmg_handle** out) {
+  *out = nullptr;
+  if (!mesh || !hier) {
+    set_error("setup: invalid argument");
+    return CDGMG_ERR_ARG;
+  }
+  cdgmg_options o;
+  if (opts)
+    o = *opts;
+  else
+    cdgmg_default_options(&o);
+  RETURN_IF(check_options(o));
+  cdgmg_handle* h = new (std::nothrow) cdgmg_handle();
+  if (!h) return CDGMG_ERR_NOMEM;
+  h->o = o;
+  h->stream = stream;
+  if (ws) h->own_ws = *ws;
+  int rc;
+  try {
+    rc = build_problem(*mesh, p, *hier, o, h->P);
+  } catch (const std::exception& e) {
+    set_error(std::string("setup: ") + e.what());
+    rc = CDGMG_ERR_NOMEM;
+  }
+  if (!rc) {
+    h->H0 = pick_h0(h->P.np, o.kernel_variant);
+    if (!h->H0) {
+      set_error("setup: kernel_variant must be 0 or one of 1, 2, 4, 5 dividing n_p = " + std::to_string(h->P.np));
+      rc = CDGMG_ERR_ARG;
+    }
+  }
+  if (!rc && o.p_coarse == 1 && p >= 2) rc = setup_inner(h, *mesh, *hier);
+  if (!rc) rc = upload_problem(h);
+  if (!rc && h->inner) rc = upload_embedding(h);
+  if (!rc && ws && h->ws->counting) {
+    set_error("setup: the workspace holds " + std::to_string(ws->cap) + " bytes; this problem needs " +
+              std::to_string(h->ws->used) + " (cdgmg_workspace_size)");
+    rc = CDGMG_ERR_ARG;
+  }
+  if (rc) {
+    std::string msg = cdg::last_error_cstr();
+    cdgmg_destroy(h);
+    set_error(msg);
+    return rc;
+  }
+  *out = h;
+  return CDGMG_OK;
+}
+
+// device half of setup: operators for kappa, block inverses, coarsest inverse
+int finish_setup(cdgmg_handle* h, const double* kappa_dev) {
+  RETURN_IF(build_operators(h, kappa_dev, false));
+  if (hipStreamSynchronize(h->stream) != hipSuccess) {
+    set_error("setup: device error");
+    return CDGMG_ERR_DEVICE;
+  }
+  return CDGMG_OK;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -1374,6 +1490,8 @@ void cdgmg_default_options(cdgmg_options* o) {
   o->velocity[0] = 1.0;
   o->p_coarse = 0;
   o->p_jump = 0;
+  o->coarse_group = 0;
+  o->row_threads = 0;
 }
 
 int cdgmg_agglomerate(const cdgmg_mesh* mesh, int max_levels, int64_t coarse_dofs_max, int p, uint64_t seed,
@@ -1417,45 +1535,40 @@ int cdgmg_switch(const cdgmg_mesh* mesh, int mode, uint64_t seed, int8_t* hosted
   return CDGMG_OK;
 }
 
-int cdgmg_setup(const cdgmg_mesh* mesh, int p, const double* kappa_dev, const cdgmg_hierarchy* hier,
-                const cdgmg_options* opts, void* stream, cdgmg_handle** out) {
+int cdgmg_workspace_size(const cdgmg_mesh* mesh, int p, const cdgmg_hierarchy* hier, const cdgmg_options* opts,
+                         size_t* bytes) {
   set_error("");
-  if (!mesh || !hier || !out || !kappa_dev) {
+  if (!bytes) {
+    set_error("workspace_size: invalid argument");
+    return CDGMG_ERR_ARG;
+  }
+  *bytes = 0;
+  cdgmg_handle* h = nullptr;
+  RETURN_IF(prepare(mesh, p, hier, opts, nullptr, nullptr, &h));
+  *bytes = h->ws->used;
+  cdgmg_destroy(h);
+  return CDGMG_OK;
+}
+
+int cdgmg_setup(const cdgmg_mesh* mesh, int p, const double* kappa_dev, const cdgmg_hierarchy* hier,
+                const cdgmg_options* opts, void* workspace_dev, size_t workspace_bytes, void* stream,
+                cdgmg_handle** out) {
+  set_error("");
+  if (!kappa_dev || !out || !workspace_dev) {
     set_error("setup: invalid argument");
     return CDGMG_ERR_ARG;
   }
-  cdgmg_options o;
-  if (opts)
-    o = *opts;
-  else
-    cdgmg_default_options(&o);
-  RETURN_IF(check_options(o));
-  cdgmg_handle* h = new (std::nothrow) cdgmg_handle();
-  if (!h) return CDGMG_ERR_NOMEM;
-  h->o = o;
-  h->stream = (hipStream_t)stream;
-  int rc;
-  try {
-    rc = build_problem(*mesh, p, *hier, o, h->P);
-  } catch (const std::exception& e) {
-    set_error(std::string("setup: ") + e.what());
-    rc = CDGMG_ERR_NOMEM;
+  if ((uintptr_t)workspace_dev % WS_ALIGN) {
+    set_error("setup: the workspace must be aligned to " + std::to_string(WS_ALIGN) + " bytes");
+    return CDGMG_ERR_ARG;
   }
-  if (!rc) {
-    h->H0 = pick_h0(h->P.np, o.kernel_variant);
-    if (!h->H0) {
-      set_error("setup: kernel_variant must be 0 or one of 1, 2, 4, 5 dividing n_p = " + std::to_string(h->P.np));
-      rc = CDGMG_ERR_ARG;
-    }
-  }
-  if (!rc && o.p_coarse == 1 && p >= 2) rc = setup_inner(h, *mesh, *hier);
-  if (!rc) rc = upload_problem(h);
-  if (!rc && h->inner) rc = upload_embedding(h);
-  if (!rc) rc = build_operators(h, kappa_dev, false);
-  if (!rc && hipStreamSynchronize(h->stream) != hipSuccess) {
-    set_error("setup: device error");
-    rc = CDGMG_ERR_DEVICE;
-  }
+  Workspace ws;
+  ws.base = (char*)workspace_dev;
+  ws.cap = workspace_bytes;
+  ws.counting = false;
+  cdgmg_handle* h = nullptr;
+  RETURN_IF(prepare(mesh, p, hier, opts, &ws, (hipStream_t)stream, &h));
+  int rc = finish_setup(h, kappa_dev);
   if (rc) {
     std::string msg = cdg::last_error_cstr();
     cdgmg_destroy(h);
@@ -1618,6 +1731,31 @@ int cdgmg_level_info(cdgmg_handle* h, int* n_levels, int64_t* n_elem, int64_t* n
   return CDGMG_OK;
 }
 
+int cdgmg_launch_info(cdgmg_handle* h, int* n_levels, int32_t* lanes_sweep, int32_t* lanes_restrict,
+                      int32_t* row_threads, int* wavefronts) {
+  RETURN_IF(check_handle(h));
+  if (wavefronts) *wavefronts = h->H0;
+  if (h->inner) {  // level 0 at degree p (level-0 kernels only), then the lower-degree levels
+    int ni = 0;
+    RETURN_IF(cdgmg_launch_info(h->inner, &ni, lanes_sweep ? lanes_sweep + 1 : nullptr,
+                                lanes_restrict ? lanes_restrict + 1 : nullptr, row_threads ? row_threads + 1 : nullptr,
+                                nullptr));
+    if (n_levels) *n_levels = ni + 1;
+    if (lanes_sweep) lanes_sweep[0] = 0;
+    if (lanes_restrict) lanes_restrict[0] = 0;
+    if (row_threads) row_threads[0] = TPB;  // k_prolong_rect
+    return CDGMG_OK;
+  }
+  if (n_levels) *n_levels = h->L + 1;
+  for (int l = 0; l <= h->L; ++l) {
+    const bool grp = l >= 1 && l < h->L;
+    if (lanes_sweep) lanes_sweep[l] = grp ? h->lv[l].grp_s : 0;
+    if (lanes_restrict) lanes_restrict[l] = grp ? h->lv[l].grp_r : 0;
+    if (row_threads) row_threads[l] = l < h->L ? row_tpb(h, l) : WAVE;
+  }
+  return CDGMG_OK;
+}
+
 int cdgmg_export_operator(cdgmg_handle* h, int level, int64_t* nnzb, int64_t* row_ptr, int32_t* cols,
                           double* blocks) {
   RETURN_IF(check_handle(h));
@@ -1680,22 +1818,21 @@ int cdgmg_set_profile(cdgmg_handle* h, int on) {
 
 int cdgmg_device_bytes(cdgmg_handle* h, size_t* bytes) {
   RETURN_IF(check_handle(h));
-  *bytes = 0;
-  for (const cdgmg_handle* g = h; g; g = g->inner) *bytes += g->bytes;
+  *bytes = h->ws->used;
   return CDGMG_OK;
 }
 
 int cdgmg_destroy(cdgmg_handle* h) {
   if (!h) return CDGMG_OK;
   if (h->inner) cdgmg_destroy(h->inner);
-  if (h->stream || !h->allocs.empty()) (void)hipStreamSynchronize(h->stream);
-  for (void* p : h->allocs) (void)hipFree(p);
+  // the device work of this handle ends before the caller may reuse the workspace
+  if (h->ws->base) (void)hipStreamSynchronize(h->stream);
   for (auto e : h->pool) (void)hipEventDestroy(e);
   if (h->ev_rr) (void)hipEventDestroy(h->ev_rr);
-  if (h->hgmH) (void)hipHostFree(h->hgmH);
-  if (h->hgmY) (void)hipHostFree(h->hgmY);
-  if (h->hscal) (void)hipHostFree(h->hscal);
-  if (h->herr) (void)hipHostFree(h->herr);
+  host_free(h, h->hgmH);
+  host_free(h, h->hgmY);
+  host_free(h, h->hscal);
+  host_free(h, h->herr);
   delete h;
   return CDGMG_OK;
 }

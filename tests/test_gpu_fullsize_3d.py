@@ -16,6 +16,7 @@ if not torch.cuda.is_available():  # pragma: no cover
 import paper_2012_08024_amd as cm  # noqa: E402
 from oracle.cdg import CDG  # noqa: E402
 from oracle.mesh import Topology  # noqa: E402
+from kernel_coverage import uncovered  # noqa: E402
 from workloads import CONFIGS, config_mesh  # noqa: E402
 
 
@@ -66,3 +67,13 @@ def test_vcycle_is_symmetric_and_positive_at_full_size(c5):
     Bx, By = solver.vcycle(x).cpu().numpy(), solver.vcycle(y).cpu().numpy()
     assert abs(x @ By - y @ Bx) <= 1e-5 * np.linalg.norm(x) * np.linalg.norm(By)
     assert x @ Bx > 0 and y @ By > 0
+
+
+def test_launch_configuration_is_parity_covered(c5):
+    # every coarse-level lane group, transfer workgroup size and level-0
+    # wavefront split this workload dispatches is compared with the oracle's
+    # V-cycle in test_gpu_parity.py (FP32 V-cycle, this block size)
+    cfg, mesh, kappa, solver = c5
+    info = solver.launch_info()
+    print("launch configuration", {k: (list(v) if hasattr(v, "__len__") else v) for k, v in info.items()}, flush=True)
+    assert not uncovered(info, 1, solver.np)

@@ -280,3 +280,59 @@ if given is not None:
         assert len(parents) == len(ref)
         for a, b in zip(parents, ref):
             assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
+def test_workspace_size_on_the_host():
+    # cdgmg_workspace_size runs the host half of setup without a GPU; the
+    # layout holds at least the FP64 level-0 operator, the eight outer FP64
+    # vectors, and the 2m + 1 GMRES vectors when GMRES(m) is chosen
+    m = mesh2d_jittered_delaunay(12, 1)
+    parents, sizes = cm.agglomerate(m, 4, 12, p=3)
+    npb = 10
+    base = cm.workspace_size(m, 3, parents, sizes)
+    assert base == cm.workspace_size(m, 3, parents, sizes)  # deterministic
+    n_slices = -(-m.n_elem // 64)
+    assert base >= n_slices * 64 * 4 * npb * npb * 8 + 8 * m.n_elem * npb * 8
+    gm = cm.workspace_size(m, 3, parents, sizes, outer=cm.OUTER_GMRES, restart=9)
+    assert gm - base >= 19 * n_slices * 64 * npb * 8
+    f64 = cm.workspace_size(m, 3, parents, sizes, mg_precision=cm.MG_FP64)
+    assert f64 != base
+    big = mesh2d_jittered_delaunay(24, 1)
+    pb, sb = cm.agglomerate(big, 4, 12, p=3)
+    assert cm.workspace_size(big, 3, pb, sb) > 3 * base
+
+
+def _collapsed(m):
+    # element 0's third vertex moved onto the line through its first two
+    coords = m.coords.copy()
+    a, b, c = m.e2v[0]
+    coords[c] = 0.5 * (coords[a] + coords[b])
+    return cm.HostMesh(coords, m.e2v, m.face_bc)
+
+
+def _nonmanifold(m):
+    # a third triangle on an interior edge of element 0 (the edge's two
+    # triangles plus this one share it)
+    a, b, c = m.e2v[0]
+    mid = 0.5 * (m.coords[a] + m.coords[b])
+    coords = np.vstack([m.coords, mid + np.array([1e-3, 1e-3])])
+    extra = np.array([[a, b, coords.shape[0] - 1]], dtype=np.int32)
+    e2v = np.vstack([m.e2v, extra])
+    # orient the extra triangle positively
+    p0, p1, p2 = coords[extra[0]]
+    if (p1[0] - p0[0]) * (p2[1] - p0[1]) - (p1[1] - p0[1]) * (p2[0] - p0[0]) < 0:
+        e2v[-1] = [b, a, coords.shape[0] - 1]
+    face_bc = np.vstack([m.face_bc, np.zeros((1, 3), dtype=np.int8)])
+    return cm.HostMesh(coords, e2v, face_bc)
+
+
+@pytest.mark.parametrize("make", [_collapsed, _nonmanifold])
+def test_invalid_meshes_are_refused(make):
+    m = mesh2d_jittered_delaunay(6, 1)
+    # make sure the edge used by _nonmanifold is interior (shared by two elements)
+    hm = make(m)
+    for call in (lambda: cm.switch(hm), lambda: cm.agglomerate(hm, 3, 0, p=1),
+                 lambda: cm.workspace_size(hm, 1, [], [hm.n_elem])):
+        with pytest.raises(cm.CdgmgError) as ei:
+            call()
+        assert ei.value.code == -2, str(ei.value)
