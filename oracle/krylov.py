@@ -156,3 +156,26 @@ def gmres(A, b, prec, restart=50, tol=1e-10, maxiter=500, history=None):
             y[i] = (g[i] - float(np.dot(H[i, i + 1:k], y[i + 1:k]))) / H[i, i]
         x = x + Z[:k].T @ y
     return x, it, _norm(b - A @ x) / nb
+
+
+def refine(A, b, solve, rounds=2):
+    """Iterative refinement (Wilkinson): x_0 = solve(b); then, `rounds` times,
+    r = b - A x_k with the product and the difference in extended precision
+    (numpy longdouble, a 64-bit significand on x86), d = solve(r rounded to
+    float64), x_{k+1} = x_k + d.  The FP64 rounding of a plain residual, about
+    eps || |A| |x| ||, limits an FP64 Krylov solve; here only the inner solves
+    run in FP64, each on a residual that is smaller by their own reduction
+    factor, so the error falls by that factor per round until the rounding of
+    x itself.  Returns (x, relative extended-precision residual per round)."""
+    Al = A.astype(np.longdouble)
+    bl = np.asarray(b, dtype=np.longdouble)
+    nb = float(np.sqrt(np.dot(bl, bl)))
+    x = solve(b)
+    res = []
+    for _ in range(rounds):
+        r = bl - Al @ np.asarray(x, dtype=np.longdouble)
+        res.append(float(np.sqrt(np.dot(r, r))) / nb)
+        x = x + solve(np.asarray(r, dtype=np.float64))
+    r = bl - Al @ np.asarray(x, dtype=np.longdouble)
+    res.append(float(np.sqrt(np.dot(r, r))) / nb)
+    return x, res

@@ -270,7 +270,7 @@ class Solver:
         torch = self.torch
         return torch.empty((self.n_elem if n is None else n) * self.np, dtype=dtype or torch.float64, device="cuda")
 
-    def _run_solve(self, fn, rhs, history):
+    def _run_solve(self, fn, rhs, history, strict=False):
         info = _Info()
         hist = None
         if history:
@@ -280,20 +280,22 @@ class Solver:
         rhs = self._dev(rhs).reshape(-1)
         out = self._vec()
         rc = fn(self.handle, rhs.data_ptr(), out.data_ptr(), ctypes.byref(info))
-        _check(rc, allow_warning=True)
+        _check(rc, allow_warning=not strict)
         return out, SolveInfo(info, hist), rc
 
-    def solve(self, f, history=False):
-        """u with A u = M_0 f (f nodal source, [n_elem * n_p])."""
-        u, info, rc = self._run_solve(lib.cdgmg_solve, f, history)
+    def solve(self, f, history=False, strict=False):
+        """u with A u = M_0 f (f nodal source, [n_elem * n_p]).  A solve that
+        stops at max_iter returns its last iterate (CDGMG_NOT_CONVERGED is a
+        warning) unless strict, which raises CdgmgError instead."""
+        u, info, rc = self._run_solve(lib.cdgmg_solve, f, history, strict)
         return u, info
 
-    def solve_rhs(self, b, history=False):
-        x, info, rc = self._run_solve(lib.cdgmg_solve_rhs, b, history)
+    def solve_rhs(self, b, history=False, strict=False):
+        x, info, rc = self._run_solve(lib.cdgmg_solve_rhs, b, history, strict)
         return x, info
 
-    def solve_transpose(self, g, history=False):
-        x, info, rc = self._run_solve(lib.cdgmg_solve_transpose, g, history)
+    def solve_transpose(self, g, history=False, strict=False):
+        x, info, rc = self._run_solve(lib.cdgmg_solve_transpose, g, history, strict)
         return x, info
 
     def grad_kappa(self, u, lam):

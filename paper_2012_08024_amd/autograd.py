@@ -4,7 +4,8 @@ Forward u = A(kappa)^{-1} M_0 f.  Backward, with the incoming gradient
 g = dL/du: lambda = A^{-T} g through the same hierarchy (A is symmetric),
 dL/dkappa_e = -lambda^T (dA/dkappa_e) u from the element-local kernel, and
 dL/df = M_0 lambda.  All products run in the library; torch only carries the
-tensors.
+tensors.  Both solves are strict: one that stops at max_iter raises
+CdgmgError instead of returning an unconverged u, lambda or gradient.
 """
 import torch
 
@@ -13,7 +14,7 @@ class _Solve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, kappa, f, solver):
         solver.ensure_kappa(kappa)
-        u, info = solver.solve(f.detach())
+        u, _ = solver.solve(f.detach(), strict=True)
         ctx.solver = solver
         ctx.save_for_backward(kappa, u)
         ctx.mark_non_differentiable()
@@ -24,7 +25,7 @@ class _Solve(torch.autograd.Function):
         solver = ctx.solver
         kappa, u = ctx.saved_tensors
         solver.ensure_kappa(kappa)
-        lam, _ = solver.solve_transpose(grad_u.contiguous())
+        lam, _ = solver.solve_transpose(grad_u.contiguous(), strict=True)
         gk = solver.grad_kappa(u, lam) if ctx.needs_input_grad[0] else None
         gf = solver.apply_mass(lam) if ctx.needs_input_grad[1] else None
         return gk, gf, None

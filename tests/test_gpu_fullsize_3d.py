@@ -17,7 +17,7 @@ import paper_2012_08024_amd as cm  # noqa: E402
 from oracle.cdg import CDG  # noqa: E402
 from oracle.mesh import Topology  # noqa: E402
 from kernel_coverage import uncovered  # noqa: E402
-from workloads import CONFIGS, config_mesh  # noqa: E402
+from workloads import CONFIGS, config_mesh, source_sine  # noqa: E402
 
 
 @pytest.fixture(scope="module", params=["c3", "c5"])
@@ -26,7 +26,8 @@ def c5(request):
     mesh, kappa = config_mesh(cfg)
     parents, sizes = cm.agglomerate(mesh, cfg["levels"], cfg["agg_seed"], p=cfg["p"])
     print(request.param, "full size", list(sizes), flush=True)
-    solver = cm.Solver(mesh, cfg["p"], kappa, parents, sizes, mg_precision=cm.MG_FP32, tol=cfg["tol"])
+    solver = cm.Solver(mesh, cfg["p"], kappa, parents, sizes, mg_precision=cm.MG_FP32, tol=cfg["tol"],
+                       max_iter=1000)
     print(request.param, "setup done", flush=True)
     yield cfg, mesh, kappa, solver
     solver.close()
@@ -77,3 +78,27 @@ def test_launch_configuration_is_parity_covered(c5):
     info = solver.launch_info()
     print("launch configuration", {k: (list(v) if hasattr(v, "__len__") else v) for k, v in info.items()}, flush=True)
     assert not uncovered(info, 1, solver.np)
+
+
+def test_adjoint_homogeneity_identity_at_full_size(c5):
+    # the gradient of L = 1/2 ||u - u_t||_M^2 through the FP32 V-cycle's FCG at
+    # full size: sum_e kappa_e dL/dkappa_e = -(u - u_t)^T M_0 u (A is linear
+    # and homogeneous in kappa, so lambda^T A u = (A lambda)^T u = g^T u; the
+    # gap is -r_lambda^T u, of the order of the adjoint solve's residual).
+    # u_t is the solution at kappa = 1 (the 3D p = 3 workload's target), or at
+    # kappa = 2 where the workload's kappa is 1
+    cfg, mesh, kappa, solver = c5
+    f = torch.tensor(source_sine(solver.node_coords().reshape(-1, 3)), device="cuda")
+    kt = np.ones(mesh.n_elem) * (2.0 if np.all(kappa == 1.0) else 1.0)
+    solver.update_kappa(kt)
+    ut, it_t = solver.solve(f, strict=True)
+    solver.update_kappa(kappa)
+    u, it_u = solver.solve(f, strict=True)
+    g = solver.apply_mass(u - ut)
+    lam, it_l = solver.solve_transpose(g, strict=True)
+    gk = solver.grad_kappa(u, lam)
+    lhs = float(torch.dot(torch.tensor(kappa, device="cuda"), gk))
+    rhs = -float(torch.dot(u - ut, solver.apply_mass(u)))
+    print("homogeneity: lhs %.12e rhs %.12e relative gap %.2e; iterations %d %d %d"
+          % (lhs, rhs, abs(lhs - rhs) / abs(rhs), it_t.iterations, it_u.iterations, it_l.iterations), flush=True)
+    assert abs(lhs - rhs) <= 1e-8 * abs(rhs)

@@ -149,3 +149,28 @@ def test_fcg1_iterates_equal_pcg_for_symmetric_preconditioner():
     # and the residual contracts
     r = [np.linalg.norm(b - H.A[0] @ x) for x in h1]
     assert (r[-1] / r[0]) ** (1.0 / (len(r) - 1)) < 1.0
+
+
+def test_refinement_recovers_an_exact_integer_solution():
+    # iterative refinement with an extended-precision residual: on an SPD
+    # system with integer entries and an integer solution x* (b = A x* exact
+    # in FP64), inner solves accurate to only 1e-3 still reach x* to the
+    # rounding of x; the extended residual falls by about 1e-3 per round
+    import scipy.sparse as sp
+    from oracle.krylov import refine
+    n = 40
+    T = sp.diags([-np.ones(n - 1), 4.0 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1])
+    A = (sp.kron(sp.eye(n), T) + sp.kron(sp.diags([-np.ones(n - 1), -np.ones(n - 1)], [-1, 1]), sp.eye(n)))
+    A = (A + sp.eye(n * n) * 0.25).tocsr()  # entries 4.25 and -1: exact in FP64, and so is b
+    xs = np.random.default_rng(3).integers(-50, 50, n * n).astype(np.float64)
+    b = A @ xs
+    assert np.array_equal(b, np.asarray((A.astype(np.longdouble) @ xs.astype(np.longdouble)), dtype=np.float64))
+    Dinv = 1.0 / A.diagonal()
+    x, res = refine(A, b, lambda r: fcg(A, r, lambda v: Dinv * v, tol=1e-3)[0], rounds=6)
+    assert np.abs(x - xs).max() <= 1e-13 * np.abs(xs).max()
+    assert res[-1] <= 1e-15
+    assert all(res[k + 1] <= 1e-2 * res[k] for k in range(3))
+    # a plain FP64 solve to the same final residual is not available: FCG
+    # at 1e-3 alone stays far from x*
+    x0 = fcg(A, b, lambda v: Dinv * v, tol=1e-3)[0]
+    assert np.abs(x0 - xs).max() > 1e-6 * np.abs(xs).max()
