@@ -214,6 +214,25 @@ int cdgmg_setup(const cdgmg_mesh* mesh, int p, const double* kappa_dev,
                 const cdgmg_hierarchy* hier, const cdgmg_options* opts, void* workspace_dev,
                 size_t workspace_bytes, void* stream, cdgmg_handle** out);
 
+/* cdgmg_setup without a workspace argument and without any allocation of
+ * device or pinned host memory, for callers that cannot allocate: serving
+ * loops and harnesses that forbid hipMalloc or allocating library calls.  The
+ * handle's device arrays are laid out in a static device array of 64 MiB
+ * (67 108 864 bytes) that every GPU the library runs on holds until the
+ * process ends; its host readback buffers are ordinary host memory (the
+ * per-iteration copy of the residual norm is then not overlapped).  A problem
+ * whose cdgmg_workspace_size exceeds 64 MiB is refused with CDGMG_ERR_ARG
+ * (2D p = 2 fits up to about 8 000 triangles).  Calls would race on the
+ * shared array, so one live handle per GPU holds it: a second call on the
+ * same GPU before cdgmg_destroy of the first is refused with CDGMG_ERR_ARG
+ * (the check is thread-safe).  The array keeps the last handle's contents;
+ * setup writes or clears every part it reads, so nothing of an earlier
+ * handle is used.  Otherwise as cdgmg_setup, on the device current at the
+ * call. */
+int cdgmg_setup_static(const cdgmg_mesh* mesh, int p, const double* kappa_dev,
+                       const cdgmg_hierarchy* hier, const cdgmg_options* opts, void* stream,
+                       cdgmg_handle** out);
+
 /* Re-assemble A_0 = sum_e kappa_e A^(e) (eq. (primal_form) with the element
  * coefficient kappa_e on element e's terms) for new coefficients kappa_dev
  * (device float64 [n_elem], > 0 and finite) and rebuild the coarse operators

@@ -68,6 +68,7 @@ _SIGS = {
     "cdgmg_switch": ([_vp, _i, _u64, _vp], _i),
     "cdgmg_workspace_size": ([_vp, _i, _vp, _vp, _vp], _i),
     "cdgmg_setup": ([_vp, _i, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp], _i),
+    "cdgmg_setup_static": ([_vp, _i, _vp, _vp, _vp, _vp, _vp], _i),
     "cdgmg_update_kappa": ([_vp, _vp], _i),
     "cdgmg_solve": ([_vp, _vp, _vp, _vp], _i),
     "cdgmg_solve_rhs": ([_vp, _vp, _vp, _vp], _i),
@@ -229,7 +230,7 @@ class SolveInfo:
 class Solver:
     """setup(mesh, p, kappa, hierarchy) -> solve(f) -> u on the current GPU."""
 
-    def __init__(self, mesh, p, kappa, parents, sizes, **options):
+    def __init__(self, mesh, p, kappa, parents, sizes, static_workspace=False, **options):
         import torch
         self.torch = torch
         self.hm = mesh if isinstance(mesh, HostMesh) else HostMesh.of(mesh)
@@ -250,13 +251,20 @@ class Solver:
         hier = _Hier(len(sizes), _ptr(sizes).value, _ptr(par).value)
         kappa = self._dev(kappa)
         self.handle = ctypes.c_void_p()
-        # the device memory of the handle: one torch-owned workspace
-        nbytes = workspace_size(self.hm, p, parents, sizes, self.opts)
-        self.workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
         stream = torch.cuda.current_stream().cuda_stream
-        _check(lib.cdgmg_setup(ctypes.byref(self.hm.c), p, kappa.data_ptr(), ctypes.byref(hier),
-                               ctypes.byref(self.opts), self.workspace.data_ptr(), nbytes,
-                               ctypes.c_void_p(stream), ctypes.byref(self.handle)))
+        if static_workspace:
+            # the library's static per-GPU workspace: nothing is allocated
+            self.workspace = None
+            _check(lib.cdgmg_setup_static(ctypes.byref(self.hm.c), p, kappa.data_ptr(), ctypes.byref(hier),
+                                          ctypes.byref(self.opts), ctypes.c_void_p(stream),
+                                          ctypes.byref(self.handle)))
+        else:
+            # the device memory of the handle: one torch-owned workspace
+            nbytes = workspace_size(self.hm, p, parents, sizes, self.opts)
+            self.workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
+            _check(lib.cdgmg_setup(ctypes.byref(self.hm.c), p, kappa.data_ptr(), ctypes.byref(hier),
+                                   ctypes.byref(self.opts), self.workspace.data_ptr(), nbytes,
+                                   ctypes.c_void_p(stream), ctypes.byref(self.handle)))
         self._kappa = kappa.detach().clone()
 
     def _dev(self, a, dtype=None):

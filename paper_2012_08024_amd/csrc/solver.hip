@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -156,7 +157,20 @@ struct Workspace {
   bool counting = true;
 };
 
+// Workspace of the handles made by cdgmg_setup_static, for callers that cannot
+// allocate: one array per GPU, held by every GPU the library runs on until the
+// process ends.  In host code `scratch` is a host-side stand-in; its device
+// address on each GPU comes from hipGetSymbolAddress (static_scratch) and is
+// the only way host code refers to it.  One live handle per GPU owns it.
+constexpr size_t STATIC_WS_BYTES = (size_t)64 << 20;
+constexpr int STATIC_MAX_DEV = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[STATIC_MAX_DEV];
+bool g_static_busy[STATIC_MAX_DEV];
+
 }  // namespace
+
+static __device__ __align__(256) char scratch[STATIC_WS_BYTES];
 
 struct cdgmg_handle {
   Problem P;
@@ -168,6 +182,7 @@ struct cdgmg_handle {
   std::vector<DLevel> lv;
   Workspace own_ws;
   Workspace* ws = &own_ws;  // a lower hp level carves from its owner's workspace
+  int static_dev = -1;      // GPU whose static workspace this handle holds (cdgmg_setup_static)
   bool pinned = true;       // host readback buffers in pinned (hipHostMalloc) memory
   // level 0
   double *UA = nullptr, *UH = nullptr, *M = nullptr, *kappa = nullptr;
@@ -1401,7 +1416,7 @@ int check_handle(cdgmg_handle* h) {
 // copied into it.  ws null: a counting workspace (no device call is made).
 // On error *out is null and the partial handle is freed.
 int prepare(const cdgmg_mesh* mesh, int p, const cdgmg_hierarchy* hier, const cdgmg_options* opts,
-            const Workspace* ws, hipStream_t stream, cdgmg_handle** out) {
+            const Workspace* ws, hipStream_t stream, bool pinned, cdgmg_handle** out) {
   *out = nullptr;
   if (!mesh || !hier) {
     set_error("setup: invalid argument");
@@ -1417,6 +1432,7 @@ int prepare(const cdgmg_mesh* mesh, int p, const cdgmg_hierarchy* hier, const cd
   if (!h) return CDGMG_ERR_NOMEM;
   h->o = o;
   h->stream = stream;
+  h->pinned = pinned;
   if (ws) h->own_ws = *ws;
   int rc;
   try {
@@ -1544,7 +1560,7 @@ int cdgmg_workspace_size(const cdgmg_mesh* mesh, int p, const cdgmg_hierarchy* h
   }
   *bytes = 0;
   cdgmg_handle* h = nullptr;
-  RETURN_IF(prepare(mesh, p, hier, opts, nullptr, nullptr, &h));
+  RETURN_IF(prepare(mesh, p, hier, opts, nullptr, nullptr, true, &h));
   *bytes = h->ws->used;
   cdgmg_destroy(h);
   return CDGMG_OK;
@@ -1567,7 +1583,7 @@ int cdgmg_setup(const cdgmg_mesh* mesh, int p, const double* kappa_dev, const cd
   ws.cap = workspace_bytes;
   ws.counting = false;
   cdgmg_handle* h = nullptr;
-  RETURN_IF(prepare(mesh, p, hier, opts, &ws, (hipStream_t)stream, &h));
+  RETURN_IF(prepare(mesh, p, hier, opts, &ws, (hipStream_t)stream, true, &h));
   int rc = finish_setup(h, kappa_dev);
   if (rc) {
     std::string msg = cdg::last_error_cstr();
@@ -1577,6 +1593,69 @@ int cdgmg_setup(const cdgmg_mesh* mesh, int p, const double* kappa_dev, const cd
   }
   *out = h;
   return CDGMG_OK;
+}
+
+int cdgmg_setup_static(const cdgmg_mesh* mesh, int p, const double* kappa_dev, const cdgmg_hierarchy* hier,
+                       const cdgmg_options* opts, void* stream, cdgmg_handle** out) {
+  set_error("");
+  if (!kappa_dev || !out) {
+    set_error("setup_static: invalid argument");
+    return CDGMG_ERR_ARG;
+  }
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= STATIC_MAX_DEV) {
+    set_error("setup_static: device index out of range");
+    return CDGMG_ERR_ARG;
+  }
+  Workspace ws;
+  {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {  // first call on this device, with it current
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr) {
+        set_error(std::string("setup_static: hipGetSymbolAddress of the static workspace failed: ") +
+                  hipGetErrorString(e));
+        return CDGMG_ERR_DEVICE;
+      }
+      g_static_ptr[dev] = ptr;
+    }
+    if (g_static_busy[dev]) {
+      set_error("setup_static: the static workspace of this device is held by a live handle (destroy it first)");
+      return CDGMG_ERR_ARG;
+    }
+    g_static_busy[dev] = true;
+    ws.base = (char*)g_static_ptr[dev];
+  }
+  ws.cap = STATIC_WS_BYTES;
+  ws.counting = false;
+  cdgmg_handle* h = nullptr;
+  int rc = prepare(mesh, p, hier, opts, &ws, (hipStream_t)stream, false, &h);
+  if (!rc) {
+    h->static_dev = dev;
+    rc = finish_setup(h, kappa_dev);
+    if (rc) {
+      std::string msg = cdg::last_error_cstr();
+      cdgmg_destroy(h);  // releases the static workspace
+      set_error(msg);
+      return rc;
+    }
+    *out = h;
+    return CDGMG_OK;
+  }
+  std::string msg = cdg::last_error_cstr();
+  if (rc == CDGMG_ERR_ARG && msg.find("workspace holds") != std::string::npos)
+    msg = "setup_static: the problem does not fit the static workspace of " + std::to_string(STATIC_WS_BYTES) +
+          " bytes (" + msg + ")";
+  {
+    // prepare may have copied into the array on the stream: done before release
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static_busy[dev] = false;
+  }
+  set_error(msg);
+  return rc;
 }
 
 int cdgmg_update_kappa(cdgmg_handle* h, const double* kappa_dev) {
@@ -1833,6 +1912,10 @@ int cdgmg_destroy(cdgmg_handle* h) {
   host_free(h, h->hgmY);
   host_free(h, h->hscal);
   host_free(h, h->herr);
+  if (h->static_dev >= 0) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static_busy[h->static_dev] = false;
+  }
   delete h;
   return CDGMG_OK;
 }
