@@ -9,7 +9,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcdgmg.so")
 ARCH = os.environ.get("CDGMG_ARCH", "gfx950")
 
-HOST_SRC = ["host_mesh.cpp", "host_fem.cpp", "host_flux.cpp", "host_debug.cpp"]
+HOST_SRC = ["host_mesh.cpp", "host_fem.cpp", "host_flux.cpp", "host_debug.cpp", "host_abi.cpp"]
 DEV_SRC = ["solver.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed FP32 instructions are disabled for all device code; FMA contraction
@@ -52,6 +52,25 @@ def build(verbose=True):
     _run([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lpthread"])
     os.replace(tmp, LIB)
     return LIB
+
+
+def build_host_check(out_dir=None):
+    """The host half of the library (no HIP) and a driver, built with
+    AddressSanitizer and UndefinedBehaviorSanitizer for CPU tests; returns the
+    executable's path."""
+    out_dir = out_dir or os.path.join(BUILD, "sanitize")
+    os.makedirs(out_dir, exist_ok=True)
+    flags = ["-O1", "-g", "-std=c++17", "-pthread", "-fno-omit-frame-pointer",
+             "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+    objs, cmds = [], []
+    for src in HOST_SRC + ["host_check.cpp"]:
+        obj = os.path.join(out_dir, src + ".o")
+        cmds.append(["g++"] + flags + ["-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    _run_all(cmds)
+    exe = os.path.join(out_dir, "host_check")
+    _run(["g++"] + flags + ["-o", exe] + objs)
+    return exe
 
 
 if __name__ == "__main__":
