@@ -49,38 +49,40 @@ def cpu_model():
 
 def cpu_baseline(cfg, n_sample):
     """The FP64 oracle (same generator, smaller n; same p, levels, cycle and
-    outer solver) timed around the solve only, on one thread."""
-    from threadpoolctl import threadpool_limits
+    outer solver) timed around the solve only, on one thread.  Returns the
+    record and (mesh, oracle solution) for the GPU comparison."""
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle.agglomerate import build_hierarchy
     from oracle.cdg import CDG
     from oracle.krylov import fcg
     from oracle.multigrid import Hierarchy
-    from workloads import mesh2d_jittered_delaunay, mesh3d_kuhn, source_sine
+    from workloads import config_mesh, source_sine
 
     with threadpool_limits(1):
-        if cfg["dim"] == 2:
-            m = mesh2d_jittered_delaunay(n_sample, cfg["mesh_seed"])
-        else:
-            m = mesh3d_kuhn(n_sample, cfg["mesh_seed"])
+        m, kappa = config_mesh(cfg, n=n_sample)
         t0 = time.perf_counter()
         cdg = CDG(m.coords, m.e2v, m.face_bc, cfg["p"])
-        par = build_hierarchy(m.e2v, cdg.topo.neighbor_pairs(), cfg["levels"], cfg["agg_seed"])
-        H = Hierarchy(cdg, par, coarsening="primal")
+        par = build_hierarchy(m.e2v, cdg.topo.neighbor_pairs(), cfg["levels"] or 50, cfg["agg_seed"],
+                              coarse_dofs=cfg.get("coarse_dofs") or None, n_p=cdg.np)
+        H = Hierarchy(cdg, par, kappa=kappa, coarsening="primal")
         t_setup = time.perf_counter() - t0
         b = cdg.M0() @ source_sine(cdg.nodes_phys().reshape(-1, cfg["dim"]))
         t0 = time.perf_counter()
         x, it, res = fcg(H.A[0], b, H.vcycle, tol=cfg["tol"])
         t_solve = time.perf_counter() - t0
+        pools = [{k: d.get(k) for k in ("internal_api", "num_threads")} for d in threadpool_info()]
     dofs = cdg.N * cdg.np
-    return {
+    rec = {
         "value": dofs / t_solve, "unit": "DOFs/s", "cores": 1, "kind": "oracle",
         "sample": "same generator at n=%d (%d elements, %d DOFs), p=%d, %d levels, FP64 V(2,2) "
                   "block Jacobi in FCG(1) to %.0e; solve only, setup %.1f s excluded"
                   % (n_sample, cdg.N, dofs, cfg["p"], len(H.sizes), cfg["tol"], t_setup),
-        "iterations": it, "solve_s": t_solve, "cpu": cpu_model(),
-        "threads": "1 (threadpool_limits(1); SciPy sparse products are single-threaded)",
+        "iterations": it, "solve_s": t_solve, "cpu": cpu_model(), "host_cpu_count": os.cpu_count(),
+        "threads": "1 process, 1 thread: threadpool_limits(1) on the BLAS pools %s; SciPy sparse products "
+                   "are single-threaded" % pools,
     }
+    return rec, m, x
 
 
 def smoother_bytes(nnzb0, n0, npb, s):
@@ -291,8 +293,22 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("CPU oracle sample n=%d" % args.cpu_sample_n)
-        cpu = cpu_baseline(cfg, args.cpu_sample_n)
+        cpu, m_s, x_s = cpu_baseline(cfg, args.cpu_sample_n)
         log("CPU oracle: %.3g DOFs/s (%d iterations)" % (cpu["value"], cpu["iterations"]))
+        # the same sample solved by the GPU path (FP32 V-cycle, same options)
+        ps, ss = cm.agglomerate(m_s, cfg["levels"] or 50, cfg["agg_seed"], p=cfg["p"],
+                                coarse_dofs=cfg.get("coarse_dofs", 0))
+        _, ks = config_mesh(cfg, n=args.cpu_sample_n)
+        sg = cm.Solver(m_s, cfg["p"], ks, ps, ss, mg_precision=cm.MG_FP32, tol=cfg["tol"], outer=outer,
+                       restart=args.restart, p_coarse=args.p_coarse, p_jump=args.p_jump)
+        ug, ig = sg.solve(source_sine(sg.node_coords().reshape(-1, mesh.dim)))
+        sg.close()
+        ug = ug.cpu().numpy()
+        cpu["gpu_iterations_on_sample"] = ig.iterations
+        cpu["error_vs_oracle"] = float(np.linalg.norm(ug - x_s) / np.linalg.norm(x_s))
+        cpu["error_vs_oracle_max"] = float(np.abs(ug - x_s).max() / np.abs(x_s).max())
+        log("GPU on the sample: %d iterations, relative difference to the oracle %.2e"
+            % (ig.iterations, cpu["error_vs_oracle"]))
 
     result = {
         "metric": METRIC,
