@@ -85,26 +85,48 @@ def cpu_baseline(cfg, n_sample):
     return rec, m, x
 
 
-def smoother_bytes(nnzb0, n0, npb, s):
-    """Algorithmic HBM bytes of one level-0 damped block-Jacobi sweep on the
-    D^{-1}-prescaled operator: its off-diagonal blocks and their column
-    indices, and D^{-1} b, x read, x written."""
+def facet_nodes(dim, npb):
+    """Nodes of the degree-p simplex on one facet: the nonzero rows or columns
+    of a level-0 off-diagonal block in facet-trace form."""
+    p = {3: 1, 6: 2, 10: 3} if dim == 2 else {4: 1, 10: 2, 20: 3}
+    q = p[npb]
+    return q + 1 if dim == 2 else (q + 1) * (q + 2) // 2
+
+
+def smoother_bytes(nnzb0, n0, npb, s, nfn, nf):
+    """Algorithmic HBM bytes of one level-0 damped block-Jacobi sweep
+    x <- (1 - omega) x + omega D^{-1} (b - A_off x) on the facet-trace form:
+    the off-diagonal blocks' n_p x n_fn stored values, their column indices and
+    kinds (one int32 and one byte per facet slot), D^{-1}, and b, x read, x
+    written."""
     off = nnzb0 - n0
-    return off * npb * npb * s + 4 * off + 3 * n0 * npb * s
+    return off * npb * nfn * s + 5 * n0 * nf + n0 * npb * npb * s + 3 * n0 * npb * s
 
 
-def spmv_bytes(nnzb0, n0, npb):
-    """Outer FP64 q = A_0 p with (p,q), (p,r): A_0 blocks + cols, p, r read, q written."""
-    return nnzb0 * npb * npb * 8 + 4 * nnzb0 + 3 * n0 * npb * 8
+def restrict_bytes(nnzb0, n0, npb, s, nfn, nf):
+    """Level-0 residual + restriction L_e^T (b - A_rr x - A_off x): the
+    off-diagonal values, indices and kinds, the diagonal blocks, L_e, b and x
+    read, the restricted residual written."""
+    off = nnzb0 - n0
+    return off * npb * nfn * s + 5 * n0 * nf + 2 * n0 * npb * npb * s + 3 * n0 * npb * s
 
 
-def iteration_bytes(sizes, nnzb, npb, nu1=2, nu2=2, s=4):
+def spmv_bytes(nnzb0, n0, npb, nfn, nf):
+    """Outer FP64 q = A_0 p with (p,q), (p,r): dense diagonal blocks, the
+    off-diagonal blocks' facet-trace values, indices and kinds, p, r read, q
+    written."""
+    off = nnzb0 - n0
+    return n0 * npb * npb * 8 + off * npb * nfn * 8 + 5 * n0 * nf + 3 * n0 * npb * 8
+
+
+def iteration_bytes(sizes, nnzb, npb, nfn, nf, nu1=2, nu2=2, s=4):
     """Algorithmic bytes of one FCG(1) iteration with a V(nu1, nu2) cycle in
     precision s (bytes) and the FP64 outer loop, per level: what each kernel
     must read and write once (operator blocks, indices, vectors), nothing for
-    re-reads.  The first pre-sweep of every level is fused with forming
-    D^{-1} b (no operator read); the last post-sweep of level 0 also reads q
-    for the fused (z, q) dot."""
+    re-reads.  Level 0 runs on the facet-trace form with D^{-1}; the coarse
+    levels on D^{-1}-prescaled strips.  The first pre-sweep of every level is
+    fused with forming D^{-1} b (no operator read); the last post-sweep of
+    level 0 also reads q for the fused (z, q) dot."""
     L = len(sizes) - 1
     n = [int(x) for x in sizes]
     nz = [int(x) for x in nnzb]
@@ -117,17 +139,21 @@ def iteration_bytes(sizes, nnzb, npb, nu1=2, nu2=2, s=4):
             b += n[l] * npb * ld * s + ld * s + n[l] * npb * s
             out["level%d" % l] = b
             break
-        off = nz[l] - n[l]
-        sweep = off * p2 * s + 4 * off + 3 * n[l] * npb * s + (0 if l == 0 else 8 * n[l])
-        entry = (n[l] * npb * 8 if l == 0 else n[l - 1] * npb * s + 4 * n[l]) + n[l] * p2 * s + 2 * n[l] * npb * s
-        restrict = sweep + n[l] * p2 * s
         prolong = n[l] * p2 * s + 2 * n[l] * npb * s + 4 * n[l] + n[l + 1] * npb * s
-        b = entry + (nu1 - 1) * sweep + restrict + prolong + nu2 * sweep
         if l == 0:
-            b += n[0] * npb * 8  # q read by the last post-sweep's dot
+            sweep = smoother_bytes(nz[0], n[0], npb, s, nfn, nf)
+            entry = n[0] * npb * 8 + n[0] * p2 * s + 2 * n[0] * npb * s
+            restrict = restrict_bytes(nz[0], n[0], npb, s, nfn, nf) + n[0] * npb * s
+            b = entry + (nu1 - 1) * sweep + restrict + prolong + nu2 * sweep + n[0] * npb * 8
+        else:
+            off = nz[l] - n[l]
+            sweep = off * p2 * s + 4 * off + 3 * n[l] * npb * s + 8 * n[l]
+            entry = n[l - 1] * npb * s + 4 * n[l] + n[l] * p2 * s + 2 * n[l] * npb * s
+            restrict = sweep + n[l] * p2 * s
+            b = entry + (nu1 - 1) * sweep + restrict + prolong + nu2 * sweep
         out["level%d" % l] = b
     m = n[0] * npb
-    out["outer"] = (m * s + 2 * m * 8) + spmv_bytes(nz[0], n[0], npb) + 6 * m * 8
+    out["outer"] = (m * s + 2 * m * 8) + spmv_bytes(nz[0], n[0], npb, nfn, nf) + 6 * m * 8
     out["total"] = sum(out.values())
     return out
 
@@ -243,11 +269,12 @@ def main():
     s32.set_profile(False)
     avg_smooth_ms = kms["smooth0"] / max(kcnt["smooth0"], 1)
     avg_spmv_ms = kms["spmv"] / max(kcnt["spmv"], 1)
-    sb = smoother_bytes(int(nnzb[0]), mesh.n_elem, npb, 4)
+    nfn, nf = facet_nodes(mesh.dim, npb), mesh.dim + 1
+    sb = smoother_bytes(int(nnzb[0]), mesh.n_elem, npb, 4, nfn, nf)
     achieved = sb / (avg_smooth_ms * 1e-3) / 1e9
-    spb = spmv_bytes(int(nnzb[0]), mesh.n_elem, npb)
+    spb = spmv_bytes(int(nnzb[0]), mesh.n_elem, npb, nfn, nf)
     spmv_gbs = spb / (avg_spmv_ms * 1e-3) / 1e9
-    itb = iteration_bytes(sizes, nnzb, npb) if len(nnzb) == len(sizes) else None
+    itb = iteration_bytes(sizes, nnzb, npb, nfn, nf) if len(nnzb) == len(sizes) else None
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "traffic_%s.json" % args.config)
     if os.path.exists(tpath):
@@ -352,12 +379,14 @@ def main():
         "kernel_ms_per_solve": {k: kms[k] / args.steps for k in cm.K_NAMES if kcnt[k]},
         "kernel_launches_per_solve": {k: kcnt[k] / args.steps for k in cm.K_NAMES if kcnt[k]},
         "roofline": {
-            "kernel": "level-0 damped block-Jacobi sweep (k_sweep0<float,%d,H>, FP32)" % npb,
+            "kernel": "level-0 damped block-Jacobi sweep on the facet-trace form (k_sweep0<float,%d,H,%d>, FP32)"
+                      % (npb, nf),
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "algorithmic_bytes_per_launch": sb, "avg_launch_ms": avg_smooth_ms,
         },
-        "outer_spmv_roofline": {"kernel": "outer q = A_0 p with dots (k_spmv_dots_hs<%d,H>, FP64)" % npb, "achieved": spmv_gbs,
+        "outer_spmv_roofline": {"kernel": "outer q = A_0 p on the facet-trace form, with dots (k_spmv0<%d,H,%d>, FP64)"
+                                          % (npb, nf), "achieved": spmv_gbs,
                                 "frac": spmv_gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": spb,
                                 "avg_launch_ms": avg_spmv_ms},
         "algorithmic_bytes_per_iteration": itb,

@@ -184,11 +184,13 @@ void RefElem::init(int d_, int p_) {
   exps = graded_exponents(d, p);
   np = (int)exps.size();
   nodes.clear();
+  bary.clear();
   if (d == 2) {
     for (int j = 0; j <= p; ++j)
       for (int i = 0; i <= p - j; ++i) {
         nodes.push_back((double)i / p);
         nodes.push_back((double)j / p);
+        bary.push_back({p - i - j, i, j, 1});
       }
   } else {
     for (int k = 0; k <= p; ++k)
@@ -197,6 +199,7 @@ void RefElem::init(int d_, int p_) {
           nodes.push_back((double)i / p);
           nodes.push_back((double)j / p);
           nodes.push_back((double)k / p);
+          bary.push_back({p - i - j - k, i, j, k});
         }
   }
   std::vector<double> V(np * np);
@@ -524,13 +527,20 @@ int build_problem(const cdgmg_mesh& m, int p, const cdgmg_hierarchy& h, const cd
         if (!hosted) continue;  // unhosted interior facet or Neumann facet
         Facet F = facet(m, R, e, i);
         Geo GN{};
-        if (nb >= 0) GN = geometry(m, nb);
+        int jn = 0;  // the facet's local index in the neighbour
+        if (nb >= 0) {
+          GN = geometry(m, nb);
+          while (T.nbr[nb * nf + jn] != e) ++jn;
+        }
+        // traces on the facet: basis functions of nodes off the facet vanish
+        // there identically, and are set to exact zeros (so every
+        // off-diagonal block couples the neighbours through facet nodes only)
         for (int q = 0; q < R.nfq; ++q) {
           to_ref(G, d, &F.x[q * d], xi);
           R.eval(xi, phi);
           R.eval_grad(xi, gr);
           for (int n = 0; n < np; ++n) {
-            TK[q * np + n] = phi[n];
+            TK[q * np + n] = R.on_facet(n, i) ? phi[n] : 0.0;
             double dn = 0.0;
             for (int c = 0; c < d; ++c) {
               double gc = 0.0;
@@ -542,7 +552,7 @@ int build_problem(const cdgmg_mesh& m, int p, const cdgmg_hierarchy& h, const cd
           if (nb >= 0) {
             to_ref(GN, d, &F.x[q * d], xi);
             R.eval(xi, phi);
-            for (int n = 0; n < np; ++n) TN[q * np + n] = phi[n];
+            for (int n = 0; n < np; ++n) TN[q * np + n] = R.on_facet(n, jn) ? phi[n] : 0.0;
           }
         }
         // jump w = T_N u_N - T_K u_K;  F_K = -T_K^T W T_K, F_N = T_K^T W T_N
@@ -581,8 +591,7 @@ int build_problem(const cdgmg_mesh& m, int p, const cdgmg_hierarchy& h, const cd
             UNN[a * np + b] = s2;
           }
         const int64_t rn = iperm0[nb];
-        int j = 0;
-        while (T.nbr[nb * nf + j] != e) ++j;
+        const int j = jn;
         double* ua = &P.UA[((size_t)r * W0 + i + 1) * nb2];
         double* uh = &P.UH[((size_t)r * W0 + i + 1) * nb2];
         double* ub = &P.UA[((size_t)rn * W0 + j + 1) * nb2];
@@ -648,15 +657,19 @@ int build_problem(const cdgmg_mesh& m, int p, const cdgmg_hierarchy& h, const cd
           for (int c = 0; c < d; ++c) vn += v[c] * F.n[c];
           if (vn >= 0.0) continue;
           Geo GN{};
-          if (nb >= 0) GN = geometry(m, nb);
+          int jn = 0;
+          if (nb >= 0) {
+            GN = geometry(m, nb);
+            while (T.nbr[nb * nf + jn] != e) ++jn;
+          }
           for (int q = 0; q < R.nfq; ++q) {
             to_ref(G, d, &F.x[q * d], xi);
             R.eval(xi, phi);
-            for (int n = 0; n < np; ++n) TK[q * np + n] = phi[n];
+            for (int n = 0; n < np; ++n) TK[q * np + n] = R.on_facet(n, i) ? phi[n] : 0.0;
             if (nb >= 0) {
               to_ref(GN, d, &F.x[q * d], xi);
               R.eval(xi, phi);
-              for (int n = 0; n < np; ++n) TN[q * np + n] = phi[n];
+              for (int n = 0; n < np; ++n) TN[q * np + n] = R.on_facet(n, jn) ? phi[n] : 0.0;
             }
           }
           matTmulM(np, TK.data(), F.w.data(), TK.data(), R.nfq, tmp.data());

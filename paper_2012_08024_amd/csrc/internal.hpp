@@ -47,6 +47,10 @@ struct RefElem {
   int d = 0, p = 0, np = 0;
   std::vector<std::array<int, 3>> exps;  // graded monomial exponents
   std::vector<double> nodes;             // [np][d]
+  std::vector<std::array<int, 4>> bary;  // [np]: integer barycentric coordinates p * lambda_f of each node
+  // node n lies on local facet f (opposite vertex f) iff bary[n][f] == 0; the
+  // trace of its basis function on every other facet is identically zero
+  bool on_facet(int n, int f) const { return bary[n][f] == 0; }
   std::vector<double> coef;              // [nmono][np]: phi_n = sum_m coef[m][n] xi^m
   std::vector<double> qx, qw;            // volume rule on the reference simplex
   std::vector<double> fx, fw;            // facet rule on the reference (d-1)-simplex

@@ -565,107 +565,388 @@ __global__ __launch_bounds__(TPB) void k_dense_gemv(int64_t n, int64_t ld, const
 }
 
 // ------------------------------------------------------------------
-// V-cycle kernels on D^{-1}-prescaled operators.  The damped block-Jacobi
-// sweep x <- x + omega D^{-1} (b - A x) is evaluated as
-//     x <- (1 - omega) x + omega (bt - At_off x),   bt = D^{-1} b,  At = D^{-1} A,
-// where the diagonal block of At is the identity and is not stored, and the
-// restricted residual L_e^T (b - A x)_e as Lt_e^T (bt - At x)_e with
-// Lt_e = D_e^T L_e.  The sweeps thus read neither D^{-1} nor the diagonal block.
+// Error-free transformations (Knuth TwoSum; FMA TwoProduct) for the outer
+// loop.  The relative rounding noise of a plain FP64 product A x is about
+// eps * || |A| |x| || / || A x ||, which grows like h^{-2} for this operator
+// (about 4e-10 on a 2D p=3 mesh with h = 1/316): above a 1e-10 target.  The
+// outer q = A p and the true residual are therefore accumulated as
+// double-double sums (Ogita, Rump & Oishi, "Accurate sum and dot product",
+// 2005, algorithm Dot2) and the iterate is kept as x_hi + x_lo.  These
+// kernels are bound by HBM bytes, so the extra FP64 operations are free.
+// FMA contraction must stay off in these routines: fusing the rounded product
+// p = a x into the following sum would make the error terms double-count.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+#pragma clang fp contract(off)
+  s = (a + b);
+  const double bb = (s - a);
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void dot2_acc(double a, double x, double& s, double& c) {
+#pragma clang fp contract(off)
+  const double p = (a * x);
+  const double ep = __builtin_fma(a, x, -p);
+  double t;
+  two_sum(s, p, s, t);
+  c = (c + (t + ep));
+}
+
+
+
+// ------------------------------------------------------------------
+// Level 0 in facet-trace form.  In the primal form (eq. (primal_form)) the
+// element K couples to its neighbour K' across the facet f only through the
+// terms that f's host contributes: jumps of traces on f, lifted traces, and
+// the host's normal derivatives paired with the other side's trace.  The
+// neighbour's basis therefore enters A(K, K') only through its trace on f, and
+// with the nodal basis the trace of a function whose node is off f vanishes
+// identically.  So an off-diagonal block of A_0 has nonzero entries only
+//   - in the columns of the neighbour's facet nodes, when K hosts f
+//     ("column" kind: A(K, K') = V P_f'^T, V n_p x n_fn), or
+//   - in the rows of K's facet nodes, when K' hosts f ("row" kind:
+//     A(K, K') = P_f V^T),
+// n_fn = p + 1 (2D) or (p + 1)(p + 2) / 2 (3D) facet nodes of n_p.  The host
+// assembly sets the vanishing traces to exact zeros, and setup checks that
+// every dropped entry is zero.  Both kinds store V, n_p x n_fn values: in
+// canonical order v[i][k] (i < n_p, k < n_fn) at
+//     ((s n_f + w) n_p n_fn + i n_fn + k) 64 + lane      (slice s, facet slot w),
+// column kind: v[i][k] = A(r, c)[i][fn(c's facet, k)]; row kind:
+// v[j][k] = A(r, c)[fn(r's facet w, k)][j].  meta[(s n_f + w) 64 + lane] is the
+// neighbour's local facet (column kind) or n_f (row kind); boundary slots are
+// zero column-kind blocks with the row itself as column.
 //
-// Level 0 (component-split): H wavefronts per 64-row slice, wavefront h owns
-// output components [h NI, (h+1) NI), NI = n_p / H (H = 1 is one thread per
-// row).  Every level-0 slice has the n_f + 1 slots of the element's facets
-// (zero blocks where a facet has no neighbour), so the slot loops are unrolled
-// and the column indices of all slots are loaded first.  Off-diagonal blocks:
-// block (r, w') at ((64 n_f s + 64 w') n_p^2 + (i n_p + j) 64 + lane), its
-// column at cols[64 (n_f + 1) s + 64 (w' + 1) + lane].
-template <typename T, int NP, int H, int NF>
-__device__ __forceinline__ void hs_scaled_residual(int64_t r, int lane, int h, const int32_t* __restrict__ cols,
-                                                   const T* __restrict__ At, const T* __restrict__ bt,
-                                                   const T* __restrict__ x, T* acc) {
-  constexpr int NP2 = NP * NP, NI = NP / H;
-  const int64_t s = r / WAVE;
-  const int64_t B = s * WAVE * (NF + 1), Bo = s * WAVE * NF;
-  int32_t c[NF];
+// The level-0 V-cycle runs on this form without prescaling: a damped
+// block-Jacobi sweep is x <- (1 - omega) x + omega D^{-1} (b - A_off x)
+// (D^{-1} A_rr = I), the restricted residual L_e^T (b - A_rr x - A_off x).
+// Per element this reads n_f n_p n_fn off-diagonal values and D^{-1} (n_p^2)
+// instead of the n_f n_p^2 of a prescaled D^{-1} A_off.
+//
+// H wavefronts share a 64-row slice (H divides n_p): wavefront h owns output
+// rows i in [h NI, (h + 1) NI), NI = n_p / H, of the column-kind products and
+// the input components j in the same range of the row-kind ones; the row-kind
+// partial sums (all n_p rows) are added across wavefronts through LDS.
+
+constexpr int deg_of(int np, int d) {
+  return d == 2 ? (np == 3 ? 1 : np == 6 ? 2 : 3) : (np == 4 ? 1 : np == 10 ? 2 : 3);
+}
+constexpr int facet_nodes(int np, int nf) {
+  return nf == 3 ? deg_of(np, 2) + 1 : (deg_of(np, 3) + 1) * (deg_of(np, 3) + 2) / 2;
+}
+// the k-th node (in the nodal order of the element) on local facet f, the facet
+// opposite vertex f: the nodes whose f-th integer barycentric coordinate is 0
+constexpr int facet_node(int np, int nf, int f, int k) {
+  const int d = nf - 1, p = deg_of(np, d);
+  int n = 0, cnt = 0;
+  for (int c = 0; c <= (d == 3 ? p : 0); ++c)
+    for (int j = 0; j <= p - c; ++j)
+      for (int i = 0; i <= p - j - c; ++i) {
+        const int lam[4] = {p - i - j - c, i, j, c};
+        if (lam[f] == 0) {
+          if (cnt == k) return n;
+          ++cnt;
+        }
+        ++n;
+      }
+  return 0;
+}
+template <int NP, int NF>
+struct FacetTab {
+  static constexpr int NFN = facet_nodes(NP, NF);
+  int v[NF][NFN];
+  constexpr FacetTab() : v() {
+    for (int f = 0; f < NF; ++f)
+      for (int k = 0; k < NFN; ++k) v[f][k] = facet_node(NP, NF, f, k);
+  }
+};
+// node of the k-th facet node on a facet chosen at run time (k fixed)
+template <int NP, int NF>
+__device__ __forceinline__ int facet_node_at(int f, int k) {
+  constexpr FacetTab<NP, NF> FT{};
+  int v = FT.v[0][k];
 #pragma unroll
-  for (int w = 0; w < NF; ++w) c[w] = cols[B + (int64_t)WAVE * (w + 1) + lane];
-#pragma unroll
-  for (int t = 0; t < NI; ++t) acc[t] = bt[r * NP + h * NI + t] - x[r * NP + h * NI + t];
+  for (int g = 1; g < NF; ++g) v = f == g ? FT.v[g][k] : v;
+  return v;
+}
+
+// sums of products: plain (rounded each step, contracted to FMA) or Dot2
+// (Ogita-Rump-Oishi, value s + c); addlo adds a product of a low-order part
+template <typename T, bool COMP>
+struct Acc {
+  T s = T(0);
+  __device__ __forceinline__ void add(T a, T x) { s += a * x; }
+  __device__ __forceinline__ void addlo(T a, T x) { s += a * x; }
+  __device__ __forceinline__ void merge(const Acc& o) { s += o.s; }
+  __device__ __forceinline__ T value() const { return s; }
+  __device__ __forceinline__ T lo() const { return T(0); }
+  __device__ __forceinline__ void set_lo(T) {}
+};
+template <>
+struct Acc<double, true> {
+  double s = 0.0, c = 0.0;
+  __device__ __forceinline__ double lo() const { return c; }
+  __device__ __forceinline__ void set_lo(double v) { c = v; }
+  __device__ __forceinline__ void add(double a, double x) { dot2_acc(a, x, s, c); }
+  __device__ __forceinline__ void addlo(double a, double x) { c = __builtin_fma(a, x, c); }
+  __device__ __forceinline__ void merge(const Acc& o) {
+#pragma clang fp contract(off)
+    double e;
+    two_sum(s, o.s, s, e);
+    c = (c + (o.c + e));
+  }
+  __device__ __forceinline__ double value() const {
+#pragma clang fp contract(off)
+    return s + c;
+  }
+};
+
+template <typename T, bool NT>
+__device__ __forceinline__ T ld(const T* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
+// This wavefront's share of sign * A_off x at row r = 64 s + lane: column-kind
+// blocks into acc[t] (row h NI + t), row-kind blocks into sc[i] (all rows,
+// partial over this wavefront's input components).  With LO the vector is
+// x + xl (xl the low-order part, accumulated without compensation).  The slot
+// loop is not unrolled, so that one slot's values are in registers at a time;
+// the row-kind sums go to r's facet-w nodes through a branch on the
+// (wavefront-uniform) slot.
+template <typename T, int NP, int H, int NF, bool COMP, bool LO, bool NT>
+__device__ __forceinline__ void off0(int64_t s, int lane, int h, const int32_t* __restrict__ cols,
+                                     const int8_t* __restrict__ meta, const T* __restrict__ Ac,
+                                     const T* __restrict__ x, const T* __restrict__ xl, T sign,
+                                     Acc<T, COMP>* acc, Acc<T, COMP>* sc) {
+  constexpr FacetTab<NP, NF> FT{};
+  constexpr int NFN = FacetTab<NP, NF>::NFN, NPF = NP * NFN, NI = NP / H;
+  // columns and kinds of all slots first: each slot's gathers then wait for
+  // one memory latency only
+  int32_t cw[NF];
+  int kw[NF];
 #pragma unroll
   for (int w = 0; w < NF; ++w) {
-    T xv[NP];
+    cw[w] = cols[(s * (NF + 1) + w + 1) * WAVE + lane];
+    kw[w] = meta[(s * NF + w) * WAVE + lane];
+  }
+#pragma unroll 1
+  for (int w = 0; w < NF; ++w) {
+    int32_t cv = cw[0];
+    int kd = kw[0];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) xv[j] = x[(int64_t)c[w] * NP + j];
-    const T* Ab = At + (Bo + (int64_t)WAVE * w) * NP2 + (int64_t)h * NI * NP * WAVE + lane;
+    for (int g = 1; g < NF; ++g) {
+      cv = w == g ? cw[g] : cv;
+      kd = w == g ? kw[g] : kd;
+    }
+    const int64_t cb = (int64_t)cv * NP;
+    const bool row = kd == NF;
+    T xo[NI], xs[NFN], xol[LO ? NI : 1], xsl[LO ? NFN : 1];
 #pragma unroll
-    for (int t = 0; t < NI; ++t)
+    for (int t = 0; t < NI; ++t) {
+      xo[t] = x[cb + h * NI + t];
+      if constexpr (LO) xol[t] = xl[cb + h * NI + t];
+    }
 #pragma unroll
-      for (int j = 0; j < NP; ++j) acc[t] -= Ab[(t * NP + j) * WAVE] * xv[j];
+    for (int k = 0; k < NFN; ++k) {
+      const int64_t a = cb + facet_node_at<NP, NF>(kd, k);
+      xs[k] = row ? T(0) : x[a];
+      if constexpr (LO) xsl[k] = row ? T(0) : xl[a];
+    }
+    Acc<T, COMP> sw[NFN];
+    const T* V = Ac + ((s * NF + w) * NPF + (int64_t)h * NI * NFN) * WAVE + lane;
+#pragma unroll
+    for (int t = 0; t < NI; ++t) {
+      const T xr = row ? xo[t] : T(0);
+      const T xrl = LO && row ? xol[LO ? t : 0] : T(0);
+#pragma unroll
+      for (int k = 0; k < NFN; ++k) {
+        const T v = sign * ld<T, NT>(V + (t * NFN + k) * WAVE);
+        acc[t].add(v, xs[k]);
+        sw[k].add(v, xr);
+        if constexpr (LO) {
+          acc[t].addlo(v, xsl[k]);
+          sw[k].addlo(v, xrl);
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < NF; ++g)
+      if (w == g)
+#pragma unroll
+        for (int k = 0; k < NFN; ++k) sc[FT.v[g][k]].merge(sw[k]);
   }
 }
 
-// sweep on level 0; with DOT, also the slice's partial sum of (xout, dv) in
-// FP64 (part[slice]), which the outer loop needs of the preconditioned residual
-template <typename T, int NP, int H, int NF, bool DOT>
-__global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* __restrict__ cols, const T* __restrict__ At,
-                                                     const T* __restrict__ bt, const T* __restrict__ xin, T omega,
-                                                     T* __restrict__ xout, const double* __restrict__ dv,
-                                                     double* __restrict__ part, int rev) {
+// Adds the row-kind partial sums of all wavefronts of the slice to acc (this
+// wavefront's rows), summed in wavefront order through one n_p x 64 LDS buffer
+// (shc: the low-order parts, COMP).  Every thread of the workgroup calls it.
+template <typename T, int NP, int H, bool COMP>
+__device__ __forceinline__ void gather_rows(int lane, int h, bool valid, Acc<T, COMP>* acc, Acc<T, COMP>* sc,
+                                            T* shs, T* shc) {
   constexpr int NI = NP / H;
+  if constexpr (H == 1) {
+#pragma unroll
+    for (int t = 0; t < NI; ++t) acc[t].merge(sc[t]);
+  } else {
+    for (int g = 0; g < H; ++g) {
+      if (h == g && valid) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          Acc<T, COMP> o = sc[i];
+          if (g > 0) {
+            Acc<T, COMP> prev;
+            prev.s = shs[i * WAVE + lane];
+            if constexpr (COMP) prev.set_lo(shc[i * WAVE + lane]);
+            prev.merge(sc[i]);
+            o = prev;
+          }
+          shs[i * WAVE + lane] = o.s;
+          if constexpr (COMP) shc[i * WAVE + lane] = o.lo();
+        }
+      }
+      __syncthreads();
+    }
+    if (valid) {
+#pragma unroll
+      for (int t = 0; t < NI; ++t) {
+        Acc<T, COMP> o;
+        o.s = shs[(h * NI + t) * WAVE + lane];
+        if constexpr (COMP) o.set_lo(shc[(h * NI + t) * WAVE + lane]);
+        acc[t].merge(o);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// every wavefront of the slice gets the whole vector v (NP values; this
+// wavefront holds rows h NI + t in own[t]) through LDS
+template <typename T, int NP, int H>
+__device__ __forceinline__ void share_rows(int lane, int h, bool valid, const T* own, T* all, T* sh) {
+  constexpr int NI = NP / H;
+  if constexpr (H == 1) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) all[i] = own[i];
+  } else {
+    if (valid)
+#pragma unroll
+      for (int t = 0; t < NI; ++t) sh[(h * NI + t) * WAVE + lane] = own[t];
+    __syncthreads();
+    if (valid)
+#pragma unroll
+      for (int i = 0; i < NP; ++i) all[i] = sh[i * WAVE + lane];
+  }
+}
+
+// sweep on level 0: x_out = (1 - omega) x + omega D^{-1} (b - A_off x); with
+// DOT also the slice's partial sum of (x_out, dv) in FP64 (part[slice])
+template <typename T, int NP, int H, int NF, bool DOT>
+__global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* __restrict__ cols,
+                                                     const int8_t* __restrict__ meta, const T* __restrict__ Ac,
+                                                     const T* __restrict__ Dinv, const T* __restrict__ b,
+                                                     const T* __restrict__ xin, T omega, T* __restrict__ xout,
+                                                     const double* __restrict__ dv, double* __restrict__ part, int rev) {
+  constexpr int NP2 = NP * NP, NI = NP / H;
+  __shared__ T sh[H > 1 ? NP * WAVE : 1];
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
   const int64_t sl = slice_order(rev), r = sl * WAVE + lane;
-  double d = 0.0;
-  if (r < n) {
-    T acc[NI];
-    hs_scaled_residual<T, NP, H, NF>(r, lane, h, cols, At, bt, xin, acc);
+  const bool valid = r < n;
+  Acc<T, false> acc[NI], sc[NP];
+  if (valid) {
 #pragma unroll
+    for (int t = 0; t < NI; ++t) acc[t].s = b[r * NP + h * NI + t];
+    off0<T, NP, H, NF, false, false, false>(sl, lane, h, cols, meta, Ac, xin, nullptr, T(-1), acc, sc);
+  }
+  gather_rows<T, NP, H, false>(lane, h, valid, acc, sc, sh, nullptr);
+  T own[NI], sv[NP];
+#pragma unroll
+  for (int t = 0; t < NI; ++t) own[t] = acc[t].value();
+  share_rows<T, NP, H>(lane, h, valid, own, sv, sh);
+  double d = 0.0;
+  if (valid) {
+    const T* D = Dinv + sl * WAVE * NP2 + lane;
+    // FP32 blocks: all of D^{-1}'s loads in flight at once; FP64: two rows
+    constexpr int UF = sizeof(T) == 4 ? NI : 2;
+#pragma unroll UF
     for (int t = 0; t < NI; ++t) {
-      const int64_t k = r * NP + h * NI + t;
-      const T v = xin[k] + omega * acc[t];
+      const int i = h * NI + t;
+      T y = 0;
+#pragma unroll
+      for (int j = 0; j < NP; ++j) y += D[(i * NP + j) * WAVE] * sv[j];
+      const int64_t k = r * NP + i;
+      const T xi = xin[k];
+      const T v = xi + omega * (y - xi);
       xout[k] = v;
       if constexpr (DOT) d += (double)v * dv[k];
     }
   }
   if constexpr (DOT) {
-    __shared__ double sh[H];
-    d = block_sum(d, sh);
+    __shared__ double shd[H];
+    d = block_sum(d, shd);
     if (threadIdx.x == 0) part[sl] = d;
   }
 }
 
-// residual + restriction on level 0: t_e = Lt_e^T (bt - At x)_e
+// residual of level 0 in this wavefront's rows: b - A_rr x - A_off x, then the
+// whole residual vector of the row in res[NP] (every thread calls it)
 template <typename T, int NP, int H, int NF>
-__global__ __launch_bounds__(WAVE * H) void k_restrict0(int64_t n, const int32_t* __restrict__ cols, const T* __restrict__ At,
-                                                        const T* __restrict__ bt, const T* __restrict__ x,
-                                                        const T* __restrict__ Lt, T* __restrict__ t_out, int rev) {
+__device__ __forceinline__ void residual0(int64_t sl, int64_t r, int lane, int h, bool valid,
+                                          const int32_t* __restrict__ cols, const int8_t* __restrict__ meta,
+                                          const T* __restrict__ Ac, const T* __restrict__ Ad,
+                                          const T* __restrict__ b, const T* __restrict__ x, T* sh, T* res) {
   constexpr int NP2 = NP * NP, NI = NP / H;
-  __shared__ T sres[NP][WAVE];
+  Acc<T, false> acc[NI], sc[NP];
+  if (valid) {
+    const T* Dg = Ad + sl * WAVE * NP2 + lane;
+#pragma unroll
+    for (int t = 0; t < NI; ++t) acc[t].s = b[r * NP + h * NI + t];
+#pragma unroll 2
+    for (int j = 0; j < NP; ++j) {
+      const T xj = x[r * NP + j];
+#pragma unroll
+      for (int t = 0; t < NI; ++t) acc[t].add(-__builtin_nontemporal_load(Dg + ((h * NI + t) * NP + j) * WAVE), xj);
+    }
+    off0<T, NP, H, NF, false, false, false>(sl, lane, h, cols, meta, Ac, x, nullptr, T(-1), acc, sc);
+  }
+  gather_rows<T, NP, H, false>(lane, h, valid, acc, sc, sh, nullptr);
+  T own[NI];
+#pragma unroll
+  for (int t = 0; t < NI; ++t) own[t] = acc[t].value();
+  share_rows<T, NP, H>(lane, h, valid, own, res, sh);
+}
+
+// residual + restriction on level 0: t_e = L_e^T (b - A x)_e
+template <typename T, int NP, int H, int NF>
+__global__ __launch_bounds__(WAVE * H) void k_restrict0(int64_t n, const int32_t* __restrict__ cols,
+                                                        const int8_t* __restrict__ meta, const T* __restrict__ Ac,
+                                                        const T* __restrict__ Ad, const T* __restrict__ b,
+                                                        const T* __restrict__ x, const T* __restrict__ Lb,
+                                                        T* __restrict__ t_out, int rev) {
+  constexpr int NP2 = NP * NP, NI = NP / H;
+  __shared__ T sh[H > 1 ? NP * WAVE : 1];
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
   const int64_t sl = slice_order(rev), r = sl * WAVE + lane;
   const bool valid = r < n;
-  if (valid) {
-    T acc[NI];
-    hs_scaled_residual<T, NP, H, NF>(r, lane, h, cols, At, bt, x, acc);
-#pragma unroll
-    for (int t = 0; t < NI; ++t) sres[h * NI + t][lane] = acc[t];
-  }
-  __syncthreads();
+  T res[NP];
+  residual0<T, NP, H, NF>(sl, r, lane, h, valid, cols, meta, Ac, Ad, b, x, sh, res);
   if (!valid) return;
-  const T* Lr = Lt + sl * WAVE * NP2 + lane;
-#pragma unroll
+  const T* Lr = Lb + sl * WAVE * NP2 + lane;
+  constexpr int UF = sizeof(T) == 4 ? NI : 2;
+#pragma unroll UF
   for (int t = 0; t < NI; ++t) {
     const int j = h * NI + t;
     T s = 0;
 #pragma unroll
-    for (int i = 0; i < NP; ++i) s += __builtin_nontemporal_load(Lr + (i * NP + j) * WAVE) * sres[i][lane];
+    for (int i = 0; i < NP; ++i) s += __builtin_nontemporal_load(Lr + (i * NP + j) * WAVE) * res[i];
     t_out[r * NP + j] = s;
   }
 }
 
-// level-0 entry from the FP64 outer residual: bt = D^{-1} (T) r, x = omega bt
+// level-0 entry from the FP64 outer residual: b = (T) r, x = omega D^{-1} b
+// (the first sweep from zero)
 template <typename T, int NP, int H>
 __global__ __launch_bounds__(WAVE * H) void k_entry0(int64_t n, const double* __restrict__ src,
-                                                     const T* __restrict__ Dinv, T omega, T* __restrict__ bt,
+                                                     const T* __restrict__ Dinv, T omega, T* __restrict__ b,
                                                      T* __restrict__ x) {
   constexpr int NP2 = NP * NP, NI = NP / H;
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
@@ -676,15 +957,85 @@ __global__ __launch_bounds__(WAVE * H) void k_entry0(int64_t n, const double* __
   for (int j = 0; j < NP; ++j) v[j] = (T)src[r * NP + j];
   const T* D = Dinv + sl * WAVE * NP2 + lane;
 #pragma unroll
+  for (int t = 0; t < NI; ++t) b[r * NP + h * NI + t] = v[h * NI + t];
+  constexpr int UF = sizeof(T) == 4 ? NI : 2;
+#pragma unroll UF
   for (int t = 0; t < NI; ++t) {
     const int i = h * NI + t;
     T s = 0;
 #pragma unroll
     for (int j = 0; j < NP; ++j) s += __builtin_nontemporal_load(D + (i * NP + j) * WAVE) * v[j];
-    bt[r * NP + i] = s;
     x[r * NP + i] = omega * s;
   }
 }
+
+// setup: the facet-trace form of the off-diagonal level-0 blocks from the
+// dense sliced A_0 (FP64) in precision T, one thread per (slice, slot, value,
+// lane); err = 1 if a dropped entry of the block is not zero
+template <typename T, int NP, int NF>
+__global__ void k_compress0(int64_t n, int64_t ns, const double* __restrict__ A, const int8_t* __restrict__ meta,
+                            T* __restrict__ Ac, int* __restrict__ err) {
+  constexpr FacetTab<NP, NF> FT{};
+  constexpr int NFN = FacetTab<NP, NF>::NFN, NPF = NP * NFN, NP2 = NP * NP;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = (int)(idx % WAVE);
+  int64_t rest = idx / WAVE;
+  const int m = (int)(rest % NPF);
+  rest /= NPF;
+  const int w = (int)(rest % NF);
+  const int64_t s = rest / NF;
+  if (s >= ns) return;
+  const int i = m / NFN, k = m % NFN;
+  const int kd = meta[(s * NF + w) * WAVE + lane];
+  int fr = 0, fc = 0;  // r's facet-w node and c's facet node of index k
+#pragma unroll
+  for (int g = 0; g < NF; ++g) {
+    if (g == w) fr = FT.v[g][k];
+    if (g == kd) fc = FT.v[g][k];
+  }
+  const int a = kd == NF ? fr : i, bb = kd == NF ? i : fc;
+  const double* blk = A + ((s * (NF + 1) + w + 1) * WAVE) * NP2 + lane;
+  if (s * WAVE + lane >= n) {  // rows past the last element: zero blocks
+    Ac[((s * NF + w) * NPF + m) * WAVE + lane] = T(0);
+    return;
+  }
+  Ac[((s * NF + w) * NPF + m) * WAVE + lane] = (T)blk[(a * NP + bb) * WAVE];
+  // check: the thread of value (i, 0) checks row i (column kind) or column i
+  // (row kind) of the block off the kept facet nodes
+  if (k == 0) {
+    const int f = kd == NF ? w : kd;
+    bool bad = false;
+    for (int q = 0; q < NP; ++q) {
+      bool on = false;
+#pragma unroll
+      for (int kk = 0; kk < NFN; ++kk) on = on || q == facet_node_at<NP, NF>(f, kk);
+      const double v = kd == NF ? blk[(q * NP + i) * WAVE] : blk[(i * NP + q) * WAVE];
+      if (!on && v != 0.0) bad = true;
+    }
+    if (bad) *err = 1;
+  }
+}
+
+// setup: the diagonal blocks of the dense sliced A_0 in the per-row layout, in T
+template <typename T, int NP, int NF>
+__global__ void k_diag0(int64_t ns, const double* __restrict__ A, T* __restrict__ Ad) {
+  constexpr int NP2 = NP * NP;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = (int)(idx % WAVE);
+  const int64_t rest = idx / WAVE;
+  const int ij = (int)(rest % NP2);
+  const int64_t s = rest / NP2;
+  if (s >= ns) return;
+  Ad[(s * NP2 + ij) * WAVE + lane] = (T)A[(s * (NF + 1) * NP2 + ij) * WAVE + lane];
+}
+
+// ------------------------------------------------------------------
+// Coarse-level V-cycle kernels on D^{-1}-prescaled operators.  The damped
+// block-Jacobi sweep x <- x + omega D^{-1} (b - A x) is evaluated as
+//     x <- (1 - omega) x + omega (bt - At_off x),   bt = D^{-1} b,  At = D^{-1} A,
+// where the diagonal block of At is the identity and is not stored, and the
+// restricted residual L_e^T (b - A x)_e as Lt_e^T (bt - At x)_e with
+// Lt_e = D_e^T L_e.  These sweeps read neither D^{-1} nor the diagonal block.
 
 // coarse-level entry: b_I = sum over children of t_e; bt = D^{-1} b, x = omega bt
 // (no D^{-1}: the coarsest level, bt receives b itself)
@@ -858,51 +1209,26 @@ __global__ void k_galerkin_p(int64_t ns, int W, const double* __restrict__ A0, c
   A1[slot * WAVE * N1 + (int64_t)kl * WAVE + lane] = acc;
 }
 
-// Lt_e = D_e^T T (n_p0 x n_p1) per row, per-row layout with blocks of n_p0 n_p1
-template <typename T, int NP0, int NP1>
-__global__ void k_scale_L_rect(int64_t n, const int64_t* __restrict__ sblk, const double* __restrict__ A,
-                               const double* __restrict__ Tm, T* __restrict__ Lt) {
-  constexpr int N0 = NP0 * NP0, NR = NP0 * NP1;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = (int)(idx % WAVE);
-  const int64_t rest = idx / WAVE;
-  const int ij = (int)(rest % NR);
-  const int64_t s = rest / NR;
-  const int64_t r = s * WAVE + lane;
-  if (r >= n) return;
-  const int i = ij / NP1, j = ij % NP1;
-  const int64_t B = sblk[s];
-  double acc = 0.0;
-#pragma unroll
-  for (int m = 0; m < NP0; ++m) acc += A[blk_off(B, 0, N0, m * NP0 + i, lane)] * Tm[m * NP1 + j];
-  Lt[s * WAVE * NR + (int64_t)ij * WAVE + lane] = (T)acc;
-}
-
 // level-0 residual + restriction to the lower-degree space, FP64 output for
-// the lower hierarchy: t_r = Lt_r^T (bt - At x)_r, Lt_r = D_r^T T
+// the lower hierarchy: t_r = T^T (b - A x)_r with the constant embedding T
+// (n_p0 x n_p1, row-major)
 template <typename T, int NP0, int NP1, int H, int NF>
 __global__ __launch_bounds__(WAVE * H) void k_restrict0_rect(int64_t n, const int32_t* __restrict__ cols,
-                                                             const T* __restrict__ At, const T* __restrict__ bt,
-                                                             const T* __restrict__ x, const T* __restrict__ Lt,
+                                                             const int8_t* __restrict__ meta, const T* __restrict__ Ac,
+                                                             const T* __restrict__ Ad, const T* __restrict__ b,
+                                                             const T* __restrict__ x, const T* __restrict__ Tm,
                                                              double* __restrict__ t_out, int rev) {
-  constexpr int NI = NP0 / H, NR = NP0 * NP1;
-  __shared__ T sres[NP0][WAVE];
+  __shared__ T sh[H > 1 ? NP0 * WAVE : 1];
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
   const int64_t sl = slice_order(rev), r = sl * WAVE + lane;
   const bool valid = r < n;
-  if (valid) {
-    T acc[NI];
-    hs_scaled_residual<T, NP0, H, NF>(r, lane, h, cols, At, bt, x, acc);
-#pragma unroll
-    for (int t = 0; t < NI; ++t) sres[h * NI + t][lane] = acc[t];
-  }
-  __syncthreads();
+  T res[NP0];
+  residual0<T, NP0, H, NF>(sl, r, lane, h, valid, cols, meta, Ac, Ad, b, x, sh, res);
   if (!valid) return;
-  const T* Lr = Lt + sl * WAVE * NR + lane;
   for (int j = h; j < NP1; j += H) {
     T s = 0;
 #pragma unroll
-    for (int i = 0; i < NP0; ++i) s += __builtin_nontemporal_load(Lr + (i * NP1 + j) * WAVE) * sres[i][lane];
+    for (int i = 0; i < NP0; ++i) s += Tm[i * NP1 + j] * res[i];
     t_out[r * NP1 + j] = (double)s;
   }
 }
@@ -926,31 +1252,6 @@ __global__ __launch_bounds__(TPB) void k_prolong_rect(int64_t n, const T* __rest
 }
 
 // ----------------------------------------------------------- prescaling (setup)
-// At_off(r, w) = D_r^{-1} A(r, w), w >= 1, into the level-0 sliced layout
-// without slot 0; one thread per output entry (slice, slot, i, j, lane),
-// grid over ns x (Wmax - 1) x n_p^2 x 64
-template <typename T, int NP>
-__global__ void k_scale_sliced(int64_t n, int Wmax, const int64_t* __restrict__ sblk, const double* __restrict__ A,
-                               const double* __restrict__ Dinv, T* __restrict__ At) {
-  constexpr int NP2 = NP * NP;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = (int)(idx % WAVE);
-  int64_t rest = idx / WAVE;
-  const int ij = (int)(rest % NP2);
-  rest /= NP2;
-  const int w = (int)(rest % (Wmax - 1)) + 1;
-  const int64_t s = rest / (Wmax - 1);
-  if (s * WAVE + lane >= n) return;
-  const int64_t B = sblk[s], Bo = B - WAVE * s;
-  if (w >= (int)((sblk[s + 1] - B) / WAVE)) return;
-  const int i = ij / NP, j = ij % NP;
-  const double* D = Dinv + s * WAVE * NP2 + lane;
-  double acc = 0.0;
-#pragma unroll
-  for (int m = 0; m < NP; ++m) acc += D[(i * NP + m) * WAVE] * A[blk_off(B, w, NP2, m * NP + j, lane)];
-  At[(Bo + (int64_t)WAVE * (w - 1)) * NP2 + (int64_t)ij * WAVE + lane] = (T)acc;
-}
-
 // coarse strips: off-diagonal blocks of D^{-1} A, component-major, unpadded;
 // one thread per (stored block b, i, j), b over the level's row-major blocks
 template <typename T, int NP>
@@ -1112,34 +1413,6 @@ __global__ __launch_bounds__(RED_T) void k_reduce(const double* __restrict__ par
 }
 
 
-// ------------------------------------------------------------------
-// Error-free transformations (Knuth TwoSum; FMA TwoProduct) for the outer
-// loop.  The relative rounding noise of a plain FP64 product A x is about
-// eps * || |A| |x| || / || A x ||, which grows like h^{-2} for this operator
-// (about 4e-10 on a 2D p=3 mesh with h = 1/316): above a 1e-10 target.  The
-// outer q = A p and the true residual are therefore accumulated as
-// double-double sums (Ogita, Rump & Oishi, "Accurate sum and dot product",
-// 2005, algorithm Dot2) and the iterate is kept as x_hi + x_lo.  These
-// kernels are bound by HBM bytes, so the extra FP64 operations are free.
-// FMA contraction must stay off in these routines: fusing the rounded product
-// p = a x into the following sum would make the error terms double-count.
-__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
-#pragma clang fp contract(off)
-  s = (a + b);
-  const double bb = (s - a);
-  e = (a - (s - bb)) + (b - bb);
-}
-__device__ __forceinline__ void dot2_acc(double a, double x, double& s, double& c) {
-#pragma clang fp contract(off)
-  const double p = (a * x);
-  const double ep = __builtin_fma(a, x, -p);
-  double t;
-  two_sum(s, p, s, t);
-  c = (c + (t + ep));
-}
-
-
-
 // x_hi + x_lo += alpha p (double-double); r -= alpha q; partial ||r||^2
 __global__ __launch_bounds__(TPB) void k_update_xr2(int64_t m, const double* __restrict__ p,
                                                     const double* __restrict__ q, double* __restrict__ xh,
@@ -1226,51 +1499,41 @@ __global__ void k_update_x_multi(int64_t m, int nk, const double* __restrict__ Z
   xl[i] = (lo - (nh - hi));
 }
 
-// Component-split outer kernels on A_0 (H wavefronts per slice, the n_f + 1
-// slots unrolled as in the level-0 sweep): q = A p with partial sums of
-// (p, q), (p, r) (DOTS); COMP selects the compensated (Dot2) accumulation.
-// One partial per slice.
+// Outer FP64 product q = A_0 p on the facet-trace form (diagonal blocks dense,
+// read from the sliced A_0 at slot 0) with the partial sums of (p, q) and
+// (p, r) per slice (DOTS); COMP accumulates in Dot2.  All operator loads are
+// non-temporal (read once per outer iteration).
 template <int NP, int H, int NF, bool COMP, bool DOTS = true>
-__global__ __launch_bounds__(WAVE * H) void k_spmv_dots_hs(int64_t n, const int32_t* __restrict__ cols,
-                                                           const double* __restrict__ A, const double* __restrict__ p,
-                                                           const double* __restrict__ rr, double* __restrict__ q,
-                                                           double* __restrict__ part) {
+__global__ __launch_bounds__(WAVE * H) void k_spmv0(int64_t n, const int32_t* __restrict__ cols,
+                                                    const int8_t* __restrict__ meta, const double* __restrict__ A,
+                                                    const double* __restrict__ Ac, const double* __restrict__ p,
+                                                    const double* __restrict__ rr, double* __restrict__ q,
+                                                    double* __restrict__ part) {
 #pragma clang fp contract(off)
   constexpr int NP2 = NP * NP, NI = NP / H;
+  __shared__ double shs[H > 1 ? NP * WAVE : 1], shc[H > 1 && COMP ? NP * WAVE : 1];
   __shared__ double sh[H];
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
   const int64_t sl = xcd_slice(), r = sl * WAVE + lane;
-  double pq = 0.0, pr = 0.0;
-  if (r < n) {
-    constexpr int W = NF + 1;
-    const int64_t B = (r / WAVE) * WAVE * W;
-    int32_t cw[W];
+  const bool valid = r < n;
+  Acc<double, COMP> acc[NI], sc[NP];
+  if (valid) {
+    const double* Dg = A + (sl * (NF + 1) * NP2) * WAVE + lane;
+#pragma unroll 2
+    for (int j = 0; j < NP; ++j) {
+      const double xj = p[r * NP + j];
 #pragma unroll
-    for (int w = 0; w < W; ++w) cw[w] = cols[B + (int64_t)WAVE * w + lane];
-    double s[NI], c[NI];
-#pragma unroll
-    for (int t = 0; t < NI; ++t) s[t] = c[t] = 0.0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const int32_t col = cw[w];
-      double xv[NP];
-#pragma unroll
-      for (int j = 0; j < NP; ++j) xv[j] = p[(int64_t)col * NP + j];
-      const double* Ab = A + (B + (int64_t)WAVE * w) * NP2 + (int64_t)h * NI * NP * WAVE + lane;
-#pragma unroll
-      for (int t = 0; t < NI; ++t)
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-          if constexpr (COMP)
-            dot2_acc(__builtin_nontemporal_load(Ab + (t * NP + j) * WAVE), xv[j], s[t], c[t]);
-          else
-            s[t] = __builtin_fma(__builtin_nontemporal_load(Ab + (t * NP + j) * WAVE), xv[j], s[t]);
-        }
+      for (int t = 0; t < NI; ++t) acc[t].add(__builtin_nontemporal_load(Dg + ((h * NI + t) * NP + j) * WAVE), xj);
     }
+    off0<double, NP, H, NF, COMP, false, true>(sl, lane, h, cols, meta, Ac, p, nullptr, 1.0, acc, sc);
+  }
+  gather_rows<double, NP, H, COMP>(lane, h, valid, acc, sc, shs, shc);
+  double pq = 0.0, pr = 0.0;
+  if (valid) {
 #pragma unroll
     for (int t = 0; t < NI; ++t) {
       const int i = h * NI + t;
-      const double qi = COMP ? (s[t] + c[t]) : s[t];
+      const double qi = acc[t].value();
       q[r * NP + i] = qi;
       if constexpr (DOTS) {
         const double pi = p[r * NP + i];
@@ -1287,53 +1550,44 @@ __global__ __launch_bounds__(WAVE * H) void k_spmv_dots_hs(int64_t n, const int3
   }
 }
 
-// true residual rt = b - A (xh + xl), compensated, component-split; partial ||rt||^2 per slice
+// true residual rt = b - A (xh + xl) on the facet-trace form, compensated;
+// partial ||rt||^2 per slice
 template <int NP, int H, int NF>
-__global__ __launch_bounds__(WAVE * H) void k_residual2_hs(int64_t n, const int32_t* __restrict__ cols,
-                                                           const double* __restrict__ A, const double* __restrict__ b,
-                                                           const double* __restrict__ xh,
-                                                           const double* __restrict__ xl, double* __restrict__ rt,
-                                                           double* __restrict__ part) {
+__global__ __launch_bounds__(WAVE * H) void k_residual0(int64_t n, const int32_t* __restrict__ cols,
+                                                        const int8_t* __restrict__ meta, const double* __restrict__ A,
+                                                        const double* __restrict__ Ac, const double* __restrict__ b,
+                                                        const double* __restrict__ xh, const double* __restrict__ xl,
+                                                        double* __restrict__ rt, double* __restrict__ part) {
 #pragma clang fp contract(off)
   constexpr int NP2 = NP * NP, NI = NP / H;
+  __shared__ double shs[H > 1 ? NP * WAVE : 1], shc[H > 1 ? NP * WAVE : 1];
   __shared__ double sh[H];
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
   const int64_t sl = xcd_slice(), r = sl * WAVE + lane;
-  double rr = 0.0;
-  if (r < n) {
-    constexpr int W = NF + 1;
-    const int64_t B = (r / WAVE) * WAVE * W;
-    int32_t cw[W];
+  const bool valid = r < n;
+  Acc<double, true> acc[NI], sc[NP];
+  if (valid) {
+    const double* Dg = A + (sl * (NF + 1) * NP2) * WAVE + lane;
 #pragma unroll
-    for (int w = 0; w < W; ++w) cw[w] = cols[B + (int64_t)WAVE * w + lane];
-    double s[NI], c[NI];
+    for (int t = 0; t < NI; ++t) acc[t].s = b[r * NP + h * NI + t];
+#pragma unroll 2
+    for (int j = 0; j < NP; ++j) {
+      const double hj = xh[r * NP + j], lj = xl[r * NP + j];
 #pragma unroll
-    for (int t = 0; t < NI; ++t) {
-      s[t] = b[r * NP + h * NI + t];
-      c[t] = 0.0;
-    }
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const int32_t col = cw[w];
-      double hv[NP], lv[NP];
-#pragma unroll
-      for (int j = 0; j < NP; ++j) {
-        hv[j] = xh[(int64_t)col * NP + j];
-        lv[j] = xl[(int64_t)col * NP + j];
+      for (int t = 0; t < NI; ++t) {
+        const double a = -__builtin_nontemporal_load(Dg + ((h * NI + t) * NP + j) * WAVE);
+        acc[t].add(a, hj);
+        acc[t].addlo(a, lj);
       }
-      const double* Ab = A + (B + (int64_t)WAVE * w) * NP2 + (int64_t)h * NI * NP * WAVE + lane;
-#pragma unroll
-      for (int t = 0; t < NI; ++t)
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-          const double a = __builtin_nontemporal_load(Ab + (t * NP + j) * WAVE);
-          dot2_acc(-a, hv[j], s[t], c[t]);
-          c[t] = __builtin_fma(-a, lv[j], c[t]);
-        }
     }
+    off0<double, NP, H, NF, true, true, true>(sl, lane, h, cols, meta, Ac, xh, xl, -1.0, acc, sc);
+  }
+  gather_rows<double, NP, H, true>(lane, h, valid, acc, sc, shs, shc);
+  double rr = 0.0;
+  if (valid) {
 #pragma unroll
     for (int t = 0; t < NI; ++t) {
-      const double v = s[t] + c[t];
+      const double v = acc[t].value();
       rt[r * NP + h * NI + t] = v;
       rr = __builtin_fma(v, v, rr);
     }

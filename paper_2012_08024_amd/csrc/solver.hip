@@ -104,6 +104,11 @@ constexpr bool l0_pair(int np, int nf) {
 
 namespace {
 
+// facet nodes of the degree-p simplex: n_fn of the facet-trace form
+inline int fnodes(int np, int nf) {
+  return nf == 3 ? (np == 3 ? 2 : np == 6 ? 3 : 4) : (np == 4 ? 3 : np == 10 ? 6 : 10);
+}
+
 struct DLevel {
   int64_t n = 0, ns = 0, slots = 0, nnzb = 0;
   int32_t* cols = nullptr;
@@ -113,9 +118,11 @@ struct DLevel {
   double* D64 = nullptr;  // D_l^{-1}, FP64, per-row layout
   double* L64 = nullptr;  // L_e, FP64, per-row layout
   // V-cycle operators in the multigrid precision T (FP64 mode: Dm = D64, Lm = L64)
-  void* At = nullptr;  // level 0: off-diagonal blocks of D^{-1} A, sliced without slot 0
+  void* Ac = nullptr;  // level 0: off-diagonal blocks in facet-trace form (FP64 mode: the outer A0c)
+  void* Ad = nullptr;  // level 0: diagonal blocks, per-row layout
+  int8_t* meta = nullptr;  // level 0: facet-trace kind of each off-diagonal slot
   void* Dm = nullptr;  // D^{-1}
-  void* Lt = nullptr;  // D^T L_e (D the diagonal block of A)
+  void* Lt = nullptr;  // D^T L_e (D the diagonal block of A), levels 1 .. L-1
   void* Lm = nullptr;  // L_e
   int32_t* parent = nullptr;
   int32_t* child_start = nullptr;
@@ -187,6 +194,7 @@ struct cdgmg_handle {
   // level 0
   double *UA = nullptr, *UH = nullptr, *M = nullptr, *kappa = nullptr;
   double* UC = nullptr;    // upwind convection blocks (beta != 0), operator layout
+  double* A0c = nullptr;   // off-diagonal blocks of A_0 in facet-trace form, FP64 (outer loop)
   // hp front end: the lower-degree hierarchy below level 0 (owned), the nodal
   // embedding T [np][np1] in FP64 and in the multigrid precision
   cdgmg_handle* inner = nullptr;
@@ -452,11 +460,8 @@ int upload_problem(cdgmg_handle* h) {
     RETURN_IF(dzero(h, D.A64, (size_t)D.slots * np2 * sizeof(double)));
     const size_t rowblk = (size_t)D.ns * SLICE * np2;
     if (l == 0 && h->inner) {  // hp front end: level 0 restricts to the lower degree
-      const size_t rect = (size_t)D.ns * SLICE * np * h->np1;
       RETURN_IF(dalloc(h, &D.D64, rowblk));
       void* tmp;
-      RETURN_IF(dalloc(h, (char**)&tmp, rect * (fp32 ? sizeof(float) : sizeof(double))));
-      D.Lt = tmp;
       if (fp32) {
         RETURN_IF(dalloc(h, (char**)&tmp, rowblk * sizeof(float)));
         D.Dm = tmp;
@@ -474,23 +479,50 @@ int upload_problem(cdgmg_handle* h) {
         D.Lm = tmp;
         RETURN_IF(dalloc(h, &tmp, rowblk));
         D.Dm = tmp;
-        RETURN_IF(dalloc(h, &tmp, rowblk));
-        D.Lt = tmp;
+        if (l > 0) {
+          RETURN_IF(dalloc(h, &tmp, rowblk));
+          D.Lt = tmp;
+        }
       } else {
         D.Lm = D.L64;
         D.Dm = D.D64;
-        double* tmp;
-        RETURN_IF(dalloc(h, &tmp, rowblk));
-        D.Lt = tmp;
+        if (l > 0) {
+          double* tmp;
+          RETURN_IF(dalloc(h, &tmp, rowblk));
+          D.Lt = tmp;
+        }
       }
       RETURN_IF(upload(h, &D.parent, H.parent));
     }
-    if (l == 0 && (P.L > 0 || h->inner)) {
-      const size_t na = (size_t)(D.slots - SLICE * D.ns) * np2;
-      void* tmp;
-      RETURN_IF(dalloc(h, (char**)&tmp, na * (fp32 ? sizeof(float) : sizeof(double))));
-      RETURN_IF(dzero(h, tmp, na * (fp32 ? sizeof(float) : sizeof(double))));
-      D.At = tmp;
+    if (l == 0) {
+      // facet-trace form of the off-diagonal blocks: the kind of each slot
+      // (the neighbour's local facet when this row hosts it, else n_f)
+      const int nf = P.nf, W = P.nf + 1;
+      std::vector<int8_t> meta((size_t)D.ns * nf * SLICE, 0);
+      for (int64_t r = 0; r < D.n; ++r)
+        for (int w = 0; w < nf; ++w) {
+          const int hf = P.hostflag[r * W + w + 1];
+          meta[((r / SLICE) * nf + w) * SLICE + r % SLICE] =
+              (int8_t)(hf == 1 ? P.revslot[r * W + w + 1] - 1 : hf == 0 ? nf : 0);
+        }
+      RETURN_IF(upload(h, &D.meta, meta));
+      const size_t nc = (size_t)D.ns * SLICE * nf * np * fnodes(np, nf);
+      const bool smooth = P.L > 0 || h->inner;
+      if (!h->given_A0 || (smooth && !fp32)) RETURN_IF(dalloc(h, &h->A0c, nc));
+      if (smooth) {
+        if (fp32) {
+          float* tmp;
+          RETURN_IF(dalloc(h, &tmp, nc));
+          D.Ac = tmp;
+          RETURN_IF(dalloc(h, &tmp, rowblk));
+          D.Ad = tmp;
+        } else {
+          D.Ac = h->A0c;
+          double* tmp;
+          RETURN_IF(dalloc(h, &tmp, rowblk));
+          D.Ad = tmp;
+        }
+      }
     }
     if (l >= 1 && l < P.L) {
       std::vector<int32_t> wc(H.nnzb);
@@ -552,6 +584,7 @@ int upload_problem(cdgmg_handle* h) {
   if (!P.UC.empty()) {
     RETURN_IF(upload(h, &h->UC, to_sliced(P.UC, P.lv[0], h->W0, np2)));
     RETURN_IF(dalloc(h, &h->Atmp, (size_t)h->lv[0].slots * np2));
+    RETURN_IF(dzero(h, h->Atmp, (size_t)h->lv[0].slots * np2 * sizeof(double)));  // padding rows stay zero
     std::vector<double>().swap(P.UC);
   }
   RETURN_IF(dalloc(h, &h->kappa, P.N0));
@@ -615,21 +648,46 @@ int upload_problem(cdgmg_handle* h) {
   return CDGMG_OK;
 }
 
-// hp front end, level 0 at degree p: D^{-1}, the next p-level's operator
-// T^T A_0 T, the whole lower-degree hierarchy, and the prescaled level-0 operators
-// (D^{-1} A_0 off-diagonal, D^{-1}, D^T T)
-template <typename T, int NP0, int NP1>
-void prescale_hp(cdgmg_handle* h) {
-  constexpr int NP2 = NP0 * NP0;
+#define NF_DISPATCH(nfv, ...)                                                   \
+  switch (nfv) {                                                                \
+    case 3: { constexpr int NF = 3; if constexpr (l0_pair(NP, NF)) { __VA_ARGS__; } } break; \
+    case 4: { constexpr int NF = 4; if constexpr (l0_pair(NP, NF)) { __VA_ARGS__; } } break; \
+    default: break;                                                             \
+  }
+
+// the off-diagonal blocks of the sliced A_0 (FP64) in facet-trace form, in T;
+// the dropped entries are checked to be zero (err)
+template <typename T, int NP>
+void compress0(cdgmg_handle* h, T* out) {
   DLevel& D = h->lv[0];
-  launch(h, -1, k_scale_sliced<T, NP0>, dim3(grid_for(D.ns * (h->W0 - 1) * NP2 * WAVE)), dim3(TPB), D.n, h->W0,
-         (const int64_t*)D.sblk, (const double*)D.A64, (const double*)D.D64, (T*)D.At);
-  launch(h, -1, k_scale_L_rect<T, NP0, NP1>, dim3(grid_for(D.ns * NP0 * NP1 * WAVE)), dim3(TPB), D.n,
-         (const int64_t*)D.sblk, (const double*)D.A64, (const double*)h->Tp64, (T*)D.Lt);
+  NF_DISPATCH(h->P.nf, {
+    constexpr int NPF = NP * FacetTab<NP, NF>::NFN;
+    launch(h, -1, k_compress0<T, NP, NF>, dim3(grid_for(D.ns * NF * NPF * WAVE)), dim3(TPB), D.n, D.ns,
+           (const double*)D.A64, (const int8_t*)D.meta, out, h->err);
+  });
+}
+
+// level 0 of the V-cycle in precision T: off-diagonal blocks in facet-trace
+// form (in FP64 mode the outer loop's copy), diagonal blocks, D^{-1}
+template <typename T, int NP>
+void level0_operators(cdgmg_handle* h) {
+  constexpr int NP2 = NP * NP;
+  DLevel& D = h->lv[0];
+  if ((void*)D.Ac != (void*)h->A0c) compress0<T, NP>(h, (T*)D.Ac);
+  NF_DISPATCH(h->P.nf, launch(h, -1, k_diag0<T, NP, NF>, dim3(grid_for(D.ns * NP2 * WAVE)), dim3(TPB), D.ns,
+                              (const double*)D.A64, (T*)D.Ad));
   if ((void*)D.Dm != (void*)D.D64) {
     const int64_t nb = D.ns * SLICE * NP2;
     launch(h, -1, k_cast<double, T>, dim3(grid_for(nb)), dim3(TPB), nb, (const double*)D.D64, (T*)D.Dm);
   }
+}
+
+// hp front end, level 0 at degree p: D^{-1}, the next p-level's operator
+// T^T A_0 T, the whole lower-degree hierarchy, and the level-0 V-cycle
+// operators (the restriction uses the constant embedding T)
+template <typename T, int NP0, int NP1>
+void prescale_hp(cdgmg_handle* h) {
+  level0_operators<T, NP0>(h);
 }
 
 int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed);
@@ -649,6 +707,7 @@ int build_hp(cdgmg_handle* h) {
   } else {
     HP_DISPATCH(h->np, h->np1, prescale_hp<double, NP0, NP1>(h));
   }
+  RETURN_IF(check_err(h, CDGMG_ERR_MESH, "setup: a level-0 off-diagonal block is not in facet-trace form"));
   HIPCHK(hipGetLastError());
   return CDGMG_OK;
 }
@@ -659,13 +718,11 @@ void prescale(cdgmg_handle* h) {
   for (int l = 0; l < h->L; ++l) {
     DLevel& D = h->lv[l];
     if (l == 0) {
-      const int W0 = h->W0;
-      launch(h, -1, k_scale_sliced<T, NP>, dim3(grid_for(D.ns * (W0 - 1) * NP2 * WAVE)), dim3(TPB), D.n, W0,
-             (const int64_t*)D.sblk, (const double*)D.A64, (const double*)D.D64, (T*)D.At);
-    } else {
-      launch(h, -1, k_scale_wpr<T, NP>, dim3(grid_for(D.nnzb * NP2)), dim3(TPB), D.nnzb, (const int32_t*)D.blk_row,
-             (const int64_t*)D.sblk, (const int64_t*)D.woff, (const double*)D.A64, (const double*)D.D64, (T*)D.R);
+      level0_operators<T, NP>(h);
+      continue;
     }
+    launch(h, -1, k_scale_wpr<T, NP>, dim3(grid_for(D.nnzb * NP2)), dim3(TPB), D.nnzb, (const int32_t*)D.blk_row,
+           (const int64_t*)D.sblk, (const int64_t*)D.woff, (const double*)D.A64, (const double*)D.D64, (T*)D.R);
     launch(h, -1, k_scale_L<T, NP>, dim3(grid_for(D.ns * NP2 * WAVE)), dim3(TPB), D.n, (const int64_t*)D.sblk,
            (const double*)D.A64, (const double*)D.L64, (T*)D.Lt);
     if ((void*)D.Dm != (void*)D.D64) {
@@ -692,7 +749,6 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed) {
                            (const int32_t*)l0.cols, (const int64_t*)l0.sblk, (const double*)h->UA,
                            (const double*)h->UH, (const int8_t*)h->hostflag, (const int8_t*)h->revslot,
                            (const double*)h->kappa, (const double*)h->UC, l0.A64));
-  if (h->inner) return build_hp(h);
   if (transposed) {
     NP_DISPATCH(np, launch(h, -1, k_transpose_A0<NP>, dim3(grid_for(h->N0)), dim3(TPB), h->N0, h->W0,
                            (const int64_t*)l0.sblk, (const int32_t*)l0.cols, (const int8_t*)h->revslot,
@@ -701,6 +757,11 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed) {
                           h->stream));
   }
   h->transposed = transposed;
+  if (h->A0c) {
+    NP_DISPATCH(np, compress0<double, NP>(h, h->A0c));
+    RETURN_IF(check_err(h, CDGMG_ERR_MESH, "setup: a level-0 off-diagonal block is not in facet-trace form"));
+  }
+  if (h->inner) return build_hp(h);
   const bool flux = h->P.flux;
   // the Galerkin hierarchy of the symmetric Poisson operator is SPD: its
   // pivots must be positive; otherwise they must be nonzero
@@ -744,6 +805,7 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed) {
   } else {
     NP_DISPATCH(np, prescale<double, NP>(h));
   }
+  RETURN_IF(check_err(h, CDGMG_ERR_MESH, "setup: a level-0 off-diagonal block is not in facet-trace form"));
   // coarsest: dense scatter + Gauss-Jordan inverse (ping-pong)
   DLevel& cl = h->lv[h->L];
   const int64_t nd = h->nd, ld = h->ld;
@@ -794,12 +856,13 @@ void smooth_sweeps(cdgmg_handle* h, int l, int count, T** x, T** xb, const doubl
       const int rev = h->at_pass++ & 1;
       if (dot) {
         L0_DISPATCH(h, launch(h, cls, k_sweep0<T, NP, H, NF, true>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
-                              (const int32_t*)d.cols, (const T*)d.At, (const T*)d.b, (const T*)*x, omega, *xb, dv,
-                              h->part, rev));
+                              (const int32_t*)d.cols, (const int8_t*)d.meta, (const T*)d.Ac, (const T*)d.Dm,
+                              (const T*)d.b, (const T*)*x, omega, *xb, dv, h->part, rev));
       } else {
         L0_DISPATCH(h, launch(h, cls, k_sweep0<T, NP, H, NF, false>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
-                              (const int32_t*)d.cols, (const T*)d.At, (const T*)d.b, (const T*)*x, omega, *xb,
-                              (const double*)nullptr, (double*)nullptr, rev));
+                              (const int32_t*)d.cols, (const int8_t*)d.meta, (const T*)d.Ac, (const T*)d.Dm,
+                              (const T*)d.b, (const T*)*x, omega, *xb, (const double*)nullptr, (double*)nullptr,
+                              rev));
       }
     } else {
       G_DISPATCH(d.grp_s, launch(h, cls, k_sweep_grp<T, NP, G>, dim3(grid_for(d.n * G)), dim3(TPB), d.n,
@@ -844,8 +907,8 @@ T* vcycle_hp(cdgmg_handle* h, const double* r64, const double* dv, int* nparts, 
   const int rev = h->at_pass++ & 1;
   HP_DISPATCH(NP, h->np1, L0_DISPATCH(h, launch(h, CDGMG_K_RESTRICT, k_restrict0_rect<T, NP0, NP1, H, NF>,
                                                 dim3((unsigned)d.ns), dim3(WAVE * H), d.n, (const int32_t*)d.cols,
-                                                (const T*)d.At, (const T*)d.b, (const T*)x, (const T*)d.Lt,
-                                                in->t1, rev)));
+                                                (const int8_t*)d.meta, (const T*)d.Ac, (const T*)d.Ad,
+                                                (const T*)d.b, (const T*)x, (const T*)h->Tpm, in->t1, rev)));
   void* zin = vcycle(in, in->t1, nullptr, nullptr);
   HP_DISPATCH(NP, h->np1, launch(h, CDGMG_K_PROLONG, k_prolong_rect<T, NP0, NP1>, dim3(grid_for(d.n)), dim3(TPB),
                                  d.n, (const T*)h->Tpm, (const T*)zin, x));
@@ -899,8 +962,8 @@ T* vcycle_t(cdgmg_handle* h, const double* r64, const double* dv, int* nparts) {
     if (l == 0) {
       const int rev = h->at_pass++ & 1;
       L0_DISPATCH(h, launch(h, CDGMG_K_RESTRICT, k_restrict0<T, NP, H, NF>, dim3((unsigned)d.ns), dim3(WAVE * H),
-                            d.n, (const int32_t*)d.cols, (const T*)d.At, (const T*)d.b, (const T*)xs[0],
-                            (const T*)d.Lt, (T*)d.t, rev));
+                            d.n, (const int32_t*)d.cols, (const int8_t*)d.meta, (const T*)d.Ac, (const T*)d.Ad,
+                            (const T*)d.b, (const T*)xs[0], (const T*)d.Lm, (T*)d.t, rev));
     } else {
       G_DISPATCH(d.grp_r, launch(h, CDGMG_K_RESTRICT, k_restrict_grp<T, NP, G>, dim3(grid_for(d.n * G)), dim3(TPB),
                              d.n, (const int32_t*)d.wcols, (const int64_t*)d.woff, (const T*)d.R, (const T*)d.b,
@@ -968,10 +1031,10 @@ int read_scalar(cdgmg_handle* h, int slot, double* out) {
 // recursive residual is replaced by it); ||r||^2 lands in scal[SC_TMP]
 void enqueue_true_residual(cdgmg_handle* h) {
   DLevel& d = h->lv[0];
-  NP_DISPATCH(h->np, L0_DISPATCH(h, launch(h, CDGMG_K_VECTOR, k_residual2_hs<NP, H, NF>, dim3((unsigned)d.ns),
-                                            dim3(WAVE * H), d.n, (const int32_t*)d.cols, (const double*)d.A64,
-                                            (const double*)h->b, (const double*)h->x, (const double*)h->xl, h->r,
-                                            h->part)));
+  NP_DISPATCH(h->np, L0_DISPATCH(h, launch(h, CDGMG_K_VECTOR, k_residual0<NP, H, NF>, dim3((unsigned)d.ns),
+                                            dim3(WAVE * H), d.n, (const int32_t*)d.cols, (const int8_t*)d.meta,
+                                            (const double*)d.A64, (const double*)h->A0c, (const double*)h->b,
+                                            (const double*)h->x, (const double*)h->xl, h->r, h->part)));
   launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(RED_T), (const double*)h->part, (int)d.ns, 1, h->scal, SC_TMP,
          -1);
 }
@@ -1067,13 +1130,15 @@ int krylov_cg(cdgmg_handle* h, cdgmg_solve_info* info) {
              (const double*)h->scal, sign, iter == 0 ? 1 : 0);
     const unsigned g = (unsigned)d0.ns;
     if (accurate) {
-      NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, NF, true>, dim3(g),
-                                            dim3(WAVE * H), d0.n, (const int32_t*)d0.cols, (const double*)d0.A64,
-                                            (const double*)h->p, (const double*)h->r, h->q, h->part)));
+      NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv0<NP, H, NF, true>, dim3(g), dim3(WAVE * H),
+                                            d0.n, (const int32_t*)d0.cols, (const int8_t*)d0.meta,
+                                            (const double*)d0.A64, (const double*)h->A0c, (const double*)h->p,
+                                            (const double*)h->r, h->q, h->part)));
     } else {
-      NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, NF, false>, dim3(g),
-                                            dim3(WAVE * H), d0.n, (const int32_t*)d0.cols, (const double*)d0.A64,
-                                            (const double*)h->p, (const double*)h->r, h->q, h->part)));
+      NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv0<NP, H, NF, false>, dim3(g), dim3(WAVE * H),
+                                            d0.n, (const int32_t*)d0.cols, (const int8_t*)d0.meta,
+                                            (const double*)d0.A64, (const double*)h->A0c, (const double*)h->p,
+                                            (const double*)h->r, h->q, h->part)));
     }
     launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(RED_T), (const double*)h->part, (int)g, 2, h->scal, SC_PQ,
            fcg ? 2 : 3);
@@ -1237,13 +1302,15 @@ int krylov_gmres(cdgmg_handle* h, cdgmg_solve_info* info) {
       const double* zj = Z + (int64_t)j * ld;
       const unsigned gs = (unsigned)d0.ns;
       if (accurate) {
-        NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, NF, true, false>, dim3(gs),
-                                              dim3(WAVE * H), d0.n, (const int32_t*)d0.cols, (const double*)d0.A64,
-                                              zj, (const double*)nullptr, w, (double*)nullptr)));
+        NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv0<NP, H, NF, true, false>, dim3(gs),
+                                              dim3(WAVE * H), d0.n, (const int32_t*)d0.cols, (const int8_t*)d0.meta,
+                                              (const double*)d0.A64, (const double*)h->A0c, zj,
+                                              (const double*)nullptr, w, (double*)nullptr)));
       } else {
-        NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv_dots_hs<NP, H, NF, false, false>, dim3(gs),
-                                              dim3(WAVE * H), d0.n, (const int32_t*)d0.cols, (const double*)d0.A64,
-                                              zj, (const double*)nullptr, w, (double*)nullptr)));
+        NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv0<NP, H, NF, false, false>, dim3(gs),
+                                              dim3(WAVE * H), d0.n, (const int32_t*)d0.cols, (const int8_t*)d0.meta,
+                                              (const double*)d0.A64, (const double*)h->A0c, zj,
+                                              (const double*)nullptr, w, (double*)nullptr)));
       }
       for (int pass = 0; pass < 2; ++pass) {
         double* hc = h->gmH + (size_t)pass * (R + 1);
@@ -1389,7 +1456,13 @@ int upload_embedding(cdgmg_handle* h) {
   double phi[32];
   for (int i = 0; i < np; ++i) {
     R1.eval(&R.nodes[(size_t)i * d], phi);
-    for (int k = 0; k < np1; ++k) T[(size_t)i * np1 + k] = phi[k];
+    for (int k = 0; k < np1; ++k) {
+      // a lower-degree basis function vanishes on every facet its node is
+      // off: exact zeros keep T^T A_0 T in the facet-trace form of A_0
+      bool zero = false;
+      for (int f = 0; f <= d; ++f) zero = zero || (R.on_facet(i, f) && !R1.on_facet(k, f));
+      T[(size_t)i * np1 + k] = zero ? 0.0 : phi[k];
+    }
   }
   RETURN_IF(upload(h, &h->Tp64, T));
   if (h->o.mg_precision == CDGMG_MG_FP32) {

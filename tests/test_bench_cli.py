@@ -17,18 +17,25 @@ def test_more_than_one_gpu_is_refused():
 def test_iteration_byte_model_adds_up():
     # the per-level byte model used for the iteration-average rate: the
     # level-0 part at the 2D p=3 benchmark sizes is entry + 3 sweeps +
-    # restriction + prolongation, and the parts sum to the total
+    # restriction + prolongation on the facet-trace form (4 of 10 rows or
+    # columns of each off-diagonal block stored), and the parts sum to the total
     import importlib.util
     spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
     b = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(b)
+    assert [b.facet_nodes(2, q) for q in (3, 6, 10)] == [2, 3, 4]
+    assert [b.facet_nodes(3, q) for q in (4, 10, 20)] == [3, 6, 10]
     sizes = [199712, 25657, 7215, 2210, 696, 217]
     nnzb = [797584, 161839, 48405, 14986, 4672, 1411]
-    t = b.iteration_bytes(sizes, nnzb, 10)
+    t = b.iteration_bytes(sizes, nnzb, 10, 4, 3)
     assert abs(t["total"] - sum(v for k, v in t.items() if k != "total")) < 1
-    sweep = b.smoother_bytes(nnzb[0], sizes[0], 10, 4)
-    n0, p2 = sizes[0], 100
-    level0 = ((n0 * 10 * 8 + n0 * p2 * 4 + 2 * n0 * 10 * 4) + sweep + (sweep + n0 * p2 * 4)
+    n0, p2, off = sizes[0], 100, nnzb[0] - sizes[0]
+    sweep = b.smoother_bytes(nnzb[0], n0, 10, 4, 4, 3)
+    assert sweep == off * 40 * 4 + 15 * n0 + n0 * p2 * 4 + 3 * n0 * 10 * 4
+    restrict = off * 40 * 4 + 15 * n0 + 2 * n0 * p2 * 4 + 3 * n0 * 10 * 4 + n0 * 10 * 4
+    level0 = ((n0 * 10 * 8 + n0 * p2 * 4 + 2 * n0 * 10 * 4) + sweep + restrict
               + (n0 * p2 * 4 + 2 * n0 * 10 * 4 + 4 * n0 + sizes[1] * 10 * 4) + 2 * sweep + n0 * 10 * 8)
     assert t["level0"] == level0
-    assert t["outer"] == (n0 * 10 * 4 + 2 * n0 * 10 * 8) + b.spmv_bytes(nnzb[0], n0, 10) + 6 * n0 * 10 * 8
+    spmv = n0 * p2 * 8 + off * 40 * 8 + 15 * n0 + 3 * n0 * 10 * 8
+    assert b.spmv_bytes(nnzb[0], n0, 10, 4, 3) == spmv
+    assert t["outer"] == (n0 * 10 * 4 + 2 * n0 * 10 * 8) + spmv + 6 * n0 * 10 * 8

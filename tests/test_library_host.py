@@ -336,3 +336,45 @@ def test_invalid_meshes_are_refused(make):
         with pytest.raises(cm.CdgmgError) as ei:
             call()
         assert ei.value.code == -2, str(ei.value)
+
+
+@pytest.mark.parametrize("d,n,p,kw", [(2, 8, 3, {}), (2, 7, 2, {"switch_mode": 1, "switch_seed": 3}),
+                                      (3, 3, 3, {}), (3, 3, 2, {}), (2, 6, 1, {}),
+                                      (2, 6, 2, {"beta": 5.0, "outer": 2, "velocity": (0.6, 0.8)})])
+def test_level0_blocks_are_in_facet_trace_form(d, n, p, kw):
+    # the primal form couples neighbours only through traces on their common
+    # facet; the library's level-0 off-diagonal blocks are exactly zero off the
+    # neighbour's facet-node columns (the row hosts the facet) or off the row's
+    # facet-node rows (the neighbour hosts it) -- the form the GPU stores
+    from oracle.refelem import equispaced_nodes
+    m = mesh2d_jittered_delaunay(n, 1) if d == 2 else mesh3d_kuhn(n, 1)
+    parents, sizes = cm.agglomerate(m, 2, 1, p=p)
+    kappa = np.random.default_rng(2).uniform(0.5, 2.0, m.n_elem)
+    rp, cols, blocks = cm.debug_host_operator(m, p, kappa, parents, sizes, 0, **kw)
+    X = np.asarray(equispaced_nodes(d, p))
+    lam = np.column_stack([1.0 - X.sum(1), X])
+    on = [np.abs(lam[:, f]) < 1e-12 for f in range(d + 1)]
+    nbr = {}
+    for e in range(m.n_elem):
+        for f in range(d + 1):
+            fv = set(np.delete(m.e2v[e], f).tolist())
+            nbr.setdefault(frozenset(fv), []).append((e, f))
+    local = {}
+    for pairs in nbr.values():
+        if len(pairs) == 2:
+            (a, fa), (b, fb) = pairs
+            local[(a, b)] = (fa, fb)
+            local[(b, a)] = (fb, fa)
+    kinds = {"column": 0, "row": 0}
+    for r in range(m.n_elem):
+        for k in range(rp[r], rp[r + 1]):
+            c = int(cols[k])
+            if c == r:
+                continue
+            fr, fc = local[(r, c)]
+            B = blocks[k]
+            col_form = not np.any(B[:, ~on[fc]])
+            row_form = not np.any(B[~on[fr], :])
+            assert col_form or row_form, (r, c)
+            kinds["column" if col_form else "row"] += 1
+    assert kinds["column"] > 0 and kinds["row"] > 0
