@@ -706,6 +706,41 @@ __device__ __forceinline__ T ld(const T* p) {
     return *p;
 }
 
+// A row of N contiguous values (a row of a row-major [rows][N] vector) in the
+// widest loads or stores its alignment allows: N sizeof(T) bytes from a
+// 16-byte aligned base, so every row starts on a multiple of the largest power
+// of two (up to 16) dividing N sizeof(T).  A gathered neighbour row then costs
+// N sizeof(T) / A memory instructions instead of N.
+template <int A>
+struct alignas(A) RowChunk {
+  uint32_t w[A / 4];
+};
+template <typename T, int N>
+constexpr int row_align() {
+  return (N * (int)sizeof(T)) % 16 == 0 ? 16 : (N * (int)sizeof(T)) % 8 == 0 ? 8 : 4;
+}
+template <typename T, int N>
+__device__ __forceinline__ void load_row(const T* p, T* v) {
+  constexpr int A = row_align<T, N>(), C = N * (int)sizeof(T) / A;
+  const RowChunk<A>* q = reinterpret_cast<const RowChunk<A>*>(p);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const RowChunk<A> t = q[c];
+    __builtin_memcpy(reinterpret_cast<char*>(v) + c * A, &t, A);
+  }
+}
+template <typename T, int N>
+__device__ __forceinline__ void store_row(T* p, const T* v) {
+  constexpr int A = row_align<T, N>(), C = N * (int)sizeof(T) / A;
+  RowChunk<A>* q = reinterpret_cast<RowChunk<A>*>(p);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    RowChunk<A> t;
+    __builtin_memcpy(&t, reinterpret_cast<const char*>(v) + c * A, A);
+    q[c] = t;
+  }
+}
+
 // This wavefront's share of sign * A_off x at row r = 64 s + lane: column-kind
 // blocks into acc[t] (row h NI + t), row-kind blocks into sc[i] (all rows,
 // partial over this wavefront's input components).  With LO the vector is
@@ -741,16 +776,33 @@ __device__ __forceinline__ void off0(int64_t s, int lane, int h, const int32_t* 
     const int64_t cb = (int64_t)cv * NP;
     const bool row = kd == NF;
     T xo[NI], xs[NFN], xol[LO ? NI : 1], xsl[LO ? NFN : 1];
+    if constexpr (H == 1) {
+      // the whole neighbour row in a few wide loads; its facet values by selection
+      load_row<T, NP>(x + cb, xo);
+      if constexpr (LO) load_row<T, NP>(xl + cb, xol);
 #pragma unroll
-    for (int t = 0; t < NI; ++t) {
-      xo[t] = x[cb + h * NI + t];
-      if constexpr (LO) xol[t] = xl[cb + h * NI + t];
-    }
+      for (int k = 0; k < NFN; ++k) {
+        T v = xo[FT.v[0][k]], vl = LO ? xol[LO ? FT.v[0][k] : 0] : T(0);
 #pragma unroll
-    for (int k = 0; k < NFN; ++k) {
-      const int64_t a = cb + facet_node_at<NP, NF>(kd, k);
-      xs[k] = row ? T(0) : x[a];
-      if constexpr (LO) xsl[k] = row ? T(0) : xl[a];
+        for (int g = 1; g < NF; ++g) {
+          v = kd == g ? xo[FT.v[g][k]] : v;
+          if constexpr (LO) vl = kd == g ? xol[FT.v[g][k]] : vl;
+        }
+        xs[k] = row ? T(0) : v;
+        if constexpr (LO) xsl[k] = row ? T(0) : vl;
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < NI; ++t) {
+        xo[t] = x[cb + h * NI + t];
+        if constexpr (LO) xol[t] = xl[cb + h * NI + t];
+      }
+#pragma unroll
+      for (int k = 0; k < NFN; ++k) {
+        const int64_t a = cb + facet_node_at<NP, NF>(kd, k);
+        xs[k] = row ? T(0) : x[a];
+        if constexpr (LO) xsl[k] = row ? T(0) : xl[a];
+      }
     }
     Acc<T, COMP> sw[NFN];
     const T* V = Ac + ((s * NF + w) * NPF + (int64_t)h * NI * NFN) * WAVE + lane;
@@ -853,8 +905,15 @@ __global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* _
   const bool valid = r < n;
   Acc<T, false> acc[NI], sc[NP];
   if (valid) {
+    if constexpr (H == 1) {
+      T bv[NP];
+      load_row<T, NP>(b + r * NP, bv);
 #pragma unroll
-    for (int t = 0; t < NI; ++t) acc[t].s = b[r * NP + h * NI + t];
+      for (int t = 0; t < NP; ++t) acc[t].s = bv[t];
+    } else {
+#pragma unroll
+      for (int t = 0; t < NI; ++t) acc[t].s = b[r * NP + h * NI + t];
+    }
     off0<T, NP, H, NF, false, false, false>(sl, lane, h, cols, meta, Ac, xin, nullptr, T(-1), acc, sc);
   }
   gather_rows<T, NP, H, false>(lane, h, valid, acc, sc, sh, nullptr);
@@ -863,7 +922,28 @@ __global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* _
   for (int t = 0; t < NI; ++t) own[t] = acc[t].value();
   share_rows<T, NP, H>(lane, h, valid, own, sv, sh);
   double d = 0.0;
-  if (valid) {
+  if constexpr (H == 1 && sizeof(T) == 4) {
+    // whole rows in and out with wide accesses
+    if (valid) {
+      const T* D = Dinv + sl * WAVE * NP2 + lane;
+      T xv[NP], xn[NP];
+      load_row<T, NP>(xin + r * NP, xv);
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        T y = 0;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) y += D[(i * NP + j) * WAVE] * sv[j];
+        xn[i] = xv[i] + omega * (y - xv[i]);
+      }
+      store_row<T, NP>(xout + r * NP, xn);
+      if constexpr (DOT) {
+        double dq[NP];
+        load_row<double, NP>(dv + r * NP, dq);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) d += (double)xn[i] * dq[i];
+      }
+    }
+  } else if (valid) {
     const T* D = Dinv + sl * WAVE * NP2 + lane;
     // FP32 blocks: all of D^{-1}'s loads in flight at once; FP64: two rows
     constexpr int UF = sizeof(T) == 4 ? NI : 2;
@@ -898,13 +978,26 @@ __device__ __forceinline__ void residual0(int64_t sl, int64_t r, int lane, int h
   Acc<T, false> acc[NI], sc[NP];
   if (valid) {
     const T* Dg = Ad + sl * WAVE * NP2 + lane;
+    if constexpr (H == 1 && sizeof(T) == 4) {
+      T bv[NP], xr[NP];
+      load_row<T, NP>(b + r * NP, bv);
+      load_row<T, NP>(x + r * NP, xr);
 #pragma unroll
-    for (int t = 0; t < NI; ++t) acc[t].s = b[r * NP + h * NI + t];
+      for (int i = 0; i < NP; ++i) {
+        acc[i].s = bv[i];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) acc[i].add(-__builtin_nontemporal_load(Dg + (i * NP + j) * WAVE), xr[j]);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < NI; ++t) acc[t].s = b[r * NP + h * NI + t];
 #pragma unroll 2
-    for (int j = 0; j < NP; ++j) {
-      const T xj = x[r * NP + j];
+      for (int j = 0; j < NP; ++j) {
+        const T xj = x[r * NP + j];
 #pragma unroll
-      for (int t = 0; t < NI; ++t) acc[t].add(-__builtin_nontemporal_load(Dg + ((h * NI + t) * NP + j) * WAVE), xj);
+        for (int t = 0; t < NI; ++t)
+          acc[t].add(-__builtin_nontemporal_load(Dg + ((h * NI + t) * NP + j) * WAVE), xj);
+      }
     }
     off0<T, NP, H, NF, false, false, false>(sl, lane, h, cols, meta, Ac, x, nullptr, T(-1), acc, sc);
   }
@@ -931,14 +1024,25 @@ __global__ __launch_bounds__(WAVE * H) void k_restrict0(int64_t n, const int32_t
   residual0<T, NP, H, NF>(sl, r, lane, h, valid, cols, meta, Ac, Ad, b, x, sh, res);
   if (!valid) return;
   const T* Lr = Lb + sl * WAVE * NP2 + lane;
-  constexpr int UF = sizeof(T) == 4 ? NI : 2;
-#pragma unroll UF
-  for (int t = 0; t < NI; ++t) {
-    const int j = h * NI + t;
-    T s = 0;
+  if constexpr (H == 1 && sizeof(T) == 4) {
+    T tv[NP];
 #pragma unroll
-    for (int i = 0; i < NP; ++i) s += __builtin_nontemporal_load(Lr + (i * NP + j) * WAVE) * res[i];
-    t_out[r * NP + j] = s;
+    for (int j = 0; j < NP; ++j) {
+      T s = 0;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) s += __builtin_nontemporal_load(Lr + (i * NP + j) * WAVE) * res[i];
+      tv[j] = s;
+    }
+    store_row<T, NP>(t_out + r * NP, tv);
+  } else {
+#pragma unroll 2
+    for (int t = 0; t < NI; ++t) {
+      const int j = h * NI + t;
+      T s = 0;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) s += __builtin_nontemporal_load(Lr + (i * NP + j) * WAVE) * res[i];
+      t_out[r * NP + j] = s;
+    }
   }
 }
 
@@ -953,19 +1057,36 @@ __global__ __launch_bounds__(WAVE * H) void k_entry0(int64_t n, const double* __
   const int64_t sl = xcd_slice(), r = sl * WAVE + lane;
   if (r >= n) return;
   T v[NP];
+  {
+    double rv[NP];
+    load_row<double, NP>(src + r * NP, rv);
 #pragma unroll
-  for (int j = 0; j < NP; ++j) v[j] = (T)src[r * NP + j];
+    for (int j = 0; j < NP; ++j) v[j] = (T)rv[j];
+  }
   const T* D = Dinv + sl * WAVE * NP2 + lane;
+  if constexpr (H == 1 && sizeof(T) == 4) {
+    T xv[NP];
 #pragma unroll
-  for (int t = 0; t < NI; ++t) b[r * NP + h * NI + t] = v[h * NI + t];
-  constexpr int UF = sizeof(T) == 4 ? NI : 2;
+    for (int i = 0; i < NP; ++i) {
+      T s = 0;
+#pragma unroll
+      for (int j = 0; j < NP; ++j) s += D[(i * NP + j) * WAVE] * v[j];
+      xv[i] = omega * s;
+    }
+    store_row<T, NP>(b + r * NP, v);
+    store_row<T, NP>(x + r * NP, xv);
+  } else {
+#pragma unroll
+    for (int t = 0; t < NI; ++t) b[r * NP + h * NI + t] = v[h * NI + t];
+    constexpr int UF = sizeof(T) == 4 ? NI : 2;
 #pragma unroll UF
-  for (int t = 0; t < NI; ++t) {
-    const int i = h * NI + t;
-    T s = 0;
+    for (int t = 0; t < NI; ++t) {
+      const int i = h * NI + t;
+      T s = 0;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) s += __builtin_nontemporal_load(D + (i * NP + j) * WAVE) * v[j];
-    x[r * NP + i] = omega * s;
+      for (int j = 0; j < NP; ++j) s += D[(i * NP + j) * WAVE] * v[j];
+      x[r * NP + i] = omega * s;
+    }
   }
 }
 
@@ -1123,28 +1244,68 @@ __device__ __forceinline__ void grp_scaled_residual(int64_t r, int g, const int3
   for (int i = 0; i < NP; ++i) res[i] = group_allsum<G>(acc[i]);
 }
 
-// lane g of a group writes components g, g + G, ...
-template <typename T, int NP, int G>
+// lane g of a group writes components g, g + G, ...  With PROL (the last
+// post-sweep of a level) the group then also prolongs its new x_r into the
+// children e of r on the finer level, x_f[e] += L_e x_r (Sec. 3.4): that
+// correction needs only this row's final value, so it saves the separate
+// prolongation launch.  cs: the level's child ranges; Lf: the finer level's
+// L_e blocks (per-row layout).
+template <typename T, int NP, int G, bool PROL = false>
 __global__ __launch_bounds__(TPB) void k_sweep_grp(int64_t n, const int32_t* __restrict__ wcols,
                                                    const int64_t* __restrict__ woff, const T* __restrict__ R,
                                                    const T* __restrict__ bt, const T* __restrict__ xin, T omega,
-                                                   T* __restrict__ xout) {
+                                                   T* __restrict__ xout, const int32_t* __restrict__ cs = nullptr,
+                                                   const T* __restrict__ Lf = nullptr, T* __restrict__ xf = nullptr) {
+  constexpr int NP2 = NP * NP;
   const int64_t gid = (int64_t)blockIdx.x * TPB + threadIdx.x;
   const int64_t r = gid / G;
   const int g = (int)(gid % G);
   if (r >= n) return;
   T sum[NP];
   grp_scaled_residual<T, NP, G>(r, g, wcols, woff, R, xin, sum);
+  if constexpr (!PROL) {
 #pragma unroll
-  for (int m = 0; m < (NP + G - 1) / G; ++m) {
-    const int i = g + m * G;
-    if (i < NP) {
-      T si = sum[0];
+    for (int m = 0; m < (NP + G - 1) / G; ++m) {
+      const int i = g + m * G;
+      if (i < NP) {
+        T si = sum[0];
 #pragma unroll
-      for (int q = 1; q < NP; ++q)
-        if (q == i) si = sum[q];
+        for (int q = 1; q < NP; ++q)
+          if (q == i) si = sum[q];
+        const T xi = xin[r * NP + i];
+        xout[r * NP + i] = xi + omega * (bt[r * NP + i] - xi - si);
+      }
+    }
+  } else {
+    // every lane forms the whole new x_r (the same values in every lane)
+    T xn[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
       const T xi = xin[r * NP + i];
-      xout[r * NP + i] = xi + omega * (bt[r * NP + i] - xi - si);
+      xn[i] = xi + omega * (bt[r * NP + i] - xi - sum[i]);
+    }
+#pragma unroll
+    for (int m = 0; m < (NP + G - 1) / G; ++m) {
+      const int i = g + m * G;
+      if (i < NP) {
+        T v = xn[0];
+#pragma unroll
+        for (int q = 1; q < NP; ++q)
+          if (q == i) v = xn[q];
+        xout[r * NP + i] = v;
+      }
+    }
+    // consecutive lanes take consecutive children (consecutive rows of the
+    // finer level) for one component, so the L_e loads of a group coalesce
+    const int32_t e0 = cs[r], ne = cs[r + 1] - e0;
+    for (int q = g; q < ne * NP; q += G) {
+      const int64_t e = e0 + q % ne;
+      const int i = q / ne;
+      const T* Le = Lf + (e / WAVE) * WAVE * NP2 + (int64_t)i * NP * WAVE + (e % WAVE);
+      T s = 0;
+#pragma unroll
+      for (int j = 0; j < NP; ++j) s += __builtin_nontemporal_load(Le + j * WAVE) * xn[j];
+      xf[e * NP + i] += s;
     }
   }
 }
@@ -1530,15 +1691,31 @@ __global__ __launch_bounds__(WAVE * H) void k_spmv0(int64_t n, const int32_t* __
   gather_rows<double, NP, H, COMP>(lane, h, valid, acc, sc, shs, shc);
   double pq = 0.0, pr = 0.0;
   if (valid) {
+    if constexpr (H == 1) {
+      double qv[NP], pv[NP], rv[NP];
 #pragma unroll
-    for (int t = 0; t < NI; ++t) {
-      const int i = h * NI + t;
-      const double qi = acc[t].value();
-      q[r * NP + i] = qi;
+      for (int i = 0; i < NP; ++i) qv[i] = acc[i].value();
+      store_row<double, NP>(q + r * NP, qv);
       if constexpr (DOTS) {
-        const double pi = p[r * NP + i];
-        pq = __builtin_fma(pi, qi, pq);
-        pr = __builtin_fma(pi, rr[r * NP + i], pr);
+        load_row<double, NP>(p + r * NP, pv);
+        load_row<double, NP>(rr + r * NP, rv);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          pq = __builtin_fma(pv[i], qv[i], pq);
+          pr = __builtin_fma(pv[i], rv[i], pr);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < NI; ++t) {
+        const int i = h * NI + t;
+        const double qi = acc[t].value();
+        q[r * NP + i] = qi;
+        if constexpr (DOTS) {
+          const double pi = p[r * NP + i];
+          pq = __builtin_fma(pi, qi, pq);
+          pr = __builtin_fma(pi, rr[r * NP + i], pr);
+        }
       }
     }
   }

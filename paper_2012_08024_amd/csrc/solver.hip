@@ -844,9 +844,11 @@ int pick_h0(int np, int variant) {
 
 // count damped block-Jacobi sweeps on level l (ping-pong x <-> xb); with dv
 // given, the last level-0 sweep also leaves the partial sums of (x, dv) in
-// h->part, one per slice
+// h->part, one per slice; with xf given (l >= 1), the last sweep also
+// prolongs into level l - 1, x_{l-1} += L x_l (xf = x_{l-1})
 template <typename T, int NP>
-void smooth_sweeps(cdgmg_handle* h, int l, int count, T** x, T** xb, const double* dv = nullptr) {
+void smooth_sweeps(cdgmg_handle* h, int l, int count, T** x, T** xb, const double* dv = nullptr,
+                   T* xf = nullptr) {
   DLevel& d = h->lv[l];
   const T omega = (T)h->o.omega;
   const int cls = l == 0 && !h->given_A0 ? CDGMG_K_SMOOTH0 : CDGMG_K_SMOOTH;
@@ -864,10 +866,16 @@ void smooth_sweeps(cdgmg_handle* h, int l, int count, T** x, T** xb, const doubl
                               (const T*)d.b, (const T*)*x, omega, *xb, (const double*)nullptr, (double*)nullptr,
                               rev));
       }
+    } else if (xf && s == count - 1) {
+      G_DISPATCH(d.grp_s, launch(h, cls, k_sweep_grp<T, NP, G, true>, dim3(grid_for(d.n * G)), dim3(TPB), d.n,
+                                 (const int32_t*)d.wcols, (const int64_t*)d.woff, (const T*)d.R, (const T*)d.b,
+                                 (const T*)*x, omega, *xb, (const int32_t*)d.child_start,
+                                 (const T*)h->lv[l - 1].Lm, xf));
     } else {
       G_DISPATCH(d.grp_s, launch(h, cls, k_sweep_grp<T, NP, G>, dim3(grid_for(d.n * G)), dim3(TPB), d.n,
                                  (const int32_t*)d.wcols, (const int64_t*)d.woff, (const T*)d.R, (const T*)d.b,
-                                 (const T*)*x, omega, *xb));
+                                 (const T*)*x, omega, *xb, (const int32_t*)nullptr, (const T*)nullptr,
+                                 (T*)nullptr));
     }
     std::swap(*x, *xb);
   }
@@ -975,12 +983,18 @@ T* vcycle_t(cdgmg_handle* h, const double* r64, const double* dv, int* nparts) {
          (const int32_t*)c.child_start, (const T*)h->lv[L - 1].t, (const T*)nullptr, omega, (T*)c.b, (T*)nullptr);
   launch(h, CDGMG_K_COARSE, k_dense_gemv<T>, dim3(grid_for(h->nd * WAVE)), dim3(TPB), h->nd, h->ld,
          (const T*)h->AinvP, (const T*)c.b, xs[L]);
+  // upward: the last post-sweep of a level l >= 2 also prolongs into level
+  // l - 1, where a separate launch would be bound by its latency (from the
+  // coarsest level, into level 0, or with nu2 = 0, a separate launch)
   for (int l = L - 1; l >= 0; --l) {
     DLevel& d = h->lv[l];
-    const int tpb = row_tpb(h, l);
-    launch(h, CDGMG_K_PROLONG, k_prolong<T, NP>, dim3(grid_for(d.n, tpb)), dim3(tpb), d.n, (const int32_t*)d.parent,
-           (const T*)d.Lm, (const T*)xs[l + 1], xs[l]);
-    smooth_sweeps<T, NP>(h, l, nu2, &xs[l], &xbs[l], l == 0 ? dv : nullptr);
+    const bool fused = l >= 1 && l + 1 < L && nu2 > 0;
+    if (!fused) {
+      const int tpb = row_tpb(h, l);
+      launch(h, CDGMG_K_PROLONG, k_prolong<T, NP>, dim3(grid_for(d.n, tpb)), dim3(tpb), d.n,
+             (const int32_t*)d.parent, (const T*)d.Lm, (const T*)xs[l + 1], xs[l]);
+    }
+    smooth_sweeps<T, NP>(h, l, nu2, &xs[l], &xbs[l], l == 0 ? dv : nullptr, l >= 2 ? xs[l - 1] : nullptr);
   }
   if (dv) {
     if (nu2 > 0)
