@@ -176,6 +176,8 @@ def main():
     ap.add_argument("--restart", type=int, default=50, help="GMRES restart length")
     ap.add_argument("--p-coarse", type=int, default=0, help="1: hp front end (p-multigrid to p = 1 first)")
     ap.add_argument("--p-jump", type=int, default=0, help="with --p-coarse 1: 1 goes from p straight to p = 1")
+    ap.add_argument("--coarsening", choices=["primal", "flux"], default="primal",
+                    help="coarse operators: Galerkin L^T A L (primal, Sec. 3.5) or the flux form (Sec. 4.1)")
     ap.add_argument("--study", choices=["coarsening", "coarsening-paper", "switch", "switch-paper", "convection",
                                         "size"],
                     help="instead of the benchmark: primal vs flux coarsening over mesh size and gamma, "
@@ -224,9 +226,10 @@ def main():
     if args.p_coarse == 1 and cfg["p"] >= 2:
         hp_desc = "p-multigrid over degrees %s, then " % (
             "%d, 1" % cfg["p"] if args.p_jump else ", ".join(str(q) for q in range(cfg["p"], 0, -1)))
+    coarsening = cm.COARSEN_FLUX if args.coarsening == "flux" else cm.COARSEN_PRIMAL
     s32 = cm.Solver(mesh, cfg["p"], kappa_t, parents, sizes, mg_precision=cm.MG_FP32, tol=cfg["tol"],
                     outer=outer, restart=args.restart, p_coarse=args.p_coarse, p_jump=args.p_jump,
-                    kernel_variant=args.kernel_variant)
+                    kernel_variant=args.kernel_variant, coarsening=coarsening)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     npb = s32.np
@@ -299,7 +302,7 @@ def main():
         s32_bytes = s32.device_bytes()
         s64 = cm.Solver(mesh, cfg["p"], kappa_t, parents, sizes, mg_precision=cm.MG_FP64, tol=cfg["tol"],
                         outer=outer, restart=args.restart, p_coarse=args.p_coarse, p_jump=args.p_jump,
-                        kernel_variant=args.kernel_variant)
+                        kernel_variant=args.kernel_variant, coarsening=coarsening)
         for _ in range(max(1, args.warmup)):
             u64, info64 = s64.solve(f)
         torch.cuda.synchronize()
@@ -353,12 +356,16 @@ def main():
         "data": "synthetic",
         "config": {
             "p_levels": s32.p_levels,
-            "workload": "%s: %dD jittered %s mesh n=%d, %d elements, CDG p=%d, %d DOFs, kappa=%s, %s%d-level "
+            "workload": "%s: %dD %s mesh n=%d, %d elements, CDG p=%d, %d DOFs, kappa=%s, %s%d-level "
                         "greedy agglomeration (seed %d), V(%d,%d) damped block Jacobi omega=%.1f, "
-                        "Galerkin coarse operators, %s, tol %.0e"
-                        % (args.config, cfg["dim"], "Delaunay" if cfg["dim"] == 2 else "Kuhn-tet", cfg["n"],
+                        "%s coarse operators, %s, tol %.0e"
+                        % (args.config, cfg["dim"],
+                           "uniform right-triangle square (Neumann x=0,1)" if cfg.get("mesh") == "square51"
+                           else "jittered Delaunay" if cfg["dim"] == 2 else "jittered Kuhn-tet", cfg["n"],
                            mesh.n_elem, cfg["p"], dofs, cfg["kappa"], hp_desc, len(sizes), cfg["agg_seed"], 2, 2,
-                           0.7, outer_name, cfg["tol"]),
+                           0.7, "Galerkin (primal)" if args.coarsening == "primal" else "flux-form (Sec. 4.1)",
+                           outer_name, cfg["tol"]),
+            "coarsening": args.coarsening,
             "elements": int(mesh.n_elem), "dofs": int(dofs), "p": cfg["p"], "levels": [int(x) for x in sizes],
             "nnzb": [int(x) for x in nnzb],
             "operator_complexity": float(sum(nnzb) / nnzb[0]),

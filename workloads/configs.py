@@ -1,6 +1,6 @@
 """The five synthetic workloads: mesh family and size, polynomial degree,
 coefficient field, hierarchy depth, cycle and outer solver, and seeds."""
-from .meshes import mesh2d_jittered_delaunay, mesh3d_kuhn
+from .meshes import mesh2d_jittered_delaunay, mesh2d_square_neumann_sides, mesh3d_kuhn
 from .fields import kappa_grf, kappa_spheres
 
 CONFIGS = {
@@ -20,6 +20,11 @@ CONFIGS = {
     # 3D Kuhn tetrahedra, 384000 tets, p=3 (7 680 000 DOFs), high-contrast spheres
     "c5": dict(dim=3, n=40, p=3, kappa="spheres", kappa_seed=51, levels=6, outer="fcg",
                mg="fp32", mesh_seed=5, agg_seed=15, tol=1e-10),
+    # the mesh class of Sec. 5.1 at the size of c2: uniform n x n square split
+    # into 199712 right triangles, Neumann sides x = 0, 1, Dirichlet y = 0, 1;
+    # p=3 (1 997 120 DOFs), kappa=1, 6 levels -- flux against primal coarsening
+    "sq316": dict(dim=2, n=316, p=3, kappa="one", levels=6, outer="fcg", mg="fp32", mesh="square51",
+                  mesh_seed=0, agg_seed=12, tol=1e-10),
 }
 
 
@@ -28,7 +33,9 @@ def config_mesh(cfg, n=None):
     import numpy as np
 
     n = cfg["n"] if n is None else n
-    if cfg["dim"] == 2:
+    if cfg.get("mesh") == "square51":
+        mesh = mesh2d_square_neumann_sides(n)
+    elif cfg["dim"] == 2:
         mesh = mesh2d_jittered_delaunay(n, cfg["mesh_seed"])
     else:
         mesh = mesh3d_kuhn(n, cfg["mesh_seed"])
