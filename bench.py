@@ -176,6 +176,8 @@ def main():
     ap.add_argument("--restart", type=int, default=50, help="GMRES restart length")
     ap.add_argument("--p-coarse", type=int, default=0, help="1: hp front end (p-multigrid to p = 1 first)")
     ap.add_argument("--p-jump", type=int, default=0, help="with --p-coarse 1: 1 goes from p straight to p = 1")
+    ap.add_argument("--coarse-fp64", type=int, default=0,
+                    help="1: the FP32 V-cycle keeps its coarsest solve in FP64")
     ap.add_argument("--coarsening", choices=["primal", "flux"], default="primal",
                     help="coarse operators: Galerkin L^T A L (primal, Sec. 3.5) or the flux form (Sec. 4.1)")
     ap.add_argument("--study", choices=["coarsening", "coarsening-paper", "switch", "switch-paper", "convection",
@@ -229,7 +231,7 @@ def main():
     coarsening = cm.COARSEN_FLUX if args.coarsening == "flux" else cm.COARSEN_PRIMAL
     s32 = cm.Solver(mesh, cfg["p"], kappa_t, parents, sizes, mg_precision=cm.MG_FP32, tol=cfg["tol"],
                     outer=outer, restart=args.restart, p_coarse=args.p_coarse, p_jump=args.p_jump,
-                    kernel_variant=args.kernel_variant, coarsening=coarsening)
+                    kernel_variant=args.kernel_variant, coarsening=coarsening, coarse_fp64=args.coarse_fp64)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     npb = s32.np
@@ -365,7 +367,7 @@ def main():
                            mesh.n_elem, cfg["p"], dofs, cfg["kappa"], hp_desc, len(sizes), cfg["agg_seed"], 2, 2,
                            0.7, "Galerkin (primal)" if args.coarsening == "primal" else "flux-form (Sec. 4.1)",
                            outer_name, cfg["tol"]),
-            "coarsening": args.coarsening,
+            "coarsening": args.coarsening, "coarse_fp64": args.coarse_fp64,
             "elements": int(mesh.n_elem), "dofs": int(dofs), "p": cfg["p"], "levels": [int(x) for x in sizes],
             "nnzb": [int(x) for x in nnzb],
             "operator_complexity": float(sum(nnzb) / nnzb[0]),

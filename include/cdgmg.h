@@ -132,6 +132,9 @@ typedef struct cdgmg_options {
   int row_threads;     /* workgroup size of the thread-per-row transfer kernels (prolongation
                           and correction, coarse-level entry): 0 (default) 64 on levels below
                           100 000 rows and 256 above, or 64 or 256 on every level */
+  int coarse_fp64;     /* with the FP32 V-cycle: 1 keeps the coarsest solve (the explicit
+                          inverse of A_L, Alg. 3) in FP64, products summed in FP64 and the
+                          result rounded to FP32 once; 0 (default) rounds the inverse to FP32 */
 } cdgmg_options;
 
 typedef struct cdgmg_solve_info {

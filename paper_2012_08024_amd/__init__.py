@@ -49,7 +49,8 @@ class _Opts(ctypes.Structure):
                 ("switch_seed", ctypes.c_uint64), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("profile", ctypes.c_int), ("kernel_variant", ctypes.c_int), ("restart", ctypes.c_int),
                 ("beta", ctypes.c_double), ("velocity", ctypes.c_double * 3), ("p_coarse", ctypes.c_int),
-                ("p_jump", ctypes.c_int), ("coarse_group", ctypes.c_int), ("row_threads", ctypes.c_int)]
+                ("p_jump", ctypes.c_int), ("coarse_group", ctypes.c_int), ("row_threads", ctypes.c_int),
+                ("coarse_fp64", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):

@@ -41,6 +41,7 @@ void cdgmg_default_options(cdgmg_options* o) {
   o->p_jump = 0;
   o->coarse_group = 0;
   o->row_threads = 0;
+  o->coarse_fp64 = 0;
 }
 
 int cdgmg_agglomerate(const cdgmg_mesh* mesh, int max_levels, int64_t coarse_dofs_max, int p, uint64_t seed,

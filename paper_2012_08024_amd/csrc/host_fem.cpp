@@ -968,6 +968,10 @@ int check_options(const cdgmg_options& o) {
     set_error("setup: coarse_group must be 0, 8, 16, 32 or 64");
     return CDGMG_ERR_ARG;
   }
+  if (o.coarse_fp64 != 0 && o.coarse_fp64 != 1) {
+    set_error("setup: coarse_fp64 must be 0 or 1");
+    return CDGMG_ERR_ARG;
+  }
   if (o.row_threads != 0 && o.row_threads != 64 && o.row_threads != 256) {
     set_error("setup: row_threads must be 0, 64 or 256");
     return CDGMG_ERR_ARG;

@@ -546,6 +546,27 @@ struct Vec16<double> {
   __device__ static double dot(const double2& a, const double2& b) { return a.x * b.x + a.y * b.y; }
 };
 
+// FP64 inverse with FP32 vectors (the FP32 V-cycle with its coarsest solve in
+// FP64): products and sum in FP64, x rounded once
+__global__ __launch_bounds__(TPB) void k_dense_gemv_mixed(int64_t n, int64_t ld, const double* __restrict__ Ainv,
+                                                          const float* __restrict__ b, float* __restrict__ x) {
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
+  const int lane = threadIdx.x % WAVE;
+  if (row >= n) return;
+  const double2* Ar = reinterpret_cast<const double2*>(Ainv + row * ld);
+  const float2* bv = reinterpret_cast<const float2*>(b);
+  const int64_t nv = ld / 2;
+  double s = 0;
+#pragma unroll 4
+  for (int64_t c = lane; c < nv; c += WAVE) {
+    const double2 a = Ar[c];
+    const float2 v = bv[c];
+    s += a.x * (double)v.x + a.y * (double)v.y;
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (lane == 0) x[row] = (float)s;
+}
+
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_dense_gemv(int64_t n, int64_t ld, const T* __restrict__ Ainv,
                                                     const T* __restrict__ b, T* __restrict__ x) {

@@ -599,7 +599,7 @@ int upload_problem(cdgmg_handle* h) {
     RETURN_IF(dalloc(h, &h->dense, (size_t)h->ld * h->ld));
     RETURN_IF(dalloc(h, &h->gjP, (size_t)GJB * GJB));
     RETURN_IF(dalloc(h, &h->gjD, (size_t)h->ld));
-    if (fp32) {
+    if (fp32 && !h->o.coarse_fp64) {
       float* tmp;
       RETURN_IF(dalloc(h, &tmp, (size_t)h->nd * h->ld));
       h->AinvP = tmp;
@@ -825,7 +825,7 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed) {
   }
   RETURN_IF(check_err(h, CDGMG_ERR_SINGULAR, flux ? "setup: the coarsest operator is singular"
                                                   : "setup: the coarsest operator is not positive definite"));
-  if (h->o.mg_precision == CDGMG_MG_FP32)
+  if (h->o.mg_precision == CDGMG_MG_FP32 && !h->o.coarse_fp64)
     launch(h, -1, k_cast<double, float>, dim3(grid_for(nd * ld)), dim3(TPB), nd * ld, (const double*)h->dense,
            (float*)h->AinvP);
   HIPCHK(hipGetLastError());
@@ -899,6 +899,21 @@ inline int row_tpb(const cdgmg_handle* h, int l) {
 
 void* vcycle(cdgmg_handle* h, const double* r64, const double* dv, int* nparts);
 
+// x = A_L^{-1} b on the coarsest level, the inverse in the multigrid precision
+// or, with coarse_fp64 in the FP32 cycle, in FP64
+template <typename T>
+void coarse_solve(cdgmg_handle* h, const T* b, T* x) {
+  if constexpr (sizeof(T) == 4) {
+    if (h->o.coarse_fp64) {
+      launch(h, CDGMG_K_COARSE, k_dense_gemv_mixed, dim3(grid_for(h->nd * WAVE)), dim3(TPB), h->nd, h->ld,
+             (const double*)h->dense, (const float*)b, (float*)x);
+      return;
+    }
+  }
+  launch(h, CDGMG_K_COARSE, k_dense_gemv<T>, dim3(grid_for(h->nd * WAVE)), dim3(TPB), h->nd, h->ld,
+         (const T*)h->AinvP, b, x);
+}
+
 // hp front end: the degree-p level 0 smooths, restricts to the lower-degree
 // space (D^T T)^T (D^{-1} r), calls the lower hierarchy's V-cycle and prolongs
 // x += T z (Sec. 4, hp paragraph)
@@ -950,8 +965,7 @@ T* vcycle_t(cdgmg_handle* h, const double* r64, const double* dv, int* nparts) {
   if (L == 0) {
     DLevel& d = h->lv[0];
     launch(h, CDGMG_K_VECTOR, k_cast<double, T>, dim3(grid_for(d.n * NP)), dim3(TPB), d.n * NP, r64, (T*)d.b);
-    launch(h, CDGMG_K_COARSE, k_dense_gemv<T>, dim3(grid_for(h->nd * WAVE)), dim3(TPB), h->nd, h->ld,
-           (const T*)h->AinvP, (const T*)d.b, xs[0]);
+    coarse_solve<T>(h, (const T*)d.b, xs[0]);
     if (dv) dot_t<T>(h, xs[0], dv, nparts);
     return xs[0];
   }
@@ -981,8 +995,7 @@ T* vcycle_t(cdgmg_handle* h, const double* r64, const double* dv, int* nparts) {
   DLevel& c = h->lv[L];
   launch(h, CDGMG_K_COARSE, k_entry_c<T, NP>, dim3(grid_for(c.n, WAVE)), dim3(WAVE), c.n,
          (const int32_t*)c.child_start, (const T*)h->lv[L - 1].t, (const T*)nullptr, omega, (T*)c.b, (T*)nullptr);
-  launch(h, CDGMG_K_COARSE, k_dense_gemv<T>, dim3(grid_for(h->nd * WAVE)), dim3(TPB), h->nd, h->ld,
-         (const T*)h->AinvP, (const T*)c.b, xs[L]);
+  coarse_solve<T>(h, (const T*)c.b, xs[L]);
   // upward: the last post-sweep of a level l >= 2 also prolongs into level
   // l - 1, where a separate launch would be bound by its latency (from the
   // coarsest level, into level 0, or with nu2 = 0, a separate launch)

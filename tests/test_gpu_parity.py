@@ -110,6 +110,34 @@ def test_vcycle_fp32_close_to_oracle(name, variant):
     solver.close()
 
 
+@pytest.mark.parametrize("name", ["2d_p3", "3d_p3"])
+def test_vcycle_fp32_with_fp64_coarsest(name):
+    # the FP32 cycle with its coarsest solve in FP64 (coarse_fp64): the same
+    # cycle as the oracle's up to the FP32 rounding of the other levels
+    mesh, solver, cdg, H, kappa, parents, sizes = _build(name, mg=cm.MG_FP32, coarse_fp64=1)
+    r = np.random.default_rng(2).standard_normal(H.A[0].shape[0])
+    z = solver.vcycle(r).cpu().numpy()
+    ref = H.vcycle(r, 2, 2, 0.7)
+    assert np.linalg.norm(z - ref) <= 1e-4 * np.linalg.norm(ref)
+    solver.close()
+
+
+def test_fp64_coarsest_one_level():
+    # one level: the FP32 cycle is the FP64 inverse applied to the FP32-rounded
+    # residual, so FCG converges to the direct solution
+    mesh = mesh2d_jittered_delaunay(6, 3)
+    parents, sizes = cm.agglomerate(mesh, 1, 1, p=2)
+    solver = cm.Solver(mesh, 2, np.ones(mesh.n_elem), parents, sizes, mg_precision=cm.MG_FP32, coarse_fp64=1,
+                       tol=1e-12)
+    cdg = CDG(mesh.coords, mesh.e2v, mesh.face_bc, 2)
+    f = source_sine(cdg.nodes_phys().reshape(-1, 2))
+    u, info = solver.solve(f)
+    ref = spl.spsolve(cdg.A().tocsc(), cdg.M0() @ f)
+    assert info.rel_residual <= 1e-12
+    assert np.linalg.norm(u.cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
+    solver.close()
+
+
 # Every kernel instantiation of the coarse levels: G lanes per row in the sweep
 # and in the residual + restriction (the automatic choice takes 16, 32 or 64 by
 # the level's size and mean row length), and both workgroup sizes of the
