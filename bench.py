@@ -20,6 +20,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_2012_08024_amd.bytemodel import (facet_nodes, iteration_bytes, restrict_bytes,  # noqa: E402
+                                            smoother_bytes, spmv_bytes)
+
 METRIC = "DOFs/s to 1e-10 rel residual: FP32-MG-in-FP64-FCG vs FP64-MG; % HBM peak"
 HBM_PEAK_GBS = 8000.0
 
@@ -37,14 +40,22 @@ def kernels_hash():
 
 
 def cpu_model():
+    """The host CPU as /proc/cpuinfo names it, with family, model, stepping,
+    clock and cache of the first processor (a virtualised host may report
+    only a short model name)."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if not line.strip():
+                    break
+                k, _, v = line.partition(":")
+                info[k.strip()] = v.strip()
     except OSError:
-        pass
-    return platform.processor()
+        return platform.processor()
+    extra = ", ".join("%s %s" % (k, info[k]) for k in ("cpu family", "model", "stepping", "cpu MHz", "cache size")
+                      if k in info)
+    return "%s (%s)" % (info.get("model name", platform.processor()), extra) if extra else info.get("model name", "")
 
 
 def cpu_baseline(cfg, n_sample):
@@ -85,79 +96,6 @@ def cpu_baseline(cfg, n_sample):
     return rec, m, x
 
 
-def facet_nodes(dim, npb):
-    """Nodes of the degree-p simplex on one facet: the nonzero rows or columns
-    of a level-0 off-diagonal block in facet-trace form."""
-    p = {3: 1, 6: 2, 10: 3} if dim == 2 else {4: 1, 10: 2, 20: 3}
-    q = p[npb]
-    return q + 1 if dim == 2 else (q + 1) * (q + 2) // 2
-
-
-def smoother_bytes(nnzb0, n0, npb, s, nfn, nf):
-    """Algorithmic HBM bytes of one level-0 damped block-Jacobi sweep
-    x <- (1 - omega) x + omega D^{-1} (b - A_off x) on the facet-trace form:
-    the off-diagonal blocks' n_p x n_fn stored values, their column indices and
-    kinds (one int32 and one byte per facet slot), D^{-1}, and b, x read, x
-    written."""
-    off = nnzb0 - n0
-    return off * npb * nfn * s + 5 * n0 * nf + n0 * npb * npb * s + 3 * n0 * npb * s
-
-
-def restrict_bytes(nnzb0, n0, npb, s, nfn, nf):
-    """Level-0 residual + restriction L_e^T (b - A_rr x - A_off x): the
-    off-diagonal values, indices and kinds, the diagonal blocks, L_e, b and x
-    read, the restricted residual written."""
-    off = nnzb0 - n0
-    return off * npb * nfn * s + 5 * n0 * nf + 2 * n0 * npb * npb * s + 3 * n0 * npb * s
-
-
-def spmv_bytes(nnzb0, n0, npb, nfn, nf):
-    """Outer FP64 q = A_0 p with (p,q), (p,r): dense diagonal blocks, the
-    off-diagonal blocks' facet-trace values, indices and kinds, p, r read, q
-    written."""
-    off = nnzb0 - n0
-    return n0 * npb * npb * 8 + off * npb * nfn * 8 + 5 * n0 * nf + 3 * n0 * npb * 8
-
-
-def iteration_bytes(sizes, nnzb, npb, nfn, nf, nu1=2, nu2=2, s=4):
-    """Algorithmic bytes of one FCG(1) iteration with a V(nu1, nu2) cycle in
-    precision s (bytes) and the FP64 outer loop, per level: what each kernel
-    must read and write once (operator blocks, indices, vectors), nothing for
-    re-reads.  Level 0 runs on the facet-trace form with D^{-1}; the coarse
-    levels on D^{-1}-prescaled strips.  The first pre-sweep of every level is
-    fused with forming D^{-1} b (no operator read); the last post-sweep of
-    level 0 also reads q for the fused (z, q) dot."""
-    L = len(sizes) - 1
-    n = [int(x) for x in sizes]
-    nz = [int(x) for x in nnzb]
-    p2 = npb * npb
-    out = {}
-    for l in range(L + 1):
-        if l == L:  # coarsest: children sums, then the dense inverse product
-            ld = -(-n[l] * npb // 64) * 64
-            b = n[l - 1] * npb * s + 4 * n[l] + n[l] * npb * s if l > 0 else n[l] * npb * 8
-            b += n[l] * npb * ld * s + ld * s + n[l] * npb * s
-            out["level%d" % l] = b
-            break
-        prolong = n[l] * p2 * s + 2 * n[l] * npb * s + 4 * n[l] + n[l + 1] * npb * s
-        if l == 0:
-            sweep = smoother_bytes(nz[0], n[0], npb, s, nfn, nf)
-            entry = n[0] * npb * 8 + n[0] * p2 * s + 2 * n[0] * npb * s
-            restrict = restrict_bytes(nz[0], n[0], npb, s, nfn, nf) + n[0] * npb * s
-            b = entry + (nu1 - 1) * sweep + restrict + prolong + nu2 * sweep + n[0] * npb * 8
-        else:
-            off = nz[l] - n[l]
-            sweep = off * p2 * s + 4 * off + 3 * n[l] * npb * s + 8 * n[l]
-            entry = n[l - 1] * npb * s + 4 * n[l] + n[l] * p2 * s + 2 * n[l] * npb * s
-            restrict = sweep + n[l] * p2 * s
-            b = entry + (nu1 - 1) * sweep + restrict + prolong + nu2 * sweep
-        out["level%d" % l] = b
-    m = n[0] * npb
-    out["outer"] = (m * s + 2 * m * 8) + spmv_bytes(nz[0], n[0], npb, nfn, nf) + 6 * m * 8
-    out["total"] = sum(out.values())
-    return out
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +123,8 @@ def main():
                     help="instead of the benchmark: primal vs flux coarsening over mesh size and gamma, "
                          "consistent vs natural switch (workload or the paper's solver settings), or "
                          "convection-diffusion under refinement; prints one JSON line with the table")
+    ap.add_argument("--sizes", default="",
+                    help="with --study size: comma-separated mesh sizes n (default 100 ... 894)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the solver runs on one GPU only (multi-GPU domain decomposition is "
@@ -199,7 +139,8 @@ def main():
         if kind == "convection":
             rows = studies.study_convection(log=log)
         elif kind == "size":
-            rows = studies.study_size(log=log)
+            kw = {"ns": tuple(int(v) for v in args.sizes.split(","))} if args.sizes else {}
+            rows = studies.study_size(log=log, **kw)
         else:
             fn = studies.study_coarsening if kind == "coarsening" else studies.study_switch
             rows = fn(setting=setting or "workload", log=log)

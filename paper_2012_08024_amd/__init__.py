@@ -10,6 +10,10 @@ import ctypes
 import os
 
 import numpy as np
+# torch before the library: torch ships its own HIP runtime under the same
+# soname, and whichever is loaded first serves the whole process, so loading
+# torch first makes the library run on torch's runtime and device context
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.path.join(_HERE, "libcdgmg.so")

@@ -151,37 +151,62 @@ __global__ __launch_bounds__(TPB) void k_diag_inverse(int64_t n, const int64_t* 
 // K7 (Galerkin): coarse block k = (I, t) accumulates L_e^T A_f(e, w) L_c over its
 // plan entries (fixed order -> deterministic).  One workgroup per coarse block,
 // one thread per entry (i, j); the operands of up to GCH plan entries are
-// staged in LDS at once so their loads overlap.
+// staged in LDS at once so their loads overlap.  The fine blocks of one
+// sliced 64-row tile share cache lines, and the children of consecutive
+// coarse rows are consecutive fine rows: consecutive coarse blocks therefore
+// go to one XCD (xcd_slice), so that those lines are fetched into one L2
+// instead of into all eight.
 template <int NP>
 __global__ void k_galerkin(int64_t nblk, const int32_t* __restrict__ blk_row, const int64_t* __restrict__ row_blk,
                            const int64_t* __restrict__ plan_ptr, const int32_t* __restrict__ plan_e,
-                           const int32_t* __restrict__ plan_w, const int32_t* __restrict__ fcols,
-                           const int64_t* __restrict__ fsblk, const double* __restrict__ Af,
-                           const double* __restrict__ Lf, const int64_t* __restrict__ csblk,
-                           double* __restrict__ Ac) {
+                           const int32_t* __restrict__ plan_c, const int64_t* __restrict__ plan_a,
+                           const double* __restrict__ Af, const double* __restrict__ Lf,
+                           const int64_t* __restrict__ csblk, double* __restrict__ Ac) {
   constexpr int NP2 = NP * NP;
   constexpr int GCH = NP2 <= 100 ? 8 : 2;
+  constexpr int NT = (NP2 + WAVE - 1) / WAVE * WAVE;  // threads per workgroup
+  constexpr int NX = (GCH * NP2 + NT - 1) / NT;       // staged values per thread and operand
   __shared__ double sA[GCH][NP2], sLe[GCH][NP2], sLc[GCH][NP2], sT[GCH][NP2];
-  const int64_t k = blockIdx.x;
+  __shared__ int64_t sa[GCH];
+  __shared__ int32_t se[GCH], sc[GCH];
+  const int64_t k = xcd_slice();
   if (k >= nblk) return;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x;
   const int i = tid / NP, j = tid % NP;
   double acc = 0.0;
   const int64_t q0 = plan_ptr[k], q1 = plan_ptr[k + 1];
   for (int64_t qc = q0; qc < q1; qc += GCH) {
     const int nc = (int)(q1 - qc < GCH ? q1 - qc : GCH);
-    for (int x = tid; x < nc * NP2; x += nt) {
-      const int t = x / NP2, ij = x % NP2;
-      const int32_t e = plan_e[qc + t];
-      const int w = plan_w[qc + t];
-      const int64_t Be = fsblk[e / WAVE];
-      const int32_t c = fcols[Be + (int64_t)WAVE * w + e % WAVE];
-      sA[t][ij] = Af[blk_off(Be, w, NP2, ij, e % WAVE)];
-      sLe[t][ij] = Lf[row_off(e, NP2, ij)];
-      sLc[t][ij] = Lf[row_off(c, NP2, ij)];
+    if (tid < nc) {
+      sa[tid] = plan_a[qc + tid];
+      se[tid] = plan_e[qc + tid];
+      sc[tid] = plan_c[qc + tid];
     }
     __syncthreads();
-    for (int x = tid; x < nc * NP2; x += nt) {
+    // all of a thread's operand loads are issued before the first LDS store
+    double va[NX], ve[NX], vc[NX];
+#pragma unroll
+    for (int u = 0; u < NX; ++u) {
+      const int x = tid + u * NT;
+      if (x < nc * NP2) {
+        const int t = x / NP2, ij = x % NP2;
+        va[u] = Af[sa[t] + (int64_t)ij * WAVE];
+        ve[u] = Lf[row_off(se[t], NP2, ij)];
+        vc[u] = Lf[row_off(sc[t], NP2, ij)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NX; ++u) {
+      const int x = tid + u * NT;
+      if (x < nc * NP2) {
+        const int t = x / NP2, ij = x % NP2;
+        sA[t][ij] = va[u];
+        sLe[t][ij] = ve[u];
+        sLc[t][ij] = vc[u];
+      }
+    }
+    __syncthreads();
+    for (int x = tid; x < nc * NP2; x += NT) {
       const int t = x / NP2, ij = x % NP2, ii = ij / NP, jj = ij % NP;
       double s = 0.0;
       for (int m = 0; m < NP; ++m) s += sA[t][ii * NP + m] * sLc[t][m * NP + jj];
@@ -288,22 +313,25 @@ __global__ void k_block_inverse_bm(int64_t n, const double* __restrict__ src, do
 }
 
 // coarsest level: scatter the sliced blocks into a dense row-major matrix
-// dense[(r n_p + i) ld + c n_p + j] += A(r, c)_{ij} over the stored blocks
+// dense[(r n_p + i) ld + c n_p + j] += A(r, c)_{ij} over the stored blocks;
+// one thread per (row, entry (i, j)) walks the row's slots in order (padding
+// slots repeat the diagonal column with zero blocks, so one thread must own
+// each destination)
 template <int NP>
 __global__ void k_dense_scatter(int64_t n, int64_t ld, const int32_t* __restrict__ cols,
                                 const int64_t* __restrict__ sblk, const double* __restrict__ A,
                                 double* __restrict__ dense) {
   constexpr int NP2 = NP * NP;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * NP2) return;
+  const int64_t r = t / NP2;
+  const int ij = (int)(t % NP2), i = ij / NP, j = ij % NP;
   const int lane = (int)(r % WAVE);
   const int64_t B = sblk[r / WAVE];
   const int W = (int)((sblk[r / WAVE + 1] - B) / WAVE);
   for (int w = 0; w < W; ++w) {
     const int32_t c = cols[B + (int64_t)WAVE * w + lane];
-    for (int i = 0; i < NP; ++i)
-      for (int j = 0; j < NP; ++j)
-        dense[(r * NP + i) * ld + (int64_t)c * NP + j] += A[blk_off(B, w, NP2, i * NP + j, lane)];
+    dense[(r * NP + i) * ld + (int64_t)c * NP + j] += A[blk_off(B, w, NP2, ij, lane)];
   }
 }
 
@@ -311,9 +339,12 @@ __global__ void k_dense_scatter(int64_t n, int64_t ld, const int32_t* __restrict
 // Blocked Gauss-Jordan inversion in place, without pivoting (the coarsest
 // Galerkin operator is SPD; a flux-coarsened one is only checked for nonzero
 // pivots), on an ld x ld matrix, ld a multiple of GJB, whose padding is the
-// identity.  For each diagonal block K, with P = A_KK^{-1}:
-//   A_KJ <- P A_KJ (J != K);  A_IJ <- A_IJ - A_IK A_KJ (I, J != K);
+// identity.  For each diagonal block K, with P = A_KK^{-1} and all right-hand
+// sides taken before the step:
+//   A_KJ <- P A_KJ (J != K);  A_IJ <- A_IJ - A_IK P A_KJ (I, J != K);
 //   A_IK <- -A_IK P (I != K);  A_KK <- P.
+// Three launches per step: the pivot block, both panels into buffers, then
+// the trailing update and the panel copies from those buffers.
 constexpr int GJB = 64;
 
 // dense <- 0 with ones on the padding diagonal (i = j >= nd)
@@ -337,115 +368,92 @@ __global__ void k_dense_diag(int64_t ld, const double* __restrict__ dense, doubl
 // holds the constants.
 constexpr double GJ_SING = 1e-11;
 
-// P = A_KK^{-1} by unblocked Gauss-Jordan (one workgroup of 256, the block in
-// registers);
+// P = A_KK^{-1} by unblocked Gauss-Jordan (one workgroup of GJT threads, the
+// block in registers);
 // writes P into A_KK and into Pout; err = 1 on a pivot at or below
 // GJ_SING diag0 (definite) or a zero pivot
-__global__ __launch_bounds__(256) void k_gj_pivot(int64_t ld, int K, double* __restrict__ dense,
+constexpr int GJT = 1024;
+__global__ __launch_bounds__(GJT) void k_gj_pivot(int64_t ld, int K, double* __restrict__ dense,
                                                   double* __restrict__ Pout, const double* __restrict__ diag0,
                                                   int* __restrict__ err, int definite) {
-  // thread (i0, j) keeps rows i0 + 4 m, m < 16, of column j in registers; per
-  // step only the pivot row and column go through LDS, double-buffered by the
-  // step's parity so that one barrier per step suffices
-  constexpr int RM = GJB / 4;
+  // thread (i0, j), i0 < NW = GJT / GJB, keeps rows i0 + NW m, m < RM, of
+  // column j in registers; per step only the pivot row and column go through
+  // LDS, double-buffered by the step's parity so that one barrier per step
+  // suffices.  The 64 steps are a serial chain: spreading the block over 16
+  // wavefronts keeps each step's work per wavefront (RM products) short.  The
+  // pivot is tested by the thread that holds it, against the original
+  // diagonal entry loaded up front.
+  constexpr int NW = GJT / GJB, RM = GJB / NW;
   __shared__ double rowk[2][GJB], colk[2][GJB];
   const int tid = threadIdx.x, j = tid % GJB, i0 = tid / GJB;
   double* Akk = dense + (int64_t)K * GJB * ld + (int64_t)K * GJB;
   double v[RM];
 #pragma unroll
-  for (int m = 0; m < RM; ++m) v[m] = Akk[(int64_t)(i0 + 4 * m) * ld + j];
+  for (int m = 0; m < RM; ++m) v[m] = Akk[(int64_t)(i0 + NW * m) * ld + j];
+  const double dj = diag0[(int64_t)K * GJB + j];
   bool bad = false;
 #pragma unroll
   for (int k = 0; k < GJB; ++k) {
     const int b = k & 1;
-    if (i0 == k % 4) rowk[b][j] = v[k / 4];
+    if (i0 == k % NW) {
+      const double pk = v[k / NW];
+      rowk[b][j] = pk;
+      if (j == k) bad = bad || (definite ? !(pk > GJ_SING * dj) : !(pk != 0.0 && pk == pk));
+    }
     if (j == k)
 #pragma unroll
-      for (int m = 0; m < RM; ++m) colk[b][i0 + 4 * m] = v[m];
+      for (int m = 0; m < RM; ++m) colk[b][i0 + NW * m] = v[m];
     __syncthreads();
     const double p = rowk[b][k];
-    if (tid == 0 && (definite ? !(p > GJ_SING * diag0[(int64_t)K * GJB + k]) : !(p != 0.0 && p == p))) bad = true;
     const double ip = 1.0 / p;
     const double rj = rowk[b][j];
 #pragma unroll
     for (int m = 0; m < RM; ++m) {
-      const int i = i0 + 4 * m;
+      const int i = i0 + NW * m;
       const double ci = colk[b][i];
       const double gen = v[m] - ci * rj * ip;
       v[m] = (i == k) ? ((j == k) ? ip : rj * ip) : ((j == k) ? -ci * ip : gen);
     }
   }
-  if (tid == 0 && bad) *err = 1;
+  if (bad) *err = 1;
 #pragma unroll
   for (int m = 0; m < RM; ++m) {
-    const int i = i0 + 4 * m;
+    const int i = i0 + NW * m;
     Akk[(int64_t)i * ld + j] = v[m];
     Pout[i * GJB + j] = v[m];
   }
 }
 
-// row panel: A_KJ <- P A_KJ for J != K (workgroup J)
-__global__ __launch_bounds__(256) void k_gj_row(int64_t ld, int K, double* __restrict__ dense,
-                                                const double* __restrict__ P) {
-  const int J = blockIdx.x;
-  if (J == K) return;
-  __shared__ double Ps[GJB][GJB];
-  __shared__ double Bs[GJB][GJB];
-  const int tid = threadIdx.x;
-  double* Akj = dense + (int64_t)K * GJB * ld + (int64_t)J * GJB;
-  for (int e = tid; e < GJB * GJB; e += 256) {
-    Ps[e / GJB][e % GJB] = P[e];
-    Bs[e / GJB][e % GJB] = Akj[(int64_t)(e / GJB) * ld + e % GJB];
+// The panel and trailing products below share one tile product: C = X Y for
+// GJB x GJB tiles, X staged transposed (Xt[k][i] = X(i, k)) and Y as is, both
+// in LDS; 256 threads, each with a 4 x 4 block of C in registers, summing over
+// k in ascending order.  The staging issues all of a thread's global loads
+// before its first LDS store, so a workgroup waits for one memory latency,
+// not sixteen.  Xt's rows are padded by two entries: its transposed stores
+// then spread over the banks while its rows stay 16-byte aligned.
+constexpr int GJP = GJB + 2;
+
+__device__ __forceinline__ void gj_stage(double (*Xt)[GJP], double (*Ys)[GJB], const double* X, int64_t ldx,
+                                         const double* Y, int64_t ldy) {
+  constexpr int NE = GJB * GJB / 256;
+  double xv[NE], yv[NE];
+#pragma unroll
+  for (int m = 0; m < NE; ++m) {
+    const int e = threadIdx.x + 256 * m, r = e / GJB, c = e % GJB;
+    xv[m] = X[(int64_t)r * ldx + c];
+    yv[m] = Y[(int64_t)r * ldy + c];
+  }
+#pragma unroll
+  for (int m = 0; m < NE; ++m) {
+    const int e = threadIdx.x + 256 * m, r = e / GJB, c = e % GJB;
+    Xt[c][r] = xv[m];
+    Ys[r][c] = yv[m];
   }
   __syncthreads();
-  for (int e = tid; e < GJB * GJB; e += 256) {
-    const int i = e / GJB, j = e % GJB;
-    double acc = 0.0;
-    for (int k = 0; k < GJB; ++k) acc += Ps[i][k] * Bs[k][j];
-    Akj[(int64_t)i * ld + j] = acc;
-  }
 }
 
-// column panel: A_IK <- -A_IK P for I != K (workgroup I)
-__global__ __launch_bounds__(256) void k_gj_col(int64_t ld, int K, double* __restrict__ dense,
-                                                const double* __restrict__ P) {
-  const int I = blockIdx.x;
-  if (I == K) return;
-  __shared__ double Ps[GJB][GJB];
-  __shared__ double Bs[GJB][GJB];
-  const int tid = threadIdx.x;
-  double* Aik = dense + (int64_t)I * GJB * ld + (int64_t)K * GJB;
-  for (int e = tid; e < GJB * GJB; e += 256) {
-    Ps[e / GJB][e % GJB] = P[e];
-    Bs[e / GJB][e % GJB] = Aik[(int64_t)(e / GJB) * ld + e % GJB];
-  }
-  __syncthreads();
-  for (int e = tid; e < GJB * GJB; e += 256) {
-    const int i = e / GJB, j = e % GJB;
-    double acc = 0.0;
-    for (int k = 0; k < GJB; ++k) acc += Bs[i][k] * Ps[k][j];
-    Aik[(int64_t)i * ld + j] = -acc;
-  }
-}
-
-// trailing update: A_IJ <- A_IJ - A_IK A_KJ for I, J != K (workgroup (J, I));
-// 256 threads, 4 x 4 outputs each; A_IK is staged transposed
-__global__ __launch_bounds__(256) void k_gj_update(int64_t ld, int K, double* __restrict__ dense) {
-  const int J = blockIdx.x, I = blockIdx.y;
-  if (I == K || J == K) return;
-  __shared__ double At[GJB][GJB];  // At[k][i] = A_IK(i, k)
-  __shared__ double Bs[GJB][GJB];  // Bs[k][j] = A_KJ(k, j)
-  const int tid = threadIdx.x;
-  const double* Aik = dense + (int64_t)I * GJB * ld + (int64_t)K * GJB;
-  const double* Akj = dense + (int64_t)K * GJB * ld + (int64_t)J * GJB;
-  for (int e = tid; e < GJB * GJB; e += 256) {
-    const int r = e / GJB, c = e % GJB;
-    At[c][r] = Aik[(int64_t)r * ld + c];
-    Bs[r][c] = Akj[(int64_t)r * ld + c];
-  }
-  __syncthreads();
-  const int ti = tid / 16, tj = tid % 16;
-  double acc[4][4];
+__device__ __forceinline__ void gj_tile(const double (*Xt)[GJP], const double (*Ys)[GJB], double acc[4][4]) {
+  const int ti = threadIdx.x / 16, tj = threadIdx.x % 16;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -453,19 +461,78 @@ __global__ __launch_bounds__(256) void k_gj_update(int64_t ld, int K, double* __
   for (int k = 0; k < GJB; ++k) {
     double av[4], bv[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) av[a] = At[k][ti * 4 + a];
+    for (int a = 0; a < 4; ++a) av[a] = Xt[k][ti * 4 + a];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) bv[b] = Bs[k][tj * 4 + b];
+    for (int b = 0; b < 4; ++b) bv[b] = Ys[k][tj * 4 + b];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
   }
-  double* Aij = dense + (int64_t)I * GJB * ld + (int64_t)J * GJB;
+}
+
+// C (ldc) = s * acc, the thread's 4 x 4 block
+__device__ __forceinline__ void gj_store(double* C, int64_t ldc, const double acc[4][4], double s) {
+  const int ti = threadIdx.x / 16, tj = threadIdx.x % 16;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) Aij[(int64_t)(ti * 4 + a) * ld + tj * 4 + b] -= acc[a][b];
+    for (int b = 0; b < 4; ++b) C[(int64_t)(ti * 4 + a) * ldc + tj * 4 + b] = s * acc[a][b];
+}
+
+// Both panels of step K, from the matrix before the step, into buffers beside
+// it (one launch; workgroup b < nbk takes row block J = b, the others column
+// block I = b - nbk):
+//   R_J = P A_KJ and Ko_J = A_KJ (row panel, [GJB][ld]);  C_I = -A_IK P ([ld][GJB]).
+__global__ __launch_bounds__(256) void k_gj_panels(int64_t ld, int K, int nbk, const double* __restrict__ dense,
+                                                   const double* __restrict__ P, double* __restrict__ R,
+                                                   double* __restrict__ Ko, double* __restrict__ C) {
+  const int b = blockIdx.x;
+  const bool row = b < nbk;
+  const int J = row ? b : b - nbk;
+  if (J == K) return;
+  __shared__ double Xt[GJB][GJP], Ys[GJB][GJB];
+  double acc[4][4];
+  if (row) {
+    const double* Akj = dense + (int64_t)K * GJB * ld + (int64_t)J * GJB;
+    gj_stage(Xt, Ys, P, GJB, Akj, ld);
+    gj_tile(Xt, Ys, acc);
+    gj_store(R + (int64_t)J * GJB, ld, acc, 1.0);
+    for (int e = threadIdx.x; e < GJB * GJB; e += 256)
+      Ko[(int64_t)(e / GJB) * ld + (int64_t)J * GJB + e % GJB] = Ys[e / GJB][e % GJB];
+  } else {
+    const double* Aik = dense + (int64_t)J * GJB * ld + (int64_t)K * GJB;
+    gj_stage(Xt, Ys, Aik, ld, P, GJB);
+    gj_tile(Xt, Ys, acc);
+    gj_store(C + (int64_t)J * GJB * GJB, GJB, acc, -1.0);
+  }
+}
+
+// the rest of step K (workgroup (J, I)), reading only the panel buffers:
+//   A_IJ <- A_IJ - A_IK P A_KJ = A_IJ + C_I Ko_J   (I, J != K)
+//   A_KJ <- R_J (J != K);  A_IK <- C_I (I != K)
+__global__ __launch_bounds__(256) void k_gj_update(int64_t ld, int K, double* __restrict__ dense,
+                                                   const double* __restrict__ R, const double* __restrict__ Ko,
+                                                   const double* __restrict__ C) {
+  const int J = blockIdx.x, I = blockIdx.y;
+  if (I == K && J == K) return;
+  double* Aij = dense + (int64_t)I * GJB * ld + (int64_t)J * GJB;
+  if (I == K || J == K) {
+    const double* src = I == K ? R + (int64_t)J * GJB : C + (int64_t)I * GJB * GJB;
+    const int64_t lds = I == K ? ld : GJB;
+    for (int e = threadIdx.x; e < GJB * GJB; e += 256)
+      Aij[(int64_t)(e / GJB) * ld + e % GJB] = src[(int64_t)(e / GJB) * lds + e % GJB];
+    return;
+  }
+  __shared__ double Xt[GJB][GJP], Ys[GJB][GJB];
+  gj_stage(Xt, Ys, C + (int64_t)I * GJB * GJB, GJB, Ko + (int64_t)J * GJB, ld);
+  double acc[4][4];
+  gj_tile(Xt, Ys, acc);
+  const int ti = threadIdx.x / 16, tj = threadIdx.x % 16;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) Aij[(int64_t)(ti * 4 + a) * ld + tj * 4 + b] += acc[a][b];
 }
 
 template <typename S, typename D>
@@ -1441,7 +1508,9 @@ __global__ void k_scale_wpr(int64_t nnzb, const int32_t* __restrict__ blk_row, c
                             const int64_t* __restrict__ woff, const double* __restrict__ A,
                             const double* __restrict__ Dinv, T* __restrict__ R) {
   constexpr int NP2 = NP * NP;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // consecutive blocks (consecutive rows, sharing the lines of their
+  // lane-interleaved D^{-1} and A entries) on one XCD
+  const int64_t idx = xcd_slice() * blockDim.x + threadIdx.x;
   if (idx >= nnzb * NP2) return;
   const int64_t b = idx / NP2;
   const int ij = (int)(idx % NP2), i = ij / NP, j = ij % NP;

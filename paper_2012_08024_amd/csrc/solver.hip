@@ -130,7 +130,8 @@ struct DLevel {
   int64_t* row_blk = nullptr;
   int64_t* plan_ptr = nullptr;
   int32_t* plan_e = nullptr;
-  int32_t* plan_w = nullptr;
+  int32_t* plan_c = nullptr;  // column of each plan entry's fine block
+  int64_t* plan_a = nullptr;  // offset of each plan entry's fine block in the sliced fine operator
   void *b = nullptr, *x = nullptr, *xb = nullptr, *t = nullptr;
   // flux-form coarsening (building level l+1 from this level l)
   double *Mbm = nullptr, *Minv = nullptr, *G = nullptr, *X = nullptr, *Y = nullptr;
@@ -211,6 +212,7 @@ struct cdgmg_handle {
   // coarsest
   int64_t nd = 0, ld = 0;
   double *dense = nullptr, *gjP = nullptr;  // coarsest operator -> its inverse (ld x ld, FP64); pivot block
+  double *gjR = nullptr, *gjK = nullptr, *gjC = nullptr;  // panel buffers of one elimination step
   double* gjD = nullptr;                     // its diagonal before elimination
   void* AinvP = nullptr;  // A_L^{-1} in the multigrid precision, leading dimension ld
   // outer vectors (internal order, FP64)
@@ -222,6 +224,12 @@ struct cdgmg_handle {
   double* hscal = nullptr;
   int* herr = nullptr;
   hipEvent_t ev_rr = nullptr;  // ||r||^2 of the last update copied to hscal
+  // operator builds: a second stream for the work beside the critical chain
+  // (none for handles that must not create resources), its fork and join
+  // events, and its own error flag
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int* err_side = nullptr;
   // GMRES: Arnoldi basis V [(m+1) x gm_ld], Z = B V [m x gm_ld], Hessenberg
   // columns (two Gram-Schmidt passes and the norm), partial sums, y
   double *gmV = nullptr, *gmZ = nullptr, *gmH = nullptr, *gmPart = nullptr, *gmY = nullptr;
@@ -336,17 +344,49 @@ std::vector<T> to_rows(const std::vector<T>& src, int64_t n, int np2) {
   return out;
 }
 
-int check_err(cdgmg_handle* h, int code, const char* what) {
-  HIPCHK(hipMemcpyAsync(h->herr, h->err, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+int check_flag(cdgmg_handle* h, int* flag, int code, const char* what) {
+  HIPCHK(hipMemcpyAsync(h->herr, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   if (*h->herr) {
     *h->herr = 0;
-    HIPCHK(hipMemsetAsync(h->err, 0, sizeof(int), h->stream));
+    HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
     set_error(what);
     return code;
   }
   return CDGMG_OK;
 }
+int check_err(cdgmg_handle* h, int code, const char* what) { return check_flag(h, h->err, code, what); }
+
+// Work of an operator build that is off its critical chain (assembly ->
+// Galerkin products level by level -> coarsest inverse) runs on the handle's
+// second stream: fork() sends the following launches there after all work
+// enqueued so far, back() returns to the main stream, and the join (at
+// destruction of the guard, so on every return path) makes the main stream
+// wait for the side work.  Without a second stream all of it stays in order
+// on the main stream.
+struct SideWork {
+  cdgmg_handle* h;
+  hipStream_t main;
+  bool used = false;
+  explicit SideWork(cdgmg_handle* hh) : h(hh), main(hh->stream) {}
+  bool on() const { return h->side != nullptr; }
+  void fork() {
+    if (!on()) return;
+    (void)hipEventRecord(h->ev_fork, main);
+    (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
+    h->stream = h->side;
+    used = true;
+  }
+  void back() { h->stream = main; }
+  void join() {
+    h->stream = main;
+    if (!used) return;
+    (void)hipEventRecord(h->ev_join, h->side);
+    (void)hipStreamWaitEvent(main, h->ev_join, 0);
+    used = false;
+  }
+  ~SideWork() { join(); }
+};
 
 // ---------------------------------------------------------------- device setup
 // Flux-form coarsening: device arrays for M_l, M_l^{-1}, G_l, X, Y per level and
@@ -558,7 +598,19 @@ int upload_problem(cdgmg_handle* h) {
       RETURN_IF(upload(h, &D.row_blk, H.row_blk));
       RETURN_IF(upload(h, &D.plan_ptr, H.plan_ptr));
       RETURN_IF(upload(h, &D.plan_e, H.plan_e));
-      RETURN_IF(upload(h, &D.plan_w, H.plan_w));
+      // each plan entry's fine block (e, w): its offset in the sliced fine
+      // operator and its column, resolved once here (kappa-independent), so
+      // that the Galerkin kernel's loads wait on one index load, not three
+      const Level& F = P.lv[l - 1];
+      std::vector<int32_t> pc(H.plan_e.size());
+      std::vector<int64_t> pa(H.plan_e.size());
+      for (size_t q = 0; q < pc.size(); ++q) {
+        const int64_t e = H.plan_e[q], B = F.slice_blk[e / SLICE] + (int64_t)SLICE * H.plan_w[q];
+        pc[q] = F.cols[B + e % SLICE];
+        pa[q] = B * np2 + e % SLICE;
+      }
+      RETURN_IF(upload(h, &D.plan_c, pc));
+      RETURN_IF(upload(h, &D.plan_a, pa));
     }
     const size_t vb = (size_t)D.ns * SLICE * np * sizeof(double);
     double* tmp;
@@ -598,6 +650,9 @@ int upload_problem(cdgmg_handle* h) {
     h->ld = (h->nd + GJB - 1) / GJB * GJB;
     RETURN_IF(dalloc(h, &h->dense, (size_t)h->ld * h->ld));
     RETURN_IF(dalloc(h, &h->gjP, (size_t)GJB * GJB));
+    RETURN_IF(dalloc(h, &h->gjR, (size_t)GJB * h->ld));
+    RETURN_IF(dalloc(h, &h->gjK, (size_t)GJB * h->ld));
+    RETURN_IF(dalloc(h, &h->gjC, (size_t)GJB * h->ld));
     RETURN_IF(dalloc(h, &h->gjD, (size_t)h->ld));
     if (fp32 && !h->o.coarse_fp64) {
       float* tmp;
@@ -633,6 +688,8 @@ int upload_problem(cdgmg_handle* h) {
   RETURN_IF(dalloc(h, &h->part, 2 * (size_t)h->nparts));
   RETURN_IF(dalloc(h, &h->err, 1));
   RETURN_IF(dzero(h, h->err, sizeof(int)));
+  RETURN_IF(dalloc(h, &h->err_side, 1));
+  RETURN_IF(dzero(h, h->err_side, sizeof(int)));
   RETURN_IF(host_alloc(h, &h->hscal, SC_N));
   RETURN_IF(host_alloc(h, &h->herr, 1));
   if (P.flux) RETURN_IF(upload_flux(h));
@@ -658,12 +715,12 @@ int upload_problem(cdgmg_handle* h) {
 // the off-diagonal blocks of the sliced A_0 (FP64) in facet-trace form, in T;
 // the dropped entries are checked to be zero (err)
 template <typename T, int NP>
-void compress0(cdgmg_handle* h, T* out) {
+void compress0(cdgmg_handle* h, T* out, int* err) {
   DLevel& D = h->lv[0];
   NF_DISPATCH(h->P.nf, {
     constexpr int NPF = NP * FacetTab<NP, NF>::NFN;
     launch(h, -1, k_compress0<T, NP, NF>, dim3(grid_for(D.ns * NF * NPF * WAVE)), dim3(TPB), D.n, D.ns,
-           (const double*)D.A64, (const int8_t*)D.meta, out, h->err);
+           (const double*)D.A64, (const int8_t*)D.meta, out, err);
   });
 }
 
@@ -673,7 +730,14 @@ template <typename T, int NP>
 void level0_operators(cdgmg_handle* h) {
   constexpr int NP2 = NP * NP;
   DLevel& D = h->lv[0];
-  if ((void*)D.Ac != (void*)h->A0c) compress0<T, NP>(h, (T*)D.Ac);
+  if ((void*)D.Ac != (void*)h->A0c) {
+    if (h->A0c) {  // the FP64 facet-trace copy, compressed and checked already: same layout
+      const int64_t nc = D.ns * SLICE * h->P.nf * NP * fnodes(NP, h->P.nf);
+      launch(h, -1, k_cast<double, T>, dim3(grid_for(nc)), dim3(TPB), nc, (const double*)h->A0c, (T*)D.Ac);
+    } else {
+      compress0<T, NP>(h, (T*)D.Ac, h->err);
+    }
+  }
   NF_DISPATCH(h->P.nf, launch(h, -1, k_diag0<T, NP, NF>, dim3(grid_for(D.ns * NP2 * WAVE)), dim3(TPB), D.ns,
                               (const double*)D.A64, (T*)D.Ad));
   if ((void*)D.Dm != (void*)D.D64) {
@@ -757,9 +821,16 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed) {
                           h->stream));
   }
   h->transposed = transposed;
+  const char* not_trace = "setup: a level-0 off-diagonal block is not in facet-trace form";
+  // the facet-trace copy of A_0 (outer loop, and source of the V-cycle's
+  // copy) beside the Galerkin chain, which reads the sliced A_0
+  SideWork side(h);
+  const bool fork = side.on() && h->A0c && !h->inner;
   if (h->A0c) {
-    NP_DISPATCH(np, compress0<double, NP>(h, h->A0c));
-    RETURN_IF(check_err(h, CDGMG_ERR_MESH, "setup: a level-0 off-diagonal block is not in facet-trace form"));
+    if (fork) side.fork();
+    NP_DISPATCH(np, compress0<double, NP>(h, h->A0c, fork ? h->err_side : h->err));
+    side.back();
+    if (!fork) RETURN_IF(check_err(h, CDGMG_ERR_MESH, not_trace));
   }
   if (h->inner) return build_hp(h);
   const bool flux = h->P.flux;
@@ -789,9 +860,8 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed) {
     }
     NP_DISPATCH(np, launch(h, -1, k_galerkin<NP>, dim3((unsigned)c.nnzb), dim3(tpb), c.nnzb,
                            (const int32_t*)c.blk_row, (const int64_t*)c.row_blk, (const int64_t*)c.plan_ptr,
-                           (const int32_t*)c.plan_e, (const int32_t*)c.plan_w, (const int32_t*)f.cols,
-                           (const int64_t*)f.sblk, (const double*)f.A64, (const double*)f.L64,
-                           (const int64_t*)c.sblk, c.A64));
+                           (const int32_t*)c.plan_e, (const int32_t*)c.plan_c, (const int64_t*)c.plan_a,
+                           (const double*)f.A64, (const double*)f.L64, (const int64_t*)c.sblk, c.A64));
     if (flux)  // A_{l+1} += -X^T M_l^{-1} X + Y^T M_{l+1}^{-1} Y
       NP_DISPATCH(np, launch(h, -1, k_triple<NP>, dim3((unsigned)f.nso), dim3(tpb), f.nso, (const TPOut*)f.so,
                              (const int64_t*)f.spp, (const TPDev*)f.sp, 1));
@@ -799,30 +869,35 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed) {
   RETURN_IF(check_err(h, CDGMG_ERR_SINGULAR, flux ? "setup: a diagonal or mass block is singular"
                                                   : "setup: a diagonal block is not positive definite"));
   // prescaled V-cycle operators D^{-1} A (off-diagonal), D^T L_e, and D^{-1} in the
-  // multigrid precision
+  // multigrid precision, beside the coarsest inverse
+  if (fork) side.fork();
   if (h->o.mg_precision == CDGMG_MG_FP32) {
     NP_DISPATCH(np, prescale<float, NP>(h));
   } else {
     NP_DISPATCH(np, prescale<double, NP>(h));
   }
-  RETURN_IF(check_err(h, CDGMG_ERR_MESH, "setup: a level-0 off-diagonal block is not in facet-trace form"));
+  side.back();
+  if (!fork) RETURN_IF(check_err(h, CDGMG_ERR_MESH, not_trace));
   // coarsest: dense scatter + Gauss-Jordan inverse (ping-pong)
   DLevel& cl = h->lv[h->L];
   const int64_t nd = h->nd, ld = h->ld;
   launch(h, -1, k_dense_init, dim3(grid_for(ld * ld)), dim3(TPB), nd, ld, h->dense);
-  NP_DISPATCH(np, launch(h, -1, k_dense_scatter<NP>, dim3(grid_for(cl.n)), dim3(TPB), cl.n, ld,
+  NP_DISPATCH(np, launch(h, -1, k_dense_scatter<NP>, dim3(grid_for(cl.n * np2)), dim3(TPB), cl.n, ld,
                          (const int32_t*)cl.cols, (const int64_t*)cl.sblk, (const double*)cl.A64, h->dense));
   launch(h, -1, k_dense_diag, dim3(grid_for(ld)), dim3(TPB), ld, (const double*)h->dense, h->gjD);
   const int nbk = (int)(ld / GJB);
   for (int K = 0; K < nbk; ++K) {
-    launch(h, -1, k_gj_pivot, dim3(1), dim3(256), ld, K, h->dense, h->gjP, (const double*)h->gjD, h->err,
+    launch(h, -1, k_gj_pivot, dim3(1), dim3(GJT), ld, K, h->dense, h->gjP, (const double*)h->gjD, h->err,
            definite);
     if (nbk > 1) {
-      launch(h, -1, k_gj_row, dim3(nbk), dim3(256), ld, K, h->dense, (const double*)h->gjP);
-      launch(h, -1, k_gj_update, dim3(nbk, nbk), dim3(256), ld, K, h->dense);
-      launch(h, -1, k_gj_col, dim3(nbk), dim3(256), ld, K, h->dense, (const double*)h->gjP);
+      launch(h, -1, k_gj_panels, dim3(2 * nbk), dim3(256), ld, K, nbk, (const double*)h->dense,
+             (const double*)h->gjP, h->gjR, h->gjK, h->gjC);
+      launch(h, -1, k_gj_update, dim3(nbk, nbk), dim3(256), ld, K, h->dense, (const double*)h->gjR,
+             (const double*)h->gjK, (const double*)h->gjC);
     }
   }
+  side.join();
+  if (fork) RETURN_IF(check_flag(h, h->err_side, CDGMG_ERR_MESH, not_trace));
   RETURN_IF(check_err(h, CDGMG_ERR_SINGULAR, flux ? "setup: the coarsest operator is singular"
                                                   : "setup: the coarsest operator is not positive definite"));
   if (h->o.mg_precision == CDGMG_MG_FP32 && !h->o.coarse_fp64)
@@ -1568,6 +1643,11 @@ int prepare(const cdgmg_mesh* mesh, int p, const cdgmg_hierarchy* hier, const cd
 
 // device half of setup: operators for kappa, block inverses, coarsest inverse
 int finish_setup(cdgmg_handle* h, const double* kappa_dev) {
+  if (h->pinned && !h->inner) {  // not for the no-allocation setup
+    HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+  }
   RETURN_IF(build_operators(h, kappa_dev, false));
   if (hipStreamSynchronize(h->stream) != hipSuccess) {
     set_error("setup: device error");
@@ -1936,6 +2016,12 @@ int cdgmg_destroy(cdgmg_handle* h) {
   if (h->inner) cdgmg_destroy(h->inner);
   // the device work of this handle ends before the caller may reuse the workspace
   if (h->ws->base) (void)hipStreamSynchronize(h->stream);
+  if (h->side) {
+    (void)hipStreamSynchronize(h->side);
+    (void)hipStreamDestroy(h->side);
+  }
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   for (auto e : h->pool) (void)hipEventDestroy(e);
   if (h->ev_rr) (void)hipEventDestroy(h->ev_rr);
   host_free(h, h->hgmH);

@@ -30,6 +30,7 @@ import numpy as np
 
 from . import (COARSEN_FLUX, COARSEN_PRIMAL, MG_FP64, OUTER_FCG, OUTER_GMRES, SWITCH_CONSISTENT, SWITCH_NATURAL,
                CdgmgError, Solver, agglomerate, n_basis, switch)
+from .bytemodel import facet_nodes, smoother_bytes
 
 SETTINGS = {
     "paper": dict(nu1=0, nu2=3, omega=2.0 / 3.0, outer=OUTER_GMRES, restart=50, tol=1e-8),
@@ -178,11 +179,12 @@ def study_size(ns=(100, 158, 224, 316, 448, 632, 894), p=3, seed=2, agg_seed=12,
             s.set_profile(False)
             npb = n_basis(2, p)
             off = int(nnzb[0]) - mesh.n_elem
-            sweep_bytes = off * npb * npb * 4 + 4 * off + 3 * mesh.n_elem * npb * 4
+            sweep_bytes = smoother_bytes(int(nnzb[0]), mesh.n_elem, npb, 4, facet_nodes(2, npb), 3)
             sweep_us = 1e3 * pinfo.kernel_ms["smooth0"] / max(pinfo.kernel_launches["smooth0"], 1)
             row = dict(n=n, elements=int(mesh.n_elem), dofs=int(mesh.n_elem * npb), levels=len(sizes),
                        iterations=info.iterations, rel_residual=info.rel_residual, solve_ms=ms,
-                       dofs_per_s=mesh.n_elem * npb / (ms * 1e-3), vcycle_operator_mb=off * npb * npb * 4 / 1e6,
+                       dofs_per_s=mesh.n_elem * npb / (ms * 1e-3), sweep_mb=sweep_bytes / 1e6,
+                       vcycle_operator_mb=(off * npb * facet_nodes(2, npb) + mesh.n_elem * npb * npb) * 4 / 1e6,
                        sweep_us=sweep_us, sweep_gbs=sweep_bytes / (sweep_us * 1e-6) / 1e9,
                        device_gb=s.device_bytes() / 1e9)
         finally:
