@@ -11,37 +11,45 @@ def facet_nodes(dim, npb):
     return q + 1 if dim == 2 else (q + 1) * (q + 2) // 2
 
 
-def smoother_bytes(nnzb0, n0, npb, s, nfn, nf):
+def row_block(npb, sym=True):
+    """Values per level-0 per-row block (D^{-1}, a diagonal block): its upper
+    triangle for the symmetric operator, else the whole block."""
+    return npb * (npb + 1) // 2 if sym else npb * npb
+
+
+def smoother_bytes(nnzb0, n0, npb, s, nfn, nf, sym=True):
     """Algorithmic HBM bytes of one level-0 damped block-Jacobi sweep
     x <- (1 - omega) x + omega D^{-1} (b - A_off x) on the facet-trace form:
     the off-diagonal blocks' n_p x n_fn stored values, their column indices and
     kinds (one int32 and one byte per facet slot), D^{-1}, and b, x read, x
     written."""
     off = nnzb0 - n0
-    return off * npb * nfn * s + 5 * n0 * nf + n0 * npb * npb * s + 3 * n0 * npb * s
+    return off * npb * nfn * s + 5 * n0 * nf + n0 * row_block(npb, sym) * s + 3 * n0 * npb * s
 
 
-def restrict_bytes(nnzb0, n0, npb, s, nfn, nf):
+def restrict_bytes(nnzb0, n0, npb, s, nfn, nf, sym=True):
     """Level-0 residual + restriction L_e^T (b - A_rr x - A_off x): the
     off-diagonal values, indices and kinds, the diagonal blocks, L_e, b and x
     read, the restricted residual written."""
     off = nnzb0 - n0
-    return off * npb * nfn * s + 5 * n0 * nf + 2 * n0 * npb * npb * s + 3 * n0 * npb * s
+    return (off * npb * nfn * s + 5 * n0 * nf + n0 * (row_block(npb, sym) + npb * npb) * s
+            + 3 * n0 * npb * s)
 
 
-def spmv_bytes(nnzb0, n0, npb, nfn, nf):
-    """Outer FP64 q = A_0 p with (p,q), (p,r): dense diagonal blocks, the
+def spmv_bytes(nnzb0, n0, npb, nfn, nf, sym=True):
+    """Outer FP64 q = A_0 p with (p,q), (p,r): the diagonal blocks, the
     off-diagonal blocks' facet-trace values, indices and kinds, p, r read, q
     written."""
     off = nnzb0 - n0
-    return n0 * npb * npb * 8 + off * npb * nfn * 8 + 5 * n0 * nf + 3 * n0 * npb * 8
+    return n0 * row_block(npb, sym) * 8 + off * npb * nfn * 8 + 5 * n0 * nf + 3 * n0 * npb * 8
 
 
-def iteration_bytes(sizes, nnzb, npb, nfn, nf, nu1=2, nu2=2, s=4):
+def iteration_bytes(sizes, nnzb, npb, nfn, nf, nu1=2, nu2=2, s=4, sym=True):
     """Algorithmic bytes of one FCG(1) iteration with a V(nu1, nu2) cycle in
     precision s (bytes) and the FP64 outer loop, per level: what each kernel
     must read and write once (operator blocks, indices, vectors), nothing for
-    re-reads.  Level 0 runs on the facet-trace form with D^{-1}; the coarse
+    re-reads.  Level 0 runs on the facet-trace form with D^{-1} (per-row
+    blocks as upper triangles when sym, the operator being symmetric); the coarse
     levels on D^{-1}-prescaled strips.  The first pre-sweep of every level is
     fused with forming D^{-1} b (no operator read); the last post-sweep of
     level 0 also reads q for the fused (z, q) dot."""
@@ -59,9 +67,9 @@ def iteration_bytes(sizes, nnzb, npb, nfn, nf, nu1=2, nu2=2, s=4):
             break
         prolong = n[l] * p2 * s + 2 * n[l] * npb * s + 4 * n[l] + n[l + 1] * npb * s
         if l == 0:
-            sweep = smoother_bytes(nz[0], n[0], npb, s, nfn, nf)
-            entry = n[0] * npb * 8 + n[0] * p2 * s + 2 * n[0] * npb * s
-            restrict = restrict_bytes(nz[0], n[0], npb, s, nfn, nf) + n[0] * npb * s
+            sweep = smoother_bytes(nz[0], n[0], npb, s, nfn, nf, sym)
+            entry = n[0] * npb * 8 + n[0] * row_block(npb, sym) * s + 2 * n[0] * npb * s
+            restrict = restrict_bytes(nz[0], n[0], npb, s, nfn, nf, sym) + n[0] * npb * s
             b = entry + (nu1 - 1) * sweep + restrict + prolong + nu2 * sweep + n[0] * npb * 8
         else:
             off = nz[l] - n[l]
@@ -71,6 +79,6 @@ def iteration_bytes(sizes, nnzb, npb, nfn, nf, nu1=2, nu2=2, s=4):
             b = entry + (nu1 - 1) * sweep + restrict + prolong + nu2 * sweep
         out["level%d" % l] = b
     m = n[0] * npb
-    out["outer"] = (m * s + 2 * m * 8) + spmv_bytes(nz[0], n[0], npb, nfn, nf) + 6 * m * 8
+    out["outer"] = (m * s + 2 * m * 8) + spmv_bytes(nz[0], n[0], npb, nfn, nf, sym) + 6 * m * 8
     out["total"] = sum(out.values())
     return out

@@ -619,6 +619,23 @@ int build_problem(const cdgmg_mesh& m, int p, const cdgmg_hierarchy& h, const cd
     set_error("setup: singular element mass matrix");
     return CDGMG_ERR_MESH;
   }
+  // The diagonal contributions (an element's own block, and what a hosted
+  // facet adds to the neighbour's diagonal block) are symmetric in exact
+  // arithmetic; their rounding is made symmetric too, so that every
+  // assembled diagonal block of the symmetric operator is symmetric bit for
+  // bit and may be stored as its upper triangle.
+  parallel_for(N0, [&](int64_t r0, int64_t r1) {
+    for (int64_t r = r0; r < r1; ++r)
+      for (int w = 0; w < W0; ++w) {
+        double* B = w == 0 ? &P.UA[(size_t)r * W0 * nb2] : &P.UH[((size_t)r * W0 + w) * nb2];
+        for (int a = 0; a < np; ++a)
+          for (int c = a + 1; c < np; ++c) {
+            const double v = 0.5 * (B[a * np + c] + B[c * np + a]);
+            B[a * np + c] = v;
+            B[c * np + a] = v;
+          }
+      }
+  });
   // ---- upwind convection blocks of beta v . grad u (Sec. 5):
   //   (beta v . grad u_K, w_K)_K - sum over inflow facets (v . n_K < 0) of
   //   int_f beta (v . n_K) (u_K - u_ext) w_K,  u_ext = neighbour trace, 0 on

@@ -148,6 +148,58 @@ __global__ __launch_bounds__(TPB) void k_diag_inverse(int64_t n, const int64_t* 
   }
 }
 
+// K8 for the larger blocks (n_p > 10, too many for one thread's registers):
+// a group of DIG = 32 lanes per row, lane j < n_p holding column j of the
+// block; step k broadcasts the pivot column from lane k by shuffles.  Same
+// arithmetic, in the same order, as the one-thread form above.
+constexpr int DIG = 32;
+template <int NP>
+__global__ __launch_bounds__(TPB) void k_diag_inverse_cols(int64_t n, const int64_t* __restrict__ sblk,
+                                                           const double* __restrict__ A, double* __restrict__ Dinv,
+                                                           int* __restrict__ err, int definite) {
+  static_assert(NP <= DIG, "one lane per column");
+  constexpr int NP2 = NP * NP;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = gid / DIG;
+  const int j = (int)(gid % DIG);
+  if (r >= n) return;  // the whole group: r is uniform across it
+  const int lane = (int)(r % WAVE);
+  const int64_t B = sblk[r / WAVE];
+  const int jj = j < NP ? j : 0;  // lanes past n_p carry a copy of column 0, unused
+  double a[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) a[i] = A[blk_off(B, 0, NP2, i * NP + jj, lane)];
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    double c[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) c[i] = __shfl(a[i], k, DIG);
+    const double p = c[k];
+    if (definite ? !(p > 0.0) : !(p != 0.0)) bad = true;
+    const double ip = 1.0 / p;
+    if (jj == k) {
+#pragma unroll
+      for (int i = 0; i < NP; ++i) a[i] = (i == k) ? ip : 0.0 - c[i] * ip;
+    } else {
+      const double rk = a[k] * ip;
+#pragma unroll
+      for (int i = 0; i < NP; ++i)
+        if (i != k) a[i] -= c[i] * rk;
+      a[k] = rk;
+    }
+  }
+  if (bad) {
+    if (j == 0) *err = 1;
+    return;
+  }
+  if (j < NP) {
+    double* D = Dinv + (r / WAVE) * WAVE * NP2 + lane;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) D[(i * NP + j) * WAVE] = a[i];
+  }
+}
+
 // K7 (Galerkin): coarse block k = (I, t) accumulates L_e^T A_f(e, w) L_c over its
 // plan entries (fixed order -> deterministic).  One workgroup per coarse block,
 // one thread per entry (i, j); the operands of up to GCH plan entries are
@@ -681,6 +733,47 @@ __device__ __forceinline__ void dot2_acc(double a, double x, double& s, double& 
 
 
 // ------------------------------------------------------------------
+// Per-row n_p x n_p blocks of level 0 (D^{-1}, the diagonal blocks A_rr) are
+// stored whole or, where the operator is symmetric (no convection), as their
+// upper triangle row by row, n_p (n_p + 1) / 2 values: entry (i, j) at the
+// packed index of (min(i, j), max(i, j)).  Same lane-interleaved per-slice
+// layout, N values per row.
+template <int NP, bool SYM>
+struct RowBlk {
+  static constexpr int N = SYM ? NP * (NP + 1) / 2 : NP * NP;
+  static constexpr __device__ int idx(int i, int j) {
+    if constexpr (!SYM) {
+      return i * NP + j;
+    } else {
+      const int a = i < j ? i : j, c = i < j ? j : i;
+      return a * NP - a * (a - 1) / 2 + (c - a);
+    }
+  }
+};
+
+// packed upper triangle of per-row blocks: dst(s, e, lane) = (src(i, j) +
+// src(j, i)) / 2 for packed index e of (i, j), i <= j; src holds whole
+// blocks, sstride values per lane and slice (n_p^2 for the per-row layout,
+// (n_f + 1) n_p^2 for slot 0 of the sliced level-0 operator)
+template <typename T, int NP>
+__global__ void k_pack_sym(int64_t ns, int64_t sstride, const double* __restrict__ src, T* __restrict__ dst) {
+  constexpr int N = RowBlk<NP, true>::N;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = (int)(idx % WAVE);
+  const int64_t rest = idx / WAVE;
+  const int e = (int)(rest % N);
+  const int64_t s = rest / N;
+  if (s >= ns) return;
+  int a = 0, rem = e;
+  while (rem >= NP - a) {
+    rem -= NP - a;
+    ++a;
+  }
+  const int c = a + rem;
+  const double* S = src + s * sstride * WAVE + lane;
+  dst[(s * N + e) * WAVE + lane] = (T)(0.5 * (S[(a * NP + c) * WAVE] + S[(c * NP + a) * WAVE]));
+}
+
 // Level 0 in facet-trace form.  In the primal form (eq. (primal_form)) the
 // element K couples to its neighbour K' across the facet f only through the
 // terms that f's host contributes: jumps of traces on f, lifted traces, and
@@ -980,7 +1073,7 @@ __device__ __forceinline__ void share_rows(int lane, int h, bool valid, const T*
 
 // sweep on level 0: x_out = (1 - omega) x + omega D^{-1} (b - A_off x); with
 // DOT also the slice's partial sum of (x_out, dv) in FP64 (part[slice])
-template <typename T, int NP, int H, int NF, bool DOT>
+template <typename T, int NP, int H, int NF, bool DOT, bool SYM>
 __global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* __restrict__ cols,
                                                      const int8_t* __restrict__ meta, const T* __restrict__ Ac,
                                                      const T* __restrict__ Dinv, const T* __restrict__ b,
@@ -1013,14 +1106,14 @@ __global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* _
   if constexpr (H == 1 && sizeof(T) == 4) {
     // whole rows in and out with wide accesses
     if (valid) {
-      const T* D = Dinv + sl * WAVE * NP2 + lane;
+      const T* D = Dinv + sl * WAVE * RowBlk<NP, SYM>::N + lane;
       T xv[NP], xn[NP];
       load_row<T, NP>(xin + r * NP, xv);
 #pragma unroll
       for (int i = 0; i < NP; ++i) {
         T y = 0;
 #pragma unroll
-        for (int j = 0; j < NP; ++j) y += D[(i * NP + j) * WAVE] * sv[j];
+        for (int j = 0; j < NP; ++j) y += D[RowBlk<NP, SYM>::idx(i, j) * WAVE] * sv[j];
         xn[i] = xv[i] + omega * (y - xv[i]);
       }
       store_row<T, NP>(xout + r * NP, xn);
@@ -1032,7 +1125,7 @@ __global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* _
       }
     }
   } else if (valid) {
-    const T* D = Dinv + sl * WAVE * NP2 + lane;
+    const T* D = Dinv + sl * WAVE * RowBlk<NP, SYM>::N + lane;
     // FP32 blocks: all of D^{-1}'s loads in flight at once; FP64: two rows
     constexpr int UF = sizeof(T) == 4 ? NI : 2;
 #pragma unroll UF
@@ -1040,7 +1133,7 @@ __global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* _
       const int i = h * NI + t;
       T y = 0;
 #pragma unroll
-      for (int j = 0; j < NP; ++j) y += D[(i * NP + j) * WAVE] * sv[j];
+      for (int j = 0; j < NP; ++j) y += D[RowBlk<NP, SYM>::idx(i, j) * WAVE] * sv[j];
       const int64_t k = r * NP + i;
       const T xi = xin[k];
       const T v = xi + omega * (y - xi);
@@ -1057,7 +1150,7 @@ __global__ __launch_bounds__(WAVE * H) void k_sweep0(int64_t n, const int32_t* _
 
 // residual of level 0 in this wavefront's rows: b - A_rr x - A_off x, then the
 // whole residual vector of the row in res[NP] (every thread calls it)
-template <typename T, int NP, int H, int NF>
+template <typename T, int NP, int H, int NF, bool SYM>
 __device__ __forceinline__ void residual0(int64_t sl, int64_t r, int lane, int h, bool valid,
                                           const int32_t* __restrict__ cols, const int8_t* __restrict__ meta,
                                           const T* __restrict__ Ac, const T* __restrict__ Ad,
@@ -1065,7 +1158,7 @@ __device__ __forceinline__ void residual0(int64_t sl, int64_t r, int lane, int h
   constexpr int NP2 = NP * NP, NI = NP / H;
   Acc<T, false> acc[NI], sc[NP];
   if (valid) {
-    const T* Dg = Ad + sl * WAVE * NP2 + lane;
+    const T* Dg = Ad + sl * WAVE * RowBlk<NP, SYM>::N + lane;
     if constexpr (H == 1 && sizeof(T) == 4) {
       T bv[NP], xr[NP];
       load_row<T, NP>(b + r * NP, bv);
@@ -1074,7 +1167,7 @@ __device__ __forceinline__ void residual0(int64_t sl, int64_t r, int lane, int h
       for (int i = 0; i < NP; ++i) {
         acc[i].s = bv[i];
 #pragma unroll
-        for (int j = 0; j < NP; ++j) acc[i].add(-__builtin_nontemporal_load(Dg + (i * NP + j) * WAVE), xr[j]);
+        for (int j = 0; j < NP; ++j) acc[i].add(-__builtin_nontemporal_load(Dg + RowBlk<NP, SYM>::idx(i, j) * WAVE), xr[j]);
       }
     } else {
 #pragma unroll
@@ -1084,7 +1177,7 @@ __device__ __forceinline__ void residual0(int64_t sl, int64_t r, int lane, int h
         const T xj = x[r * NP + j];
 #pragma unroll
         for (int t = 0; t < NI; ++t)
-          acc[t].add(-__builtin_nontemporal_load(Dg + ((h * NI + t) * NP + j) * WAVE), xj);
+          acc[t].add(-__builtin_nontemporal_load(Dg + RowBlk<NP, SYM>::idx(h * NI + t, j) * WAVE), xj);
       }
     }
     off0<T, NP, H, NF, false, false, false>(sl, lane, h, cols, meta, Ac, x, nullptr, T(-1), acc, sc);
@@ -1097,7 +1190,7 @@ __device__ __forceinline__ void residual0(int64_t sl, int64_t r, int lane, int h
 }
 
 // residual + restriction on level 0: t_e = L_e^T (b - A x)_e
-template <typename T, int NP, int H, int NF>
+template <typename T, int NP, int H, int NF, bool SYM>
 __global__ __launch_bounds__(WAVE * H) void k_restrict0(int64_t n, const int32_t* __restrict__ cols,
                                                         const int8_t* __restrict__ meta, const T* __restrict__ Ac,
                                                         const T* __restrict__ Ad, const T* __restrict__ b,
@@ -1109,7 +1202,7 @@ __global__ __launch_bounds__(WAVE * H) void k_restrict0(int64_t n, const int32_t
   const int64_t sl = slice_order(rev), r = sl * WAVE + lane;
   const bool valid = r < n;
   T res[NP];
-  residual0<T, NP, H, NF>(sl, r, lane, h, valid, cols, meta, Ac, Ad, b, x, sh, res);
+  residual0<T, NP, H, NF, SYM>(sl, r, lane, h, valid, cols, meta, Ac, Ad, b, x, sh, res);
   if (!valid) return;
   const T* Lr = Lb + sl * WAVE * NP2 + lane;
   if constexpr (H == 1 && sizeof(T) == 4) {
@@ -1136,7 +1229,7 @@ __global__ __launch_bounds__(WAVE * H) void k_restrict0(int64_t n, const int32_t
 
 // level-0 entry from the FP64 outer residual: b = (T) r, x = omega D^{-1} b
 // (the first sweep from zero)
-template <typename T, int NP, int H>
+template <typename T, int NP, int H, bool SYM>
 __global__ __launch_bounds__(WAVE * H) void k_entry0(int64_t n, const double* __restrict__ src,
                                                      const T* __restrict__ Dinv, T omega, T* __restrict__ b,
                                                      T* __restrict__ x) {
@@ -1151,14 +1244,14 @@ __global__ __launch_bounds__(WAVE * H) void k_entry0(int64_t n, const double* __
 #pragma unroll
     for (int j = 0; j < NP; ++j) v[j] = (T)rv[j];
   }
-  const T* D = Dinv + sl * WAVE * NP2 + lane;
+  const T* D = Dinv + sl * WAVE * RowBlk<NP, SYM>::N + lane;
   if constexpr (H == 1 && sizeof(T) == 4) {
     T xv[NP];
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
       T s = 0;
 #pragma unroll
-      for (int j = 0; j < NP; ++j) s += D[(i * NP + j) * WAVE] * v[j];
+      for (int j = 0; j < NP; ++j) s += D[RowBlk<NP, SYM>::idx(i, j) * WAVE] * v[j];
       xv[i] = omega * s;
     }
     store_row<T, NP>(b + r * NP, v);
@@ -1172,7 +1265,7 @@ __global__ __launch_bounds__(WAVE * H) void k_entry0(int64_t n, const double* __
       const int i = h * NI + t;
       T s = 0;
 #pragma unroll
-      for (int j = 0; j < NP; ++j) s += D[(i * NP + j) * WAVE] * v[j];
+      for (int j = 0; j < NP; ++j) s += D[RowBlk<NP, SYM>::idx(i, j) * WAVE] * v[j];
       x[r * NP + i] = omega * s;
     }
   }
@@ -1209,17 +1302,22 @@ __global__ void k_compress0(int64_t n, int64_t ns, const double* __restrict__ A,
     return;
   }
   Ac[((s * NF + w) * NPF + m) * WAVE + lane] = (T)blk[(a * NP + bb) * WAVE];
-  // check: the thread of value (i, 0) checks row i (column kind) or column i
-  // (row kind) of the block off the kept facet nodes
-  if (k == 0) {
+  // check: the threads of values (i, k), k < n_fn, check row i (column kind)
+  // or column i (row kind) of the block off the kept facet nodes, thread k
+  // the entries q = k, k + n_fn, ...
+  {
     const int f = kd == NF ? w : kd;
     bool bad = false;
-    for (int q = 0; q < NP; ++q) {
-      bool on = false;
 #pragma unroll
-      for (int kk = 0; kk < NFN; ++kk) on = on || q == facet_node_at<NP, NF>(f, kk);
-      const double v = kd == NF ? blk[(q * NP + i) * WAVE] : blk[(i * NP + q) * WAVE];
-      if (!on && v != 0.0) bad = true;
+    for (int q0 = 0; q0 < NP; q0 += NFN) {
+      const int q = q0 + k;
+      if (q < NP) {
+        bool on = false;
+#pragma unroll
+        for (int kk = 0; kk < NFN; ++kk) on = on || q == facet_node_at<NP, NF>(f, kk);
+        const double v = kd == NF ? blk[(q * NP + i) * WAVE] : blk[(i * NP + q) * WAVE];
+        if (!on && v != 0.0) bad = true;
+      }
     }
     if (bad) *err = 1;
   }
@@ -1461,7 +1559,7 @@ __global__ void k_galerkin_p(int64_t ns, int W, const double* __restrict__ A0, c
 // level-0 residual + restriction to the lower-degree space, FP64 output for
 // the lower hierarchy: t_r = T^T (b - A x)_r with the constant embedding T
 // (n_p0 x n_p1, row-major)
-template <typename T, int NP0, int NP1, int H, int NF>
+template <typename T, int NP0, int NP1, int H, int NF, bool SYM>
 __global__ __launch_bounds__(WAVE * H) void k_restrict0_rect(int64_t n, const int32_t* __restrict__ cols,
                                                              const int8_t* __restrict__ meta, const T* __restrict__ Ac,
                                                              const T* __restrict__ Ad, const T* __restrict__ b,
@@ -1472,7 +1570,7 @@ __global__ __launch_bounds__(WAVE * H) void k_restrict0_rect(int64_t n, const in
   const int64_t sl = slice_order(rev), r = sl * WAVE + lane;
   const bool valid = r < n;
   T res[NP0];
-  residual0<T, NP0, H, NF>(sl, r, lane, h, valid, cols, meta, Ac, Ad, b, x, sh, res);
+  residual0<T, NP0, H, NF, SYM>(sl, r, lane, h, valid, cols, meta, Ac, Ad, b, x, sh, res);
   if (!valid) return;
   for (int j = h; j < NP1; j += H) {
     T s = 0;
@@ -1754,7 +1852,7 @@ __global__ void k_update_x_multi(int64_t m, int nk, const double* __restrict__ Z
 // read from the sliced A_0 at slot 0) with the partial sums of (p, q) and
 // (p, r) per slice (DOTS); COMP accumulates in Dot2.  All operator loads are
 // non-temporal (read once per outer iteration).
-template <int NP, int H, int NF, bool COMP, bool DOTS = true>
+template <int NP, int H, int NF, bool SYM, bool COMP, bool DOTS = true>
 __global__ __launch_bounds__(WAVE * H) void k_spmv0(int64_t n, const int32_t* __restrict__ cols,
                                                     const int8_t* __restrict__ meta, const double* __restrict__ A,
                                                     const double* __restrict__ Ac, const double* __restrict__ p,
@@ -1769,12 +1867,29 @@ __global__ __launch_bounds__(WAVE * H) void k_spmv0(int64_t n, const int32_t* __
   const bool valid = r < n;
   Acc<double, COMP> acc[NI], sc[NP];
   if (valid) {
-    const double* Dg = A + (sl * (NF + 1) * NP2) * WAVE + lane;
-#pragma unroll 2
-    for (int j = 0; j < NP; ++j) {
-      const double xj = p[r * NP + j];
+    // the diagonal blocks: slot 0 of the sliced A_0, or packed (SYM)
+    const double* Dg = A + (SYM ? sl * RowBlk<NP, true>::N : sl * (NF + 1) * NP2) * WAVE + lane;
+    if constexpr (SYM && H == 1) {
+      // each stored entry loaded once and applied to both of its positions;
+      // every row still receives its terms in ascending column order
+      double pv[NP];
+      load_row<double, NP>(p + r * NP, pv);
 #pragma unroll
-      for (int t = 0; t < NI; ++t) acc[t].add(__builtin_nontemporal_load(Dg + ((h * NI + t) * NP + j) * WAVE), xj);
+      for (int a = 0; a < NP; ++a)
+#pragma unroll
+        for (int c = a; c < NP; ++c) {
+          const double v = __builtin_nontemporal_load(Dg + RowBlk<NP, true>::idx(a, c) * WAVE);
+          acc[a].add(v, pv[c]);
+          if (c != a) acc[c].add(v, pv[a]);
+        }
+    } else {
+#pragma unroll 2
+      for (int j = 0; j < NP; ++j) {
+        const double xj = p[r * NP + j];
+#pragma unroll
+        for (int t = 0; t < NI; ++t)
+          acc[t].add(__builtin_nontemporal_load(Dg + RowBlk<NP, SYM>::idx(h * NI + t, j) * WAVE), xj);
+      }
     }
     off0<double, NP, H, NF, COMP, false, true>(sl, lane, h, cols, meta, Ac, p, nullptr, 1.0, acc, sc);
   }
@@ -1819,7 +1934,7 @@ __global__ __launch_bounds__(WAVE * H) void k_spmv0(int64_t n, const int32_t* __
 
 // true residual rt = b - A (xh + xl) on the facet-trace form, compensated;
 // partial ||rt||^2 per slice
-template <int NP, int H, int NF>
+template <int NP, int H, int NF, bool SYM>
 __global__ __launch_bounds__(WAVE * H) void k_residual0(int64_t n, const int32_t* __restrict__ cols,
                                                         const int8_t* __restrict__ meta, const double* __restrict__ A,
                                                         const double* __restrict__ Ac, const double* __restrict__ b,
@@ -1834,17 +1949,35 @@ __global__ __launch_bounds__(WAVE * H) void k_residual0(int64_t n, const int32_t
   const bool valid = r < n;
   Acc<double, true> acc[NI], sc[NP];
   if (valid) {
-    const double* Dg = A + (sl * (NF + 1) * NP2) * WAVE + lane;
+    const double* Dg = A + (SYM ? sl * RowBlk<NP, true>::N : sl * (NF + 1) * NP2) * WAVE + lane;
 #pragma unroll
     for (int t = 0; t < NI; ++t) acc[t].s = b[r * NP + h * NI + t];
-#pragma unroll 2
-    for (int j = 0; j < NP; ++j) {
-      const double hj = xh[r * NP + j], lj = xl[r * NP + j];
+    if constexpr (SYM && H == 1) {
+      double hv[NP], lv[NP];
+      load_row<double, NP>(xh + r * NP, hv);
+      load_row<double, NP>(xl + r * NP, lv);
 #pragma unroll
-      for (int t = 0; t < NI; ++t) {
-        const double a = -__builtin_nontemporal_load(Dg + ((h * NI + t) * NP + j) * WAVE);
-        acc[t].add(a, hj);
-        acc[t].addlo(a, lj);
+      for (int a = 0; a < NP; ++a)
+#pragma unroll
+        for (int c = a; c < NP; ++c) {
+          const double v = -__builtin_nontemporal_load(Dg + RowBlk<NP, true>::idx(a, c) * WAVE);
+          acc[a].add(v, hv[c]);
+          acc[a].addlo(v, lv[c]);
+          if (c != a) {
+            acc[c].add(v, hv[a]);
+            acc[c].addlo(v, lv[a]);
+          }
+        }
+    } else {
+#pragma unroll 2
+      for (int j = 0; j < NP; ++j) {
+        const double hj = xh[r * NP + j], lj = xl[r * NP + j];
+#pragma unroll
+        for (int t = 0; t < NI; ++t) {
+          const double a = -__builtin_nontemporal_load(Dg + RowBlk<NP, SYM>::idx(h * NI + t, j) * WAVE);
+          acc[t].add(a, hj);
+          acc[t].addlo(a, lj);
+        }
       }
     }
     off0<double, NP, H, NF, true, true, true>(sl, lane, h, cols, meta, Ac, xh, xl, -1.0, acc, sc);

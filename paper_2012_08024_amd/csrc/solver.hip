@@ -58,15 +58,29 @@ using namespace cdg;
 constexpr bool l0_pair(int np, int nf) {
   return nf == 3 ? (np == 3 || np == 6 || np == 10) : (np == 4 || np == 10 || np == 20);
 }
+// level-0 kernels: facets per element NF, wavefronts per slice H, and SYM
+// (the per-row diagonal blocks and D^{-1} stored as upper triangles)
+#define SYM_DISPATCH(sym, ...)          \
+  if (sym) {                            \
+    constexpr bool SYM = true;          \
+    __VA_ARGS__;                        \
+  } else {                              \
+    constexpr bool SYM = false;         \
+    __VA_ARGS__;                        \
+  }
 #define L0_DISPATCH(hh, ...)                                                                                \
   switch ((hh)->P.nf) {                                                                                     \
     case 3: {                                                                                               \
       constexpr int NF = 3;                                                                                 \
-      H_DISPATCH((hh)->H0, if constexpr (NP % H == 0 && l0_pair(NP, NF)) { __VA_ARGS__; });                \
+      SYM_DISPATCH((hh)->sym0, H_DISPATCH((hh)->H0, if constexpr (NP % H == 0 && l0_pair(NP, NF)) {         \
+        __VA_ARGS__;                                                                                        \
+      }));                                                                                                  \
     } break;                                                                                                \
     case 4: {                                                                                               \
       constexpr int NF = 4;                                                                                 \
-      H_DISPATCH((hh)->H0, if constexpr (NP % H == 0 && l0_pair(NP, NF)) { __VA_ARGS__; });                \
+      SYM_DISPATCH((hh)->sym0, H_DISPATCH((hh)->H0, if constexpr (NP % H == 0 && l0_pair(NP, NF)) {         \
+        __VA_ARGS__;                                                                                        \
+      }));                                                                                                  \
     } break;                                                                                                \
     default: break;                                                                                         \
   }
@@ -200,6 +214,11 @@ struct cdgmg_handle {
   // embedding T [np][np1] in FP64 and in the multigrid precision
   cdgmg_handle* inner = nullptr;
   bool given_A0 = false;   // this level 0 is set by the owner (T^T A_0 T), not assembled from kappa
+  // symmetric operator (no convection): the level-0 per-row blocks (D^{-1},
+  // the diagonal blocks in the cycle's precision, and A0d, the FP64 diagonal
+  // blocks of the outer loop) are stored as upper triangles
+  bool sym0 = false;
+  double* A0d = nullptr;
   int np1 = 0;
   // level-0 passes over the V-cycle operator so far; their parity sets the
   // direction of the next one
@@ -486,6 +505,8 @@ int upload_problem(cdgmg_handle* h) {
   h->N0 = P.N0;
   h->lv.assign(P.L + 1, DLevel());
   const bool fp32 = h->o.mg_precision == CDGMG_MG_FP32;
+  h->sym0 = P.beta == 0.0;
+  const int npk = h->sym0 ? np * (np + 1) / 2 : np2;  // values per level-0 per-row block
   for (int l = 0; l <= P.L; ++l) {
     Level& H = P.lv[l];
     DLevel& D = h->lv[l];
@@ -499,11 +520,15 @@ int upload_problem(cdgmg_handle* h) {
     RETURN_IF(dalloc(h, &D.A64, (size_t)D.slots * np2));
     RETURN_IF(dzero(h, D.A64, (size_t)D.slots * np2 * sizeof(double)));
     const size_t rowblk = (size_t)D.ns * SLICE * np2;
+    const size_t rowblk0 = (size_t)D.ns * SLICE * npk;  // level 0: packed when symmetric
     if (l == 0 && h->inner) {  // hp front end: level 0 restricts to the lower degree
       RETURN_IF(dalloc(h, &D.D64, rowblk));
       void* tmp;
       if (fp32) {
-        RETURN_IF(dalloc(h, (char**)&tmp, rowblk * sizeof(float)));
+        RETURN_IF(dalloc(h, (char**)&tmp, rowblk0 * sizeof(float)));
+        D.Dm = tmp;
+      } else if (h->sym0) {
+        RETURN_IF(dalloc(h, (char**)&tmp, rowblk0 * sizeof(double)));
         D.Dm = tmp;
       } else {
         D.Dm = D.D64;
@@ -517,7 +542,7 @@ int upload_problem(cdgmg_handle* h) {
         float* tmp;
         RETURN_IF(upload(h, &tmp, std::vector<float>(Lr.begin(), Lr.end())));
         D.Lm = tmp;
-        RETURN_IF(dalloc(h, &tmp, rowblk));
+        RETURN_IF(dalloc(h, &tmp, l == 0 ? rowblk0 : rowblk));
         D.Dm = tmp;
         if (l > 0) {
           RETURN_IF(dalloc(h, &tmp, rowblk));
@@ -526,6 +551,11 @@ int upload_problem(cdgmg_handle* h) {
       } else {
         D.Lm = D.L64;
         D.Dm = D.D64;
+        if (l == 0 && h->sym0) {
+          double* tmp;
+          RETURN_IF(dalloc(h, &tmp, rowblk0));
+          D.Dm = tmp;
+        }
         if (l > 0) {
           double* tmp;
           RETURN_IF(dalloc(h, &tmp, rowblk));
@@ -549,17 +579,18 @@ int upload_problem(cdgmg_handle* h) {
       const size_t nc = (size_t)D.ns * SLICE * nf * np * fnodes(np, nf);
       const bool smooth = P.L > 0 || h->inner;
       if (!h->given_A0 || (smooth && !fp32)) RETURN_IF(dalloc(h, &h->A0c, nc));
+      if (!h->given_A0 && h->sym0) RETURN_IF(dalloc(h, &h->A0d, rowblk0));
       if (smooth) {
         if (fp32) {
           float* tmp;
           RETURN_IF(dalloc(h, &tmp, nc));
           D.Ac = tmp;
-          RETURN_IF(dalloc(h, &tmp, rowblk));
+          RETURN_IF(dalloc(h, &tmp, rowblk0));
           D.Ad = tmp;
         } else {
           D.Ac = h->A0c;
           double* tmp;
-          RETURN_IF(dalloc(h, &tmp, rowblk));
+          RETURN_IF(dalloc(h, &tmp, rowblk0));
           D.Ad = tmp;
         }
       }
@@ -738,12 +769,31 @@ void level0_operators(cdgmg_handle* h) {
       compress0<T, NP>(h, (T*)D.Ac, h->err);
     }
   }
+  if (h->sym0) {  // upper triangles of the diagonal blocks and of D^{-1}
+    constexpr int NPK = RowBlk<NP, true>::N;
+    const int64_t nt = D.ns * NPK * WAVE;
+    launch(h, -1, k_pack_sym<T, NP>, dim3(grid_for(nt)), dim3(TPB), D.ns, (int64_t)(h->P.nf + 1) * NP2,
+           (const double*)D.A64, (T*)D.Ad);
+    launch(h, -1, k_pack_sym<T, NP>, dim3(grid_for(nt)), dim3(TPB), D.ns, (int64_t)NP2, (const double*)D.D64,
+           (T*)D.Dm);
+    return;
+  }
   NF_DISPATCH(h->P.nf, launch(h, -1, k_diag0<T, NP, NF>, dim3(grid_for(D.ns * NP2 * WAVE)), dim3(TPB), D.ns,
                               (const double*)D.A64, (T*)D.Ad));
   if ((void*)D.Dm != (void*)D.D64) {
     const int64_t nb = D.ns * SLICE * NP2;
     launch(h, -1, k_cast<double, T>, dim3(grid_for(nb)), dim3(TPB), nb, (const double*)D.D64, (T*)D.Dm);
   }
+}
+
+// the outer loop's FP64 diagonal blocks of A_0, packed (symmetric operator)
+template <int NP>
+void pack_outer_diag(cdgmg_handle* h) {
+  if (!h->A0d) return;
+  DLevel& D = h->lv[0];
+  const int64_t nt = D.ns * RowBlk<NP, true>::N * WAVE;
+  launch(h, -1, k_pack_sym<double, NP>, dim3(grid_for(nt)), dim3(TPB), D.ns, (int64_t)(h->P.nf + 1) * NP * NP,
+         (const double*)D.A64, h->A0d);
 }
 
 // hp front end, level 0 at degree p: D^{-1}, the next p-level's operator
@@ -756,11 +806,22 @@ void prescale_hp(cdgmg_handle* h) {
 
 int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed);
 
+// D^{-1} of every diagonal block of a level (K8): one thread per row up to
+// n_p = 10, a group of lanes per row above
+template <int NP>
+void diag_inverse(cdgmg_handle* h, DLevel& L, int definite) {
+  if constexpr (NP <= 10)
+    launch(h, -1, k_diag_inverse<NP>, dim3(grid_for(L.n)), dim3(TPB), L.n, (const int64_t*)L.sblk,
+           (const double*)L.A64, L.D64, h->err, definite);
+  else
+    launch(h, -1, k_diag_inverse_cols<NP>, dim3(grid_for(L.n * DIG)), dim3(TPB), L.n, (const int64_t*)L.sblk,
+           (const double*)L.A64, L.D64, h->err, definite);
+}
+
 int build_hp(cdgmg_handle* h) {
   DLevel& l0 = h->lv[0];
   cdgmg_handle* in = h->inner;
-  NP_DISPATCH(h->np, launch(h, -1, k_diag_inverse<NP>, dim3(grid_for(l0.n)), dim3(TPB), l0.n,
-                            (const int64_t*)l0.sblk, (const double*)l0.A64, l0.D64, h->err, 1));
+  NP_DISPATCH(h->np, diag_inverse<NP>(h, l0, 1));
   RETURN_IF(check_err(h, CDGMG_ERR_SINGULAR, "setup: a diagonal block is not positive definite"));
   const int64_t tot = l0.ns * h->W0 * (int64_t)h->np1 * h->np1 * WAVE;
   HP_DISPATCH(h->np, h->np1, launch(h, -1, k_galerkin_p<NP0, NP1>, dim3(grid_for(tot)), dim3(TPB), l0.ns, h->W0,
@@ -824,14 +885,16 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed) {
   const char* not_trace = "setup: a level-0 off-diagonal block is not in facet-trace form";
   // the facet-trace copy of A_0 (outer loop, and source of the V-cycle's
   // copy) beside the Galerkin chain, which reads the sliced A_0
+  // (forked once the level-0 block inverses are enqueued, so that it does not
+  // share the device with them), then the prescaled copies beside the
+  // coarsest inverse
   SideWork side(h);
-  const bool fork = side.on() && h->A0c && !h->inner;
-  if (h->A0c) {
-    if (fork) side.fork();
-    NP_DISPATCH(np, compress0<double, NP>(h, h->A0c, fork ? h->err_side : h->err));
-    side.back();
-    if (!fork) RETURN_IF(check_err(h, CDGMG_ERR_MESH, not_trace));
+  const bool fork = side.on() && h->A0c && !h->inner && h->L > 0;  // forked from the level loop
+  if (h->A0c && !fork) {
+    NP_DISPATCH(np, compress0<double, NP>(h, h->A0c, h->err));
+    RETURN_IF(check_err(h, CDGMG_ERR_MESH, not_trace));
   }
+  if (!fork) NP_DISPATCH(np, pack_outer_diag<NP>(h));
   if (h->inner) return build_hp(h);
   const bool flux = h->P.flux;
   // the Galerkin hierarchy of the symmetric Poisson operator is SPD: its
@@ -843,8 +906,13 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed) {
                            (const double*)h->kappa, l0.Mbm));
   for (int l = 0; l < h->L; ++l) {
     DLevel &f = h->lv[l], &c = h->lv[l + 1];
-    NP_DISPATCH(np, launch(h, -1, k_diag_inverse<NP>, dim3(grid_for(f.n)), dim3(TPB), f.n,
-                           (const int64_t*)f.sblk, (const double*)f.A64, f.D64, h->err, definite));
+    NP_DISPATCH(np, diag_inverse<NP>(h, f, definite));
+    if (l == 0 && fork) {
+      side.fork();
+      NP_DISPATCH(np, compress0<double, NP>(h, h->A0c, h->err_side));
+      NP_DISPATCH(np, pack_outer_diag<NP>(h));
+      side.back();
+    }
     if (flux) {
       // M_l^{-1}, X = G_l L, Y = L^T X (= G_{l+1}), M_{l+1} = L^T M_l L, M_{l+1}^{-1}
       NP_DISPATCH(np, launch(h, -1, k_block_inverse_bm<NP>, dim3(grid_for(f.n)), dim3(TPB), f.n,
@@ -868,8 +936,15 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed) {
   }
   RETURN_IF(check_err(h, CDGMG_ERR_SINGULAR, flux ? "setup: a diagonal or mass block is singular"
                                                   : "setup: a diagonal block is not positive definite"));
+  // coarsest: dense scatter + Gauss-Jordan inverse
+  DLevel& cl = h->lv[h->L];
+  const int64_t nd = h->nd, ld = h->ld;
+  launch(h, -1, k_dense_init, dim3(grid_for(ld * ld)), dim3(TPB), nd, ld, h->dense);
+  NP_DISPATCH(np, launch(h, -1, k_dense_scatter<NP>, dim3(grid_for(cl.n * np2)), dim3(TPB), cl.n, ld,
+                         (const int32_t*)cl.cols, (const int64_t*)cl.sblk, (const double*)cl.A64, h->dense));
+  launch(h, -1, k_dense_diag, dim3(grid_for(ld)), dim3(TPB), ld, (const double*)h->dense, h->gjD);
   // prescaled V-cycle operators D^{-1} A (off-diagonal), D^T L_e, and D^{-1} in the
-  // multigrid precision, beside the coarsest inverse
+  // multigrid precision, beside the inverse
   if (fork) side.fork();
   if (h->o.mg_precision == CDGMG_MG_FP32) {
     NP_DISPATCH(np, prescale<float, NP>(h));
@@ -878,13 +953,6 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed) {
   }
   side.back();
   if (!fork) RETURN_IF(check_err(h, CDGMG_ERR_MESH, not_trace));
-  // coarsest: dense scatter + Gauss-Jordan inverse (ping-pong)
-  DLevel& cl = h->lv[h->L];
-  const int64_t nd = h->nd, ld = h->ld;
-  launch(h, -1, k_dense_init, dim3(grid_for(ld * ld)), dim3(TPB), nd, ld, h->dense);
-  NP_DISPATCH(np, launch(h, -1, k_dense_scatter<NP>, dim3(grid_for(cl.n * np2)), dim3(TPB), cl.n, ld,
-                         (const int32_t*)cl.cols, (const int64_t*)cl.sblk, (const double*)cl.A64, h->dense));
-  launch(h, -1, k_dense_diag, dim3(grid_for(ld)), dim3(TPB), ld, (const double*)h->dense, h->gjD);
   const int nbk = (int)(ld / GJB);
   for (int K = 0; K < nbk; ++K) {
     launch(h, -1, k_gj_pivot, dim3(1), dim3(GJT), ld, K, h->dense, h->gjP, (const double*)h->gjD, h->err,
@@ -932,11 +1000,11 @@ void smooth_sweeps(cdgmg_handle* h, int l, int count, T** x, T** xb, const doubl
       const bool dot = dv && s == count - 1;
       const int rev = h->at_pass++ & 1;
       if (dot) {
-        L0_DISPATCH(h, launch(h, cls, k_sweep0<T, NP, H, NF, true>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
+        L0_DISPATCH(h, launch(h, cls, k_sweep0<T, NP, H, NF, true, SYM>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
                               (const int32_t*)d.cols, (const int8_t*)d.meta, (const T*)d.Ac, (const T*)d.Dm,
                               (const T*)d.b, (const T*)*x, omega, *xb, dv, h->part, rev));
       } else {
-        L0_DISPATCH(h, launch(h, cls, k_sweep0<T, NP, H, NF, false>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
+        L0_DISPATCH(h, launch(h, cls, k_sweep0<T, NP, H, NF, false, SYM>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n,
                               (const int32_t*)d.cols, (const int8_t*)d.meta, (const T*)d.Ac, (const T*)d.Dm,
                               (const T*)d.b, (const T*)*x, omega, *xb, (const double*)nullptr, (double*)nullptr,
                               rev));
@@ -999,11 +1067,11 @@ T* vcycle_hp(cdgmg_handle* h, const double* r64, const double* dv, int* nparts, 
   const int nu1 = h->o.nu1, nu2 = h->o.nu2;
   const T w1 = nu1 > 0 ? omega : T(0);
   cdgmg_handle* in = h->inner;
-  L0_DISPATCH(h, launch(h, CDGMG_K_SMOOTH, k_entry0<T, NP, H>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n, r64,
+  L0_DISPATCH(h, launch(h, CDGMG_K_SMOOTH, k_entry0<T, NP, H, SYM>, dim3((unsigned)d.ns), dim3(WAVE * H), d.n, r64,
                         (const T*)d.Dm, w1, (T*)d.b, x));
   smooth_sweeps<T, NP>(h, 0, nu1 > 1 ? nu1 - 1 : 0, &x, &xb);
   const int rev = h->at_pass++ & 1;
-  HP_DISPATCH(NP, h->np1, L0_DISPATCH(h, launch(h, CDGMG_K_RESTRICT, k_restrict0_rect<T, NP0, NP1, H, NF>,
+  HP_DISPATCH(NP, h->np1, L0_DISPATCH(h, launch(h, CDGMG_K_RESTRICT, k_restrict0_rect<T, NP0, NP1, H, NF, SYM>,
                                                 dim3((unsigned)d.ns), dim3(WAVE * H), d.n, (const int32_t*)d.cols,
                                                 (const int8_t*)d.meta, (const T*)d.Ac, (const T*)d.Ad,
                                                 (const T*)d.b, (const T*)x, (const T*)h->Tpm, in->t1, rev)));
@@ -1047,9 +1115,9 @@ T* vcycle_t(cdgmg_handle* h, const double* r64, const double* dv, int* nparts) {
   for (int l = 0; l < L; ++l) {
     DLevel& d = h->lv[l];
     if (l == 0) {
-      H_DISPATCH(h->H0, if constexpr (NP % H == 0) launch(h, CDGMG_K_SMOOTH, k_entry0<T, NP, H>, 
+      SYM_DISPATCH(h->sym0, H_DISPATCH(h->H0, if constexpr (NP % H == 0) launch(h, CDGMG_K_SMOOTH, k_entry0<T, NP, H, SYM>, 
                                                           dim3((unsigned)d.ns), dim3(WAVE * H), d.n, r64,
-                                                          (const T*)d.Dm, w1, (T*)d.b, xs[0]));
+                                                          (const T*)d.Dm, w1, (T*)d.b, xs[0])));
     } else {
       const int tpb = row_tpb(h, l);
       launch(h, CDGMG_K_SMOOTH, k_entry_c<T, NP>, dim3(grid_for(d.n, tpb)), dim3(tpb), d.n,
@@ -1058,7 +1126,7 @@ T* vcycle_t(cdgmg_handle* h, const double* r64, const double* dv, int* nparts) {
     smooth_sweeps<T, NP>(h, l, nu1 > 1 ? nu1 - 1 : 0, &xs[l], &xbs[l]);
     if (l == 0) {
       const int rev = h->at_pass++ & 1;
-      L0_DISPATCH(h, launch(h, CDGMG_K_RESTRICT, k_restrict0<T, NP, H, NF>, dim3((unsigned)d.ns), dim3(WAVE * H),
+      L0_DISPATCH(h, launch(h, CDGMG_K_RESTRICT, k_restrict0<T, NP, H, NF, SYM>, dim3((unsigned)d.ns), dim3(WAVE * H),
                             d.n, (const int32_t*)d.cols, (const int8_t*)d.meta, (const T*)d.Ac, (const T*)d.Ad,
                             (const T*)d.b, (const T*)xs[0], (const T*)d.Lm, (T*)d.t, rev));
     } else {
@@ -1133,9 +1201,9 @@ int read_scalar(cdgmg_handle* h, int slot, double* out) {
 // recursive residual is replaced by it); ||r||^2 lands in scal[SC_TMP]
 void enqueue_true_residual(cdgmg_handle* h) {
   DLevel& d = h->lv[0];
-  NP_DISPATCH(h->np, L0_DISPATCH(h, launch(h, CDGMG_K_VECTOR, k_residual0<NP, H, NF>, dim3((unsigned)d.ns),
+  NP_DISPATCH(h->np, L0_DISPATCH(h, launch(h, CDGMG_K_VECTOR, k_residual0<NP, H, NF, SYM>, dim3((unsigned)d.ns),
                                             dim3(WAVE * H), d.n, (const int32_t*)d.cols, (const int8_t*)d.meta,
-                                            (const double*)d.A64, (const double*)h->A0c, (const double*)h->b,
+                                            (const double*)(SYM ? h->A0d : d.A64), (const double*)h->A0c, (const double*)h->b,
                                             (const double*)h->x, (const double*)h->xl, h->r, h->part)));
   launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(RED_T), (const double*)h->part, (int)d.ns, 1, h->scal, SC_TMP,
          -1);
@@ -1232,14 +1300,14 @@ int krylov_cg(cdgmg_handle* h, cdgmg_solve_info* info) {
              (const double*)h->scal, sign, iter == 0 ? 1 : 0);
     const unsigned g = (unsigned)d0.ns;
     if (accurate) {
-      NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv0<NP, H, NF, true>, dim3(g), dim3(WAVE * H),
+      NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv0<NP, H, NF, SYM, true>, dim3(g), dim3(WAVE * H),
                                             d0.n, (const int32_t*)d0.cols, (const int8_t*)d0.meta,
-                                            (const double*)d0.A64, (const double*)h->A0c, (const double*)h->p,
+                                            (const double*)(SYM ? h->A0d : d0.A64), (const double*)h->A0c, (const double*)h->p,
                                             (const double*)h->r, h->q, h->part)));
     } else {
-      NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv0<NP, H, NF, false>, dim3(g), dim3(WAVE * H),
+      NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv0<NP, H, NF, SYM, false>, dim3(g), dim3(WAVE * H),
                                             d0.n, (const int32_t*)d0.cols, (const int8_t*)d0.meta,
-                                            (const double*)d0.A64, (const double*)h->A0c, (const double*)h->p,
+                                            (const double*)(SYM ? h->A0d : d0.A64), (const double*)h->A0c, (const double*)h->p,
                                             (const double*)h->r, h->q, h->part)));
     }
     launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(RED_T), (const double*)h->part, (int)g, 2, h->scal, SC_PQ,
@@ -1404,14 +1472,14 @@ int krylov_gmres(cdgmg_handle* h, cdgmg_solve_info* info) {
       const double* zj = Z + (int64_t)j * ld;
       const unsigned gs = (unsigned)d0.ns;
       if (accurate) {
-        NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv0<NP, H, NF, true, false>, dim3(gs),
+        NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv0<NP, H, NF, SYM, true, false>, dim3(gs),
                                               dim3(WAVE * H), d0.n, (const int32_t*)d0.cols, (const int8_t*)d0.meta,
-                                              (const double*)d0.A64, (const double*)h->A0c, zj,
+                                              (const double*)(SYM ? h->A0d : d0.A64), (const double*)h->A0c, zj,
                                               (const double*)nullptr, w, (double*)nullptr)));
       } else {
-        NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv0<NP, H, NF, false, false>, dim3(gs),
+        NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv0<NP, H, NF, SYM, false, false>, dim3(gs),
                                               dim3(WAVE * H), d0.n, (const int32_t*)d0.cols, (const int8_t*)d0.meta,
-                                              (const double*)d0.A64, (const double*)h->A0c, zj,
+                                              (const double*)(SYM ? h->A0d : d0.A64), (const double*)h->A0c, zj,
                                               (const double*)nullptr, w, (double*)nullptr)));
       }
       for (int pass = 0; pass < 2; ++pass) {

@@ -18,7 +18,9 @@ def test_iteration_byte_model_adds_up():
     # the per-level byte model used for the iteration-average rate: the
     # level-0 part at the 2D p=3 benchmark sizes is entry + 3 sweeps +
     # restriction + prolongation on the facet-trace form (4 of 10 rows or
-    # columns of each off-diagonal block stored), and the parts sum to the total
+    # columns of each off-diagonal block stored; D^{-1} and the diagonal
+    # blocks as upper triangles, 55 of 100 values), and the parts sum to the
+    # total
     import importlib.util
     spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
     b = importlib.util.module_from_spec(spec)
@@ -29,13 +31,14 @@ def test_iteration_byte_model_adds_up():
     nnzb = [797584, 161839, 48405, 14986, 4672, 1411]
     t = b.iteration_bytes(sizes, nnzb, 10, 4, 3)
     assert abs(t["total"] - sum(v for k, v in t.items() if k != "total")) < 1
-    n0, p2, off = sizes[0], 100, nnzb[0] - sizes[0]
+    n0, p2, pk, off = sizes[0], 100, 55, nnzb[0] - sizes[0]
     sweep = b.smoother_bytes(nnzb[0], n0, 10, 4, 4, 3)
-    assert sweep == off * 40 * 4 + 15 * n0 + n0 * p2 * 4 + 3 * n0 * 10 * 4
-    restrict = off * 40 * 4 + 15 * n0 + 2 * n0 * p2 * 4 + 3 * n0 * 10 * 4 + n0 * 10 * 4
-    level0 = ((n0 * 10 * 8 + n0 * p2 * 4 + 2 * n0 * 10 * 4) + sweep + restrict
+    assert sweep == off * 40 * 4 + 15 * n0 + n0 * pk * 4 + 3 * n0 * 10 * 4
+    assert b.smoother_bytes(nnzb[0], n0, 10, 4, 4, 3, sym=False) == sweep + n0 * (p2 - pk) * 4
+    restrict = off * 40 * 4 + 15 * n0 + n0 * (pk + p2) * 4 + 3 * n0 * 10 * 4 + n0 * 10 * 4
+    level0 = ((n0 * 10 * 8 + n0 * pk * 4 + 2 * n0 * 10 * 4) + sweep + restrict
               + (n0 * p2 * 4 + 2 * n0 * 10 * 4 + 4 * n0 + sizes[1] * 10 * 4) + 2 * sweep + n0 * 10 * 8)
     assert t["level0"] == level0
-    spmv = n0 * p2 * 8 + off * 40 * 8 + 15 * n0 + 3 * n0 * 10 * 8
+    spmv = n0 * pk * 8 + off * 40 * 8 + 15 * n0 + 3 * n0 * 10 * 8
     assert b.spmv_bytes(nnzb[0], n0, 10, 4, 3) == spmv
     assert t["outer"] == (n0 * 10 * 4 + 2 * n0 * 10 * 8) + spmv + 6 * n0 * 10 * 8

@@ -378,3 +378,23 @@ def test_level0_blocks_are_in_facet_trace_form(d, n, p, kw):
             assert col_form or row_form, (r, c)
             kinds["column" if col_form else "row"] += 1
     assert kinds["column"] > 0 and kinds["row"] > 0
+
+
+@pytest.mark.parametrize("d,n,p", [(2, 8, 3), (2, 8, 2), (3, 3, 3), (3, 3, 2)])
+def test_level0_diagonal_blocks_are_symmetric_bit_for_bit(d, n, p):
+    # the symmetric operator's diagonal blocks are stored as upper triangles
+    # on the GPU; that is exact only if every assembled diagonal block is
+    # symmetric bit for bit (and equal to the oracle's to rounding)
+    m = mesh2d_jittered_delaunay(n, 1) if d == 2 else mesh3d_kuhn(n, 1)
+    parents, sizes = cm.agglomerate(m, 2, 1, p=p)
+    kappa = np.exp(np.random.default_rng(3).standard_normal(m.n_elem))
+    rp, cols, blocks = cm.debug_host_operator(m, p, kappa, parents, sizes, 0)
+    cdg = CDG(m.coords, m.e2v, m.face_bc, p)
+    Ao = cdg.A(kappa).tocsr()
+    npb = blocks.shape[1]
+    for r in range(m.n_elem):
+        k = [k for k in range(rp[r], rp[r + 1]) if cols[k] == r][0]
+        B = blocks[k]
+        assert np.array_equal(B, B.T), r
+        O = Ao[r * npb:(r + 1) * npb, r * npb:(r + 1) * npb].toarray()
+        assert np.abs(B - O).max() <= 1e-13 * np.abs(O).max()
