@@ -623,6 +623,49 @@ __global__ __launch_bounds__(TPB) void k_spmv(int64_t n, const int32_t* __restri
   for (int i = 0; i < NP; ++i) y[r * NP + i] = acc[i];
 }
 
+template <typename T, bool NT>
+__device__ __forceinline__ T ld(const T* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
+// A row of N contiguous values (a row of a row-major [rows][N] vector) in the
+// widest loads or stores its alignment allows: N sizeof(T) bytes from a
+// 16-byte aligned base, so every row starts on a multiple of the largest power
+// of two (up to 16) dividing N sizeof(T).  A gathered neighbour row then costs
+// N sizeof(T) / A memory instructions instead of N.
+template <int A>
+struct alignas(A) RowChunk {
+  uint32_t w[A / 4];
+};
+template <typename T, int N>
+constexpr int row_align() {
+  return (N * (int)sizeof(T)) % 16 == 0 ? 16 : (N * (int)sizeof(T)) % 8 == 0 ? 8 : 4;
+}
+template <typename T, int N>
+__device__ __forceinline__ void load_row(const T* p, T* v) {
+  constexpr int A = row_align<T, N>(), C = N * (int)sizeof(T) / A;
+  const RowChunk<A>* q = reinterpret_cast<const RowChunk<A>*>(p);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const RowChunk<A> t = q[c];
+    __builtin_memcpy(reinterpret_cast<char*>(v) + c * A, &t, A);
+  }
+}
+template <typename T, int N>
+__device__ __forceinline__ void store_row(T* p, const T* v) {
+  constexpr int A = row_align<T, N>(), C = N * (int)sizeof(T) / A;
+  RowChunk<A>* q = reinterpret_cast<RowChunk<A>*>(p);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    RowChunk<A> t;
+    __builtin_memcpy(&t, reinterpret_cast<const char*>(v) + c * A, A);
+    q[c] = t;
+  }
+}
+
 // prolongation and correction: x_e += L_e x_c[parent(e)]
 template <typename T, int NP>
 __global__ __launch_bounds__(TPB) void k_prolong(int64_t n, const int32_t* __restrict__ parent,
@@ -632,17 +675,19 @@ __global__ __launch_bounds__(TPB) void k_prolong(int64_t n, const int32_t* __res
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   const int64_t I = parent[r];
-  T cv[NP];
-#pragma unroll
-  for (int j = 0; j < NP; ++j) cv[j] = xc[I * NP + j];
+  // the parent's and this row's x with wide loads, the new row with wide stores
+  T cv[NP], xv[NP];
+  load_row<T, NP>(xc + I * NP, cv);
+  load_row<T, NP>(x + r * NP, xv);
   const T* Lr = Lb + (r / WAVE) * WAVE * NP2 + (r % WAVE);
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
     T s = 0;
 #pragma unroll
     for (int j = 0; j < NP; ++j) s += __builtin_nontemporal_load(Lr + (i * NP + j) * WAVE) * cv[j];
-    x[r * NP + i] += s;
+    xv[i] += s;
   }
+  store_row<T, NP>(x + r * NP, xv);
 }
 
 // coarsest: x = A_L^{-1} b, one wavefront per row; the inverse is stored with
@@ -878,49 +923,6 @@ struct Acc<double, true> {
     return s + c;
   }
 };
-
-template <typename T, bool NT>
-__device__ __forceinline__ T ld(const T* p) {
-  if constexpr (NT)
-    return __builtin_nontemporal_load(p);
-  else
-    return *p;
-}
-
-// A row of N contiguous values (a row of a row-major [rows][N] vector) in the
-// widest loads or stores its alignment allows: N sizeof(T) bytes from a
-// 16-byte aligned base, so every row starts on a multiple of the largest power
-// of two (up to 16) dividing N sizeof(T).  A gathered neighbour row then costs
-// N sizeof(T) / A memory instructions instead of N.
-template <int A>
-struct alignas(A) RowChunk {
-  uint32_t w[A / 4];
-};
-template <typename T, int N>
-constexpr int row_align() {
-  return (N * (int)sizeof(T)) % 16 == 0 ? 16 : (N * (int)sizeof(T)) % 8 == 0 ? 8 : 4;
-}
-template <typename T, int N>
-__device__ __forceinline__ void load_row(const T* p, T* v) {
-  constexpr int A = row_align<T, N>(), C = N * (int)sizeof(T) / A;
-  const RowChunk<A>* q = reinterpret_cast<const RowChunk<A>*>(p);
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const RowChunk<A> t = q[c];
-    __builtin_memcpy(reinterpret_cast<char*>(v) + c * A, &t, A);
-  }
-}
-template <typename T, int N>
-__device__ __forceinline__ void store_row(T* p, const T* v) {
-  constexpr int A = row_align<T, N>(), C = N * (int)sizeof(T) / A;
-  RowChunk<A>* q = reinterpret_cast<RowChunk<A>*>(p);
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    RowChunk<A> t;
-    __builtin_memcpy(&t, reinterpret_cast<const char*>(v) + c * A, A);
-    q[c] = t;
-  }
-}
 
 // This wavefront's share of sign * A_off x at row r = 64 s + lane: column-kind
 // blocks into acc[t] (row h NI + t), row-kind blocks into sc[i] (all rows,
