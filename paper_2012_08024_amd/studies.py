@@ -30,7 +30,7 @@ import numpy as np
 
 from . import (COARSEN_FLUX, COARSEN_PRIMAL, MG_FP64, OUTER_FCG, OUTER_GMRES, SWITCH_CONSISTENT, SWITCH_NATURAL,
                CdgmgError, Solver, agglomerate, n_basis, switch)
-from .bytemodel import facet_nodes, smoother_bytes
+from .bytemodel import facet_nodes, row_block, smoother_bytes
 
 SETTINGS = {
     "paper": dict(nu1=0, nu2=3, omega=2.0 / 3.0, outer=OUTER_GMRES, restart=50, tol=1e-8),
@@ -184,7 +184,7 @@ def study_size(ns=(100, 158, 224, 316, 448, 632, 894), p=3, seed=2, agg_seed=12,
             row = dict(n=n, elements=int(mesh.n_elem), dofs=int(mesh.n_elem * npb), levels=len(sizes),
                        iterations=info.iterations, rel_residual=info.rel_residual, solve_ms=ms,
                        dofs_per_s=mesh.n_elem * npb / (ms * 1e-3), sweep_mb=sweep_bytes / 1e6,
-                       vcycle_operator_mb=(off * npb * facet_nodes(2, npb) + mesh.n_elem * npb * npb) * 4 / 1e6,
+                       vcycle_operator_mb=(off * npb * facet_nodes(2, npb) + mesh.n_elem * row_block(npb)) * 4 / 1e6,
                        sweep_us=sweep_us, sweep_gbs=sweep_bytes / (sweep_us * 1e-6) / 1e9,
                        device_gb=s.device_bytes() / 1e9)
         finally:
