@@ -207,7 +207,11 @@ int cdgmg_workspace_size(const cdgmg_mesh* mesh, int p, const cdgmg_hierarchy* h
  * of workspace_bytes >= cdgmg_workspace_size(...) bytes, aligned to 256
  * bytes; the handle keeps every device array in it and borrows it until
  * cdgmg_destroy returns.  Device work runs on `stream` (hipStream_t, NULL =
- * default); setup returns after it has finished.
+ * default); setup returns after it has finished.  The handle also creates
+ * one stream of its own (default priority), on which the operator builds
+ * (here and in cdgmg_update_kappa) run the work beside their critical chain;
+ * `stream` waits for it before these calls return, and cdgmg_destroy
+ * releases it.
  * Errors: ARG (p, options, kappa, workspace null, misaligned or too small: the
  * message names the size needed), MESH (non-positive volume, a facet shared
  * by more than two elements), HIERARCHY (map out of range / empty aggregate),
@@ -231,7 +235,8 @@ int cdgmg_setup(const cdgmg_mesh* mesh, int p, const double* kappa_dev,
  * (the check is thread-safe).  The array keeps the last handle's contents;
  * setup writes or clears every part it reads, so nothing of an earlier
  * handle is used.  Otherwise as cdgmg_setup, on the device current at the
- * call. */
+ * call, except that the handle creates no stream of its own: its operator
+ * builds run in order on `stream`. */
 int cdgmg_setup_static(const cdgmg_mesh* mesh, int p, const double* kappa_dev,
                        const cdgmg_hierarchy* hier, const cdgmg_options* opts, void* stream,
                        cdgmg_handle** out);
