@@ -20,7 +20,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from paper_2012_08024_amd.bytemodel import (facet_nodes, iteration_bytes, restrict_bytes,  # noqa: E402
+from paper_2012_08024_amd.bytemodel import (facet_nodes, iteration_bytes,  # noqa: E402
                                             smoother_bytes, spmv_bytes)
 
 METRIC = "DOFs/s to 1e-10 rel residual: FP32-MG-in-FP64-FCG vs FP64-MG; % HBM peak"

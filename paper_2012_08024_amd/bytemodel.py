@@ -27,13 +27,22 @@ def smoother_bytes(nnzb0, n0, npb, s, nfn, nf, sym=True):
     return off * npb * nfn * s + 5 * n0 * nf + n0 * row_block(npb, sym) * s + 3 * n0 * npb * s
 
 
-def restrict_bytes(nnzb0, n0, npb, s, nfn, nf, sym=True):
+def transfer0_bytes(n0, n1, npb, s, nf):
+    """What the level-0 transfers read to form L_e on the fly: each element's
+    affine map into its parent's scaled coordinates (d + d^2 values), its
+    parent index, and the parents' monomial coefficients (n_p^2 values per
+    aggregate, read once)."""
+    d = nf - 1
+    return n0 * (d + d * d) * s + 4 * n0 + n1 * npb * npb * s
+
+
+def restrict_bytes(nnzb0, n0, npb, s, nfn, nf, sym=True, n1=0):
     """Level-0 residual + restriction L_e^T (b - A_rr x - A_off x): the
-    off-diagonal values, indices and kinds, the diagonal blocks, L_e, b and x
-    read, the restricted residual written."""
+    off-diagonal values, indices and kinds, the diagonal blocks, the transfer
+    data, b and x read, the restricted residual written."""
     off = nnzb0 - n0
-    return (off * npb * nfn * s + 5 * n0 * nf + n0 * (row_block(npb, sym) + npb * npb) * s
-            + 3 * n0 * npb * s)
+    return (off * npb * nfn * s + 5 * n0 * nf + n0 * row_block(npb, sym) * s
+            + transfer0_bytes(n0, n1, npb, s, nf) + 3 * n0 * npb * s)
 
 
 def spmv_bytes(nnzb0, n0, npb, nfn, nf, sym=True):
@@ -49,7 +58,8 @@ def iteration_bytes(sizes, nnzb, npb, nfn, nf, nu1=2, nu2=2, s=4, sym=True):
     precision s (bytes) and the FP64 outer loop, per level: what each kernel
     must read and write once (operator blocks, indices, vectors), nothing for
     re-reads.  Level 0 runs on the facet-trace form with D^{-1} (per-row
-    blocks as upper triangles when sym, the operator being symmetric); the coarse
+    blocks as upper triangles when sym, the operator being symmetric) and forms
+    its transfers L_e from the element maps and parent coefficients; the coarse
     levels on D^{-1}-prescaled strips.  The first pre-sweep of every level is
     fused with forming D^{-1} b (no operator read); the last post-sweep of
     level 0 also reads q for the fused (z, q) dot."""
@@ -67,9 +77,10 @@ def iteration_bytes(sizes, nnzb, npb, nfn, nf, nu1=2, nu2=2, s=4, sym=True):
             break
         prolong = n[l] * p2 * s + 2 * n[l] * npb * s + 4 * n[l] + n[l + 1] * npb * s
         if l == 0:
+            prolong = transfer0_bytes(n[0], n[1], npb, s, nf) + 2 * n[0] * npb * s + n[1] * npb * s
             sweep = smoother_bytes(nz[0], n[0], npb, s, nfn, nf, sym)
             entry = n[0] * npb * 8 + n[0] * row_block(npb, sym) * s + 2 * n[0] * npb * s
-            restrict = restrict_bytes(nz[0], n[0], npb, s, nfn, nf, sym) + n[0] * npb * s
+            restrict = restrict_bytes(nz[0], n[0], npb, s, nfn, nf, sym, n[1]) + n[0] * npb * s
             b = entry + (nu1 - 1) * sweep + restrict + prolong + nu2 * sweep + n[0] * npb * 8
         else:
             off = nz[l] - n[l]

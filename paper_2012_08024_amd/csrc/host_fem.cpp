@@ -834,6 +834,25 @@ int build_problem(const cdgmg_mesh& m, int p, const cdgmg_hierarchy& h, const cd
     }
   };
 
+  // ---- level-0 affine maps into the parents' scaled coordinates
+  if (L > 0) {
+    const Level& c1 = P.lv[1];
+    const int na = d + d * d;
+    P.aff0.assign((size_t)N0 * na, 0.0);
+    parallel_for(N0, [&](int64_t r0, int64_t r1) {
+      for (int64_t r = r0; r < r1; ++r) {
+        const int64_t I = P.lv[0].parent[r];
+        Geo G = geometry(m, perm0[r]);
+        double* u = &P.aff0[(size_t)r * na];
+        const double h = c1.scale[I];
+        for (int c = 0; c < d; ++c) {
+          u[c] = (G.v0[c] - c1.center[I * d + c]) / h;
+          for (int a = 0; a < d; ++a) u[d + c * d + a] = G.J[c][a] / h;
+        }
+      }
+    });
+  }
+
   // ---- transfer blocks L_e (row = child basis function, col = parent basis function)
   for (int l = 0; l < L; ++l) {
     Level &f = P.lv[l], &c = P.lv[l + 1];

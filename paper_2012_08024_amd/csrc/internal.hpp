@@ -134,6 +134,11 @@ struct Problem {
   std::vector<double> Mblk;           // [N0][np][np] element mass matrices
   std::vector<double> Gblk;           // [d][N0][nf+1][np][np] flux-form gradient (kappa-free)
   std::vector<double> nodes;          // [N0 caller order][np][d]
+  // level 0 -> 1 transfers without stored blocks: for element r (internal
+  // order) the affine map xi -> (x(xi) - c_I) / h_I into the parent's scaled
+  // coordinates, u0[d] then Js[d][d] (row-major), so that
+  // L_e(i, j) = sum_k mono_k(u0 + Js xi_i) bcoef_I(k, j)
+  std::vector<double> aff0;           // [N0][d + d d]
   double beta = 0.0;                  // convection strength (0: none)
   std::vector<double> UC;             // [N0][nf+1][np][np] upwind convection blocks (beta != 0)
   bool flux = false;

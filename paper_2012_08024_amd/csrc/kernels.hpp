@@ -5,18 +5,19 @@
 // block of (row r = 64 s + lane, slot w) is stored at
 //     ((B_s + 64 w) * n_p^2) + (i n_p + j) * 64 + lane ,   B_s = slice_blk[s],
 // so for fixed (w, i, j) the 64 rows of a slice are contiguous (coalesced).
-// Per-row blocks (D^{-1}, transfer blocks L_e, mass blocks) use the same layout
-// with W = 1: (64 s) n_p^2 + (i n_p + j) 64 + lane; level 0 of a symmetric
+// Per-row blocks (D^{-1}, coarse-level transfer blocks L_e, mass blocks) use
+// the same layout with W = 1: (64 s) n_p^2 + (i n_p + j) 64 + lane; level 0 of a symmetric
 // operator keeps D^{-1} and its diagonal blocks as upper triangles
 // (n_p (n_p + 1) / 2 values per row, RowBlk in kernels.inl).  Vectors are
 // row-major [row][n_p].  Slot 0 of every row is its diagonal block.  Level 0
 // of the solve keeps its off-diagonal blocks in facet-trace form (their
-// facet-node rows or columns only; kernels.inl).
+// facet-node rows or columns only; kernels.inl) and forms its transfers L_e
+// from each element's affine map and its parent's monomial coefficients.
 //
 // Cache use: the FP32 level-0 V-cycle data (the facet-trace values and D^{-1},
 // 140 MB at 2D p = 3, 2e5 elements) is read four times per cycle and fits
 // the 256 MB last-level cache in part.  The streams read once per cycle or
-// per outer iteration (the FP64 outer operator, transfer blocks) use
+// per outer iteration (the FP64 outer operator, transfer data) use
 // non-temporal loads so that they do not push it out.
 #pragma once
 #include <hip/hip_runtime.h>

@@ -667,6 +667,130 @@ __device__ __forceinline__ void store_row(T* p, const T* v) {
 }
 
 // prolongation and correction: x_e += L_e x_c[parent(e)]
+// Level 0 <-> 1 transfers without stored blocks (Sec. 3.4): the child's
+// nodal coefficients of the parent's basis function j are its values at the
+// child's nodes, L_e(i, j) = sum_k mono_k(z_i) C_I(k, j), with z_i the node i
+// in the parent's scaled coordinates, z_i = u0 + Js xi_i (the element's affine
+// map composed with the parent's scaling, d + d^2 values per element) and
+// C_I the parent's monomial coefficients (n_p^2 values per aggregate, read
+// by all of its children).  The reference nodes and the graded monomial
+// exponents are compile-time tables in the order of the host's reference
+// element.
+template <int NP, int D>
+struct ElemTab {
+  static constexpr int P = D == 2 ? (NP == 3 ? 1 : NP == 6 ? 2 : 3) : (NP == 4 ? 1 : NP == 10 ? 2 : 3);
+  static constexpr int NA = D + D * D;  // affine map values per element
+  int ex[NP][3];                         // graded monomial exponents
+  int nd[NP][3];                         // reference node i in multiples of 1/P
+  constexpr ElemTab() : ex{}, nd{} {
+    int k = 0;
+    for (int deg = 0; deg <= P; ++deg) {
+      if (D == 2) {
+        for (int b = 0; b <= deg; ++b) {
+          ex[k][0] = deg - b;
+          ex[k][1] = b;
+          ++k;
+        }
+      } else {
+        for (int c = 0; c <= deg; ++c)
+          for (int b = 0; b <= deg - c; ++b) {
+            ex[k][0] = deg - b - c;
+            ex[k][1] = b;
+            ex[k][2] = c;
+            ++k;
+          }
+      }
+    }
+    int n = 0;
+    if (D == 2) {
+      for (int j = 0; j <= P; ++j)
+        for (int i = 0; i <= P - j; ++i) {
+          nd[n][0] = i;
+          nd[n][1] = j;
+          ++n;
+        }
+    } else {
+      for (int kk = 0; kk <= P; ++kk)
+        for (int j = 0; j <= P - kk; ++j)
+          for (int i = 0; i <= P - j - kk; ++i) {
+            nd[n][0] = i;
+            nd[n][1] = j;
+            nd[n][2] = kk;
+            ++n;
+          }
+    }
+  }
+};
+
+// the monomials of the parent's basis at node i of this row's element; u holds
+// the element's affine map (u0, then Js row by row)
+template <typename T, int NP, int D>
+__device__ __forceinline__ void node_monomials(const T* u, int i, T* mono) {
+  constexpr ElemTab<NP, D> E{};
+  T z[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    T v = u[c];
+#pragma unroll
+    for (int a = 0; a < D; ++a) v += u[D + c * D + a] * (T(E.nd[i][a]) / T(E.P));
+    z[c] = v;
+  }
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    T v = T(1);
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        if (q < E.ex[k][c]) v *= z[c];
+    mono[k] = v;
+  }
+}
+
+// this lane's element map, per-row layout (NA values per row)
+template <typename T, int NP, int D>
+__device__ __forceinline__ void load_affine(const T* __restrict__ aff, int64_t r, T* u) {
+  constexpr int NA = ElemTab<NP, D>::NA;
+#pragma unroll
+  for (int c = 0; c < NA; ++c) u[c] = __builtin_nontemporal_load(aff + ((r / WAVE) * NA + c) * WAVE + (r % WAVE));
+}
+
+// prolongation into level 0 with the transfer formed on the fly (Sec. 3.4):
+// x_e += L_e x_I = M_e (C_I x_I), M_e(i, k) = mono_k(z_i)
+template <typename T, int NP, int NF>
+__global__ __launch_bounds__(TPB) void k_prolong0(int64_t n, const int32_t* __restrict__ parent,
+                                                  const T* __restrict__ aff, const T* __restrict__ Cp,
+                                                  const T* __restrict__ xc, T* __restrict__ x) {
+  constexpr int NP2 = NP * NP, D = NF - 1;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int64_t I = parent[r];
+  T cv[NP], y[NP], xv[NP], u[ElemTab<NP, D>::NA];
+  load_row<T, NP>(xc + I * NP, cv);
+  const T* C = Cp + I * NP2;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    T crow[NP];
+    load_row<T, NP>(C + k * NP, crow);
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) s += crow[j] * cv[j];
+    y[k] = s;
+  }
+  load_affine<T, NP, D>(aff, r, u);
+  load_row<T, NP>(x + r * NP, xv);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    T mono[NP];
+    node_monomials<T, NP, D>(u, i, mono);
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) s += mono[k] * y[k];
+    xv[i] += s;
+  }
+  store_row<T, NP>(x + r * NP, xv);
+}
+
 template <typename T, int NP>
 __global__ __launch_bounds__(TPB) void k_prolong(int64_t n, const int32_t* __restrict__ parent,
                                                  const T* __restrict__ Lb, const T* __restrict__ xc,
@@ -1196,9 +1320,10 @@ template <typename T, int NP, int H, int NF, bool SYM>
 __global__ __launch_bounds__(WAVE * H) void k_restrict0(int64_t n, const int32_t* __restrict__ cols,
                                                         const int8_t* __restrict__ meta, const T* __restrict__ Ac,
                                                         const T* __restrict__ Ad, const T* __restrict__ b,
-                                                        const T* __restrict__ x, const T* __restrict__ Lb,
-                                                        T* __restrict__ t_out, int rev) {
-  constexpr int NP2 = NP * NP, NI = NP / H;
+                                                        const T* __restrict__ x, const T* __restrict__ aff,
+                                                        const int32_t* __restrict__ parent,
+                                                        const T* __restrict__ Cp, T* __restrict__ t_out, int rev) {
+  constexpr int NP2 = NP * NP, NI = NP / H, D = NF - 1;
   __shared__ T sh[H > 1 ? NP * WAVE : 1];
   const int lane = threadIdx.x % WAVE, h = threadIdx.x / WAVE;
   const int64_t sl = slice_order(rev), r = sl * WAVE + lane;
@@ -1206,24 +1331,38 @@ __global__ __launch_bounds__(WAVE * H) void k_restrict0(int64_t n, const int32_t
   T res[NP];
   residual0<T, NP, H, NF, SYM>(sl, r, lane, h, valid, cols, meta, Ac, Ad, b, x, sh, res);
   if (!valid) return;
-  const T* Lr = Lb + sl * WAVE * NP2 + lane;
-  if constexpr (H == 1 && sizeof(T) == 4) {
+  // t = L_e^T res = C_I^T w, w_k = sum_i mono_k(z_i) res_i
+  T u[ElemTab<NP, D>::NA], w[NP];
+  load_affine<T, NP, D>(aff, r, u);
+#pragma unroll
+  for (int k = 0; k < NP; ++k) w[k] = T(0);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    T mono[NP];
+    node_monomials<T, NP, D>(u, i, mono);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) w[k] += mono[k] * res[i];
+  }
+  const T* C = Cp + (int64_t)parent[r] * NP2;
+  if constexpr (H == 1) {
     T tv[NP];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
-      T s = 0;
+    for (int j = 0; j < NP; ++j) tv[j] = T(0);
 #pragma unroll
-      for (int i = 0; i < NP; ++i) s += __builtin_nontemporal_load(Lr + (i * NP + j) * WAVE) * res[i];
-      tv[j] = s;
+    for (int k = 0; k < NP; ++k) {
+      T crow[NP];
+      load_row<T, NP>(C + k * NP, crow);
+#pragma unroll
+      for (int j = 0; j < NP; ++j) tv[j] += crow[j] * w[k];
     }
     store_row<T, NP>(t_out + r * NP, tv);
   } else {
-#pragma unroll 2
+#pragma unroll
     for (int t = 0; t < NI; ++t) {
       const int j = h * NI + t;
       T s = 0;
 #pragma unroll
-      for (int i = 0; i < NP; ++i) s += __builtin_nontemporal_load(Lr + (i * NP + j) * WAVE) * res[i];
+      for (int k = 0; k < NP; ++k) s += C[k * NP + j] * w[k];
       t_out[r * NP + j] = s;
     }
   }

@@ -137,7 +137,9 @@ struct DLevel {
   int8_t* meta = nullptr;  // level 0: facet-trace kind of each off-diagonal slot
   void* Dm = nullptr;  // D^{-1}
   void* Lt = nullptr;  // D^T L_e (D the diagonal block of A), levels 1 .. L-1
-  void* Lm = nullptr;  // L_e
+  void* Lm = nullptr;  // L_e, levels 1 .. L-1 (level 0 forms it from Aff and Cp)
+  void* Aff = nullptr;  // level 0: each element's map into its parent's scaled coordinates, per-row layout
+  void* Cp = nullptr;   // level 0: the parents' monomial coefficients, [n_1][n_p][n_p]
   int32_t* parent = nullptr;
   int32_t* child_start = nullptr;
   int32_t* blk_row = nullptr;
@@ -538,10 +540,35 @@ int upload_problem(cdgmg_handle* h) {
       RETURN_IF(dalloc(h, &D.D64, rowblk));
       std::vector<double> Lr = to_rows(H.Lblk, H.n, np2);
       RETURN_IF(upload(h, &D.L64, Lr));
+      if (l == 0) {  // the V-cycle's level-0 transfers form L_e on the fly
+        const int na = P.d + P.d * P.d;
+        if (P.aff0.size() != (size_t)H.n * na || P.lv[1].bcoef.size() != (size_t)P.lv[1].n * np2) {
+          set_error("setup: the level-0 element maps are missing");
+          return CDGMG_ERR_HIERARCHY;
+        }
+        std::vector<double> Ar = to_rows(P.aff0, H.n, na);
+        const std::vector<double>& C1 = P.lv[1].bcoef;
+        if (fp32) {
+          float* tmp;
+          RETURN_IF(upload(h, &tmp, std::vector<float>(Ar.begin(), Ar.end())));
+          D.Aff = tmp;
+          RETURN_IF(upload(h, &tmp, std::vector<float>(C1.begin(), C1.end())));
+          D.Cp = tmp;
+        } else {
+          double* tmp;
+          RETURN_IF(upload(h, &tmp, Ar));
+          D.Aff = tmp;
+          RETURN_IF(upload(h, &tmp, C1));
+          D.Cp = tmp;
+        }
+        std::vector<double>().swap(P.aff0);
+      }
       if (fp32) {
         float* tmp;
-        RETURN_IF(upload(h, &tmp, std::vector<float>(Lr.begin(), Lr.end())));
-        D.Lm = tmp;
+        if (l > 0) {
+          RETURN_IF(upload(h, &tmp, std::vector<float>(Lr.begin(), Lr.end())));
+          D.Lm = tmp;
+        }
         RETURN_IF(dalloc(h, &tmp, l == 0 ? rowblk0 : rowblk));
         D.Dm = tmp;
         if (l > 0) {
@@ -1128,7 +1155,8 @@ T* vcycle_t(cdgmg_handle* h, const double* r64, const double* dv, int* nparts) {
       const int rev = h->at_pass++ & 1;
       L0_DISPATCH(h, launch(h, CDGMG_K_RESTRICT, k_restrict0<T, NP, H, NF, SYM>, dim3((unsigned)d.ns), dim3(WAVE * H),
                             d.n, (const int32_t*)d.cols, (const int8_t*)d.meta, (const T*)d.Ac, (const T*)d.Ad,
-                            (const T*)d.b, (const T*)xs[0], (const T*)d.Lm, (T*)d.t, rev));
+                            (const T*)d.b, (const T*)xs[0], (const T*)d.Aff, (const int32_t*)d.parent,
+                            (const T*)d.Cp, (T*)d.t, rev));
     } else {
       G_DISPATCH(d.grp_r, launch(h, CDGMG_K_RESTRICT, k_restrict_grp<T, NP, G>, dim3(grid_for(d.n * G)), dim3(TPB),
                              d.n, (const int32_t*)d.wcols, (const int64_t*)d.woff, (const T*)d.R, (const T*)d.b,
@@ -1145,7 +1173,11 @@ T* vcycle_t(cdgmg_handle* h, const double* r64, const double* dv, int* nparts) {
   for (int l = L - 1; l >= 0; --l) {
     DLevel& d = h->lv[l];
     const bool fused = l >= 1 && l + 1 < L && nu2 > 0;
-    if (!fused) {
+    if (l == 0) {
+      NF_DISPATCH(h->P.nf, launch(h, CDGMG_K_PROLONG, k_prolong0<T, NP, NF>, dim3(grid_for(d.n)), dim3(TPB), d.n,
+                                  (const int32_t*)d.parent, (const T*)d.Aff, (const T*)d.Cp, (const T*)xs[1],
+                                  xs[0]));
+    } else if (!fused) {
       const int tpb = row_tpb(h, l);
       launch(h, CDGMG_K_PROLONG, k_prolong<T, NP>, dim3(grid_for(d.n, tpb)), dim3(tpb), d.n,
              (const int32_t*)d.parent, (const T*)d.Lm, (const T*)xs[l + 1], xs[l]);

@@ -19,8 +19,8 @@ def test_iteration_byte_model_adds_up():
     # level-0 part at the 2D p=3 benchmark sizes is entry + 3 sweeps +
     # restriction + prolongation on the facet-trace form (4 of 10 rows or
     # columns of each off-diagonal block stored; D^{-1} and the diagonal
-    # blocks as upper triangles, 55 of 100 values), and the parts sum to the
-    # total
+    # blocks as upper triangles, 55 of 100 values; the transfers formed on the
+    # fly), and the parts sum to the total
     import importlib.util
     spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
     b = importlib.util.module_from_spec(spec)
@@ -35,9 +35,12 @@ def test_iteration_byte_model_adds_up():
     sweep = b.smoother_bytes(nnzb[0], n0, 10, 4, 4, 3)
     assert sweep == off * 40 * 4 + 15 * n0 + n0 * pk * 4 + 3 * n0 * 10 * 4
     assert b.smoother_bytes(nnzb[0], n0, 10, 4, 4, 3, sym=False) == sweep + n0 * (p2 - pk) * 4
-    restrict = off * 40 * 4 + 15 * n0 + n0 * (pk + p2) * 4 + 3 * n0 * 10 * 4 + n0 * 10 * 4
+    # the transfers form L_e from each element's 2 + 4 map values, its parent
+    # index and the parents' 100 monomial coefficients
+    tr = n0 * 6 * 4 + 4 * n0 + sizes[1] * p2 * 4
+    restrict = off * 40 * 4 + 15 * n0 + n0 * pk * 4 + tr + 3 * n0 * 10 * 4 + n0 * 10 * 4
     level0 = ((n0 * 10 * 8 + n0 * pk * 4 + 2 * n0 * 10 * 4) + sweep + restrict
-              + (n0 * p2 * 4 + 2 * n0 * 10 * 4 + 4 * n0 + sizes[1] * 10 * 4) + 2 * sweep + n0 * 10 * 8)
+              + (tr + 2 * n0 * 10 * 4 + sizes[1] * 10 * 4) + 2 * sweep + n0 * 10 * 8)
     assert t["level0"] == level0
     spmv = n0 * pk * 8 + off * 40 * 8 + 15 * n0 + 3 * n0 * 10 * 8
     assert b.spmv_bytes(nnzb[0], n0, 10, 4, 3) == spmv
