@@ -1174,9 +1174,10 @@ T* vcycle_t(cdgmg_handle* h, const double* r64, const double* dv, int* nparts) {
     DLevel& d = h->lv[l];
     const bool fused = l >= 1 && l + 1 < L && nu2 > 0;
     if (l == 0) {
-      NF_DISPATCH(h->P.nf, launch(h, CDGMG_K_PROLONG, k_prolong0<T, NP, NF>, dim3(grid_for(d.n)), dim3(TPB), d.n,
-                                  (const int32_t*)d.parent, (const T*)d.Aff, (const T*)d.Cp, (const T*)xs[1],
-                                  xs[0]));
+      const int tpb = row_tpb(h, 0);
+      NF_DISPATCH(h->P.nf, launch(h, CDGMG_K_PROLONG, k_prolong0<T, NP, NF>, dim3(grid_for(d.n, tpb)), dim3(tpb),
+                                  d.n, (const int32_t*)d.parent, (const T*)d.Aff, (const T*)d.Cp,
+                                  (const T*)xs[1], xs[0]));
     } else if (!fused) {
       const int tpb = row_tpb(h, l);
       launch(h, CDGMG_K_PROLONG, k_prolong<T, NP>, dim3(grid_for(d.n, tpb)), dim3(tpb), d.n,
