@@ -873,6 +873,101 @@ __global__ __launch_bounds__(TPB) void k_dense_gemv(int64_t n, int64_t ld, const
   if (lane == 0) x[row] = s;
 }
 
+// The coarsest level in one launch (hierarchies of three or more levels):
+// every workgroup first forms the whole coarsest right-hand side in LDS,
+// b_I = sum of the children's restricted residuals t_e (in the order of the
+// coarse entry), then x_I = (A_L^{-1} b)_I for its own aggregate I, one
+// wavefront per row as in the dense product above, and finally prolongs x_I
+// into I's children on the level above, x_f[e] += L_e x_I (Sec. 3.4).  It
+// replaces three launches whose work is a few microseconds each.  TA is the
+// inverse's storage type (double with FP32 vectors: summed in FP64).  LDS:
+// ld + NP values of T (dynamic).
+template <typename T, typename TA, int NP>
+__global__ __launch_bounds__(1024) void k_coarsest(int64_t n, int64_t ld, const TA* __restrict__ Ainv,
+                                                   const int32_t* __restrict__ cs, const T* __restrict__ t,
+                                                   const T* __restrict__ Lf, T* __restrict__ xc,
+                                                   T* __restrict__ xf) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* sb = reinterpret_cast<T*>(smem);
+  T* sx = sb + ld;
+  using V = typename Vec16<TA>::type;
+  constexpr int KV = Vec16<TA>::k;
+  const int64_t I = blockIdx.x, nd = n * NP;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  // the prolongation's operands do not depend on x_I: thread k = tid takes
+  // component a of child e and loads its row of L_e and x_f first
+  const int32_t e0 = cs[I];
+  const int ne = cs[I + 1] - e0;
+  T lv[NP], xv = 0;
+  const bool own = tid < ne * NP;
+  if (own) {
+    const int64_t e = e0 + tid / NP;
+    const int a = tid % NP;
+    const T* Lr = Lf + (e / WAVE) * WAVE * NP * NP + (e % WAVE);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) lv[j] = __builtin_nontemporal_load(Lr + (a * NP + j) * WAVE);
+    xv = xf[e * NP + a];
+  }
+  // b in LDS: each entry's children loaded together, then summed in order
+  for (int64_t k = tid; k < ld; k += nt) {
+    T s = 0;
+    if (k < nd) {
+      const int64_t a = k / NP;
+      const int j = (int)(k - a * NP);
+      const int32_t c1 = cs[a + 1];
+      for (int32_t e = cs[a]; e < c1; e += 4) {
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = e + u < c1 ? t[(int64_t)(e + u) * NP + j] : T(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (e + u < c1) s += v[u];
+      }
+    }
+    sb[k] = s;
+  }
+  __syncthreads();
+  const int w = tid / WAVE, lane = tid % WAVE, nw = nt / WAVE;
+  for (int i = w; i < NP; i += nw) {
+    const int64_t row = I * NP + i;
+    const V* Ar = reinterpret_cast<const V*>(Ainv + row * ld);
+    TA s = 0;
+#pragma unroll 8
+    for (int64_t c = lane; c < ld / KV; c += WAVE) {
+      V bv;
+      if constexpr (sizeof(TA) == sizeof(T)) {
+        bv = reinterpret_cast<const V*>(sb)[c];
+      } else {
+        bv.x = (TA)sb[2 * c];
+        bv.y = (TA)sb[2 * c + 1];
+      }
+      s += Vec16<TA>::dot(Ar[c], bv);
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if (lane == 0) {
+      sx[i] = (T)s;
+      xc[row] = (T)s;
+    }
+  }
+  __syncthreads();
+  if (own) {
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) s += lv[j] * sx[j];
+    xf[(e0 + tid / NP) * (int64_t)NP + tid % NP] = xv + s;
+  }
+  // an aggregate of more than blockDim / n_p children: the rest in further passes
+  for (int k = tid + nt; k < ne * NP; k += nt) {
+    const int64_t e = e0 + k / NP;
+    const int a = k % NP;
+    const T* Lr = Lf + (e / WAVE) * WAVE * NP * NP + (e % WAVE);
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) s += __builtin_nontemporal_load(Lr + (a * NP + j) * WAVE) * sx[j];
+    xf[e * NP + a] += s;
+  }
+}
+
 // ------------------------------------------------------------------
 // Error-free transformations (Knuth TwoSum; FMA TwoProduct) for the outer
 // loop.  The relative rounding noise of a plain FP64 product A x is about

@@ -326,18 +326,22 @@ hipEvent_t next_event(cdgmg_handle* h) {
 }
 
 template <typename K, typename... Args>
-void launch(cdgmg_handle* h, int cls, K kernel, dim3 grid, dim3 block, Args... args) {
+void launch_lds(cdgmg_handle* h, int cls, K kernel, dim3 grid, dim3 block, size_t lds, Args... args) {
   hipEvent_t a = nullptr, b = nullptr;
   if (h->o.profile && cls >= 0) {
     a = next_event(h);
     b = next_event(h);
     if (a) (void)hipEventRecord(a, h->stream);
   }
-  hipLaunchKernelGGL(kernel, grid, block, 0, h->stream, args...);
+  hipLaunchKernelGGL(kernel, grid, block, lds, h->stream, args...);
   if (a && b) {
     (void)hipEventRecord(b, h->stream);
     h->evs.push_back({cls, a, b});
   }
+}
+template <typename K, typename... Args>
+void launch(cdgmg_handle* h, int cls, K kernel, dim3 grid, dim3 block, Args... args) {
+  launch_lds(h, cls, kernel, grid, block, 0, args...);
 }
 
 // row-major [n][W][np2] -> sliced-ELL layout of the level
@@ -1062,6 +1066,9 @@ void dot_t(cdgmg_handle* h, const T* z, const double* dv, int* nparts) {
 
 // thread-per-row kernels: one-wavefront workgroups on small levels spread the
 // few wavefronts over the compute units
+// LDS of the one-launch coarsest level (its padded right-hand side)
+constexpr size_t COARSEST_LDS = 48 * 1024;
+
 inline int row_tpb(const cdgmg_handle* h, int l) {
   if (h->o.row_threads) return h->o.row_threads;
   return h->lv[l].n < 100000 ? WAVE : TPB;
@@ -1164,9 +1171,31 @@ T* vcycle_t(cdgmg_handle* h, const double* r64, const double* dv, int* nparts) {
     }
   }
   DLevel& c = h->lv[L];
-  launch(h, CDGMG_K_COARSE, k_entry_c<T, NP>, dim3(grid_for(c.n, WAVE)), dim3(WAVE), c.n,
-         (const int32_t*)c.child_start, (const T*)h->lv[L - 1].t, (const T*)nullptr, omega, (T*)c.b, (T*)nullptr);
-  coarse_solve<T>(h, (const T*)c.b, xs[L]);
+  // from three levels on, the coarsest level's entry, solve and prolongation
+  // into level L - 1 run as one launch (its right-hand side formed in LDS)
+  const size_t lds = (size_t)(h->ld + NP) * sizeof(T);
+  const bool one = L >= 2 && lds <= COARSEST_LDS;
+  if (one) {
+    const DLevel& f = h->lv[L - 1];
+    const dim3 grid((unsigned)c.n), block((unsigned)std::min(NP, 16) * WAVE);
+    bool mixed = false;
+    if constexpr (sizeof(T) == 4) {
+      if (h->o.coarse_fp64) {
+        mixed = true;
+        launch_lds(h, CDGMG_K_COARSE, k_coarsest<float, double, NP>, grid, block, lds, c.n, h->ld,
+                   (const double*)h->dense, (const int32_t*)c.child_start, (const float*)f.t, (const float*)f.Lm,
+                   (float*)xs[L], (float*)xs[L - 1]);
+      }
+    }
+    if (!mixed)
+      launch_lds(h, CDGMG_K_COARSE, k_coarsest<T, T, NP>, grid, block, lds, c.n, h->ld, (const T*)h->AinvP,
+                 (const int32_t*)c.child_start, (const T*)f.t, (const T*)f.Lm, xs[L], xs[L - 1]);
+  } else {
+    launch(h, CDGMG_K_COARSE, k_entry_c<T, NP>, dim3(grid_for(c.n, WAVE)), dim3(WAVE), c.n,
+           (const int32_t*)c.child_start, (const T*)h->lv[L - 1].t, (const T*)nullptr, omega, (T*)c.b,
+           (T*)nullptr);
+    coarse_solve<T>(h, (const T*)c.b, xs[L]);
+  }
   // upward: the last post-sweep of a level l >= 2 also prolongs into level
   // l - 1, where a separate launch would be bound by its latency (from the
   // coarsest level, into level 0, or with nu2 = 0, a separate launch)
@@ -1178,7 +1207,7 @@ T* vcycle_t(cdgmg_handle* h, const double* r64, const double* dv, int* nparts) {
       NF_DISPATCH(h->P.nf, launch(h, CDGMG_K_PROLONG, k_prolong0<T, NP, NF>, dim3(grid_for(d.n, tpb)), dim3(tpb),
                                   d.n, (const int32_t*)d.parent, (const T*)d.Aff, (const T*)d.Cp,
                                   (const T*)xs[1], xs[0]));
-    } else if (!fused) {
+    } else if (!fused && !(one && l == L - 1)) {
       const int tpb = row_tpb(h, l);
       launch(h, CDGMG_K_PROLONG, k_prolong<T, NP>, dim3(grid_for(d.n, tpb)), dim3(tpb), d.n,
              (const int32_t*)d.parent, (const T*)d.Lm, (const T*)xs[l + 1], xs[l]);

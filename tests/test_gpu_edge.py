@@ -122,3 +122,27 @@ def test_coarsest_level_too_large_is_rejected():
     assert ei.value.code == -1
     parents, sizes = cm.agglomerate(mesh, 3, 0, p=3)
     cm.Solver(mesh, 3, np.ones(mesh.n_elem), parents, sizes).close()
+
+
+@pytest.mark.parametrize("p,mg,cf", [(1, "fp64", 0), (3, "fp64", 0), (1, "fp32", 0), (3, "fp32", 1)])
+def test_coarsest_aggregate_with_many_children(p, mg, cf):
+    # one coarsest aggregate holding every level-1 aggregate (more than 64 of
+    # them): the one-launch coarsest level (entry, dense solve, prolongation)
+    # then prolongs into its children in more than one pass of its workgroup
+    mesh = mesh2d_jittered_delaunay(24, 1)
+    p1, s1 = cm.agglomerate(mesh, 2, 5, p=p)
+    assert len(s1) == 2 and s1[1] > 64
+    parents = [p1[0], np.zeros(s1[1], dtype=np.int32)]
+    sizes = np.array([s1[0], s1[1], 1], dtype=np.int32)
+    kappa = np.random.default_rng(4).uniform(0.5, 2.0, mesh.n_elem)
+    print("case many-children", p, mg, cf, list(sizes), flush=True)
+    prec = cm.MG_FP64 if mg == "fp64" else cm.MG_FP32
+    solver = cm.Solver(mesh, p, kappa, parents, sizes, mg_precision=prec, coarse_fp64=cf)
+    cdg = CDG(mesh.coords, mesh.e2v, mesh.face_bc, p)
+    H = Hierarchy(cdg, parents, kappa=kappa, coarsening="primal")
+    r = np.random.default_rng(2).standard_normal(H.A[0].shape[0])
+    z = solver.vcycle(r).cpu().numpy()
+    ref = H.vcycle(r, 2, 2, 0.7)
+    tol = 1e-11 if mg == "fp64" else 1e-4
+    assert np.linalg.norm(z - ref) <= tol * np.linalg.norm(ref)
+    solver.close()
