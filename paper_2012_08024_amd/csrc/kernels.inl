@@ -1733,7 +1733,8 @@ __global__ __launch_bounds__(TPB) void k_sweep_grp(int64_t n, const int32_t* __r
 }
 
 // every lane forms the whole scaled residual of its row (n_p values), then
-// lane g writes t_j = sum_i Lt(i, j) res_i for j = g, g + G, ...
+// lane g writes t_j = sum_i Lt(i, j) res_i for j = g, g + G, ... (column j
+// of the row's Lt contiguous)
 template <typename T, int NP, int G>
 __global__ __launch_bounds__(TPB) void k_restrict_grp(int64_t n, const int32_t* __restrict__ wcols,
                                                       const int64_t* __restrict__ woff, const T* __restrict__ R,
@@ -1748,14 +1749,15 @@ __global__ __launch_bounds__(TPB) void k_restrict_grp(int64_t n, const int32_t* 
   grp_scaled_residual<T, NP, G>(r, g, wcols, woff, R, x, res);
 #pragma unroll
   for (int i = 0; i < NP; ++i) res[i] = bt[r * NP + i] - x[r * NP + i] - res[i];
-  const T* Lr = Lt + (r / WAVE) * WAVE * NP2 + (r % WAVE);
 #pragma unroll
   for (int m = 0; m < (NP + G - 1) / G; ++m) {
     const int j = g + m * G;
     if (j < NP) {
+      T col[NP];
+      load_row<T, NP>(Lt + r * NP2 + j * NP, col);
       T s = 0;
 #pragma unroll
-      for (int i = 0; i < NP; ++i) s += Lr[(i * NP + j) * WAVE] * res[i];
+      for (int i = 0; i < NP; ++i) s += col[i] * res[i];
       t[r * NP + j] = s;
     }
   }
@@ -1862,9 +1864,11 @@ __global__ void k_scale_wpr(int64_t nnzb, const int32_t* __restrict__ blk_row, c
   R[(o - r) * NP2 + (int64_t)i * K + (w - 1) * NP + j] = (T)acc;
 }
 
-// Lt_e = D_e^T L_e (D_e the diagonal block of A), per-row layout, so that
-// Lt^T (D^{-1} r) = L^T r also for a nonsymmetric D; one thread per
-// (row, i, j), rows fastest
+// Lt_e = D_e^T L_e (D_e the diagonal block of A), so that
+// Lt^T (D^{-1} r) = L^T r also for a nonsymmetric D; stored column by column
+// per row, Lt_e(i, j) at e n_p^2 + j n_p + i, so that the restriction's lane
+// for output j reads its column with wide loads; one thread per (row, i, j),
+// rows fastest
 template <typename T, int NP>
 __global__ void k_scale_L(int64_t n, const int64_t* __restrict__ sblk, const double* __restrict__ A,
                           const double* __restrict__ L, T* __restrict__ Lt) {
@@ -1881,7 +1885,7 @@ __global__ void k_scale_L(int64_t n, const int64_t* __restrict__ sblk, const dou
   double acc = 0.0;
 #pragma unroll
   for (int m = 0; m < NP; ++m) acc += A[blk_off(B, 0, NP2, m * NP + i, lane)] * L[row_off(r, NP2, m * NP + j)];
-  Lt[row_off(r, NP2, ij)] = (T)acc;
+  Lt[r * NP2 + j * NP + i] = (T)acc;
 }
 
 // ---------------------------------------------------------- outer (FP64) kernels
