@@ -1592,9 +1592,20 @@ __global__ __launch_bounds__(TPB) void k_entry_c(int64_t n, const int32_t* __res
   T bv[NP];
 #pragma unroll
   for (int j = 0; j < NP; ++j) bv[j] = 0;
-  for (int32_t e = child_start[r]; e < child_start[r + 1]; ++e)
+  // children two at a time with wide loads, summed in order
+  const int32_t c1 = child_start[r + 1];
+  for (int32_t e = child_start[r]; e < c1; e += 2) {
+    T v0[NP], v1[NP];
+    load_row<T, NP>(t + (int64_t)e * NP, v0);
+    const bool two = e + 1 < c1;
+    if (two) load_row<T, NP>(t + (int64_t)(e + 1) * NP, v1);
 #pragma unroll
-    for (int j = 0; j < NP; ++j) bv[j] += t[(int64_t)e * NP + j];
+    for (int j = 0; j < NP; ++j) bv[j] += v0[j];
+    if (two) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) bv[j] += v1[j];
+    }
+  }
   if (Dinv == nullptr) {
 #pragma unroll
     for (int j = 0; j < NP; ++j) bt[r * NP + j] = bv[j];
@@ -2250,14 +2261,29 @@ __global__ void k_out_dd(int64_t n, int np, const int32_t* __restrict__ perm, co
 // mode 0: FCG beta = s[ZQ] / s[PQOLD]; mode 1: PCG beta = s[ZR] / s[ZROLD]
 // mode 2: FCG alpha = s[PR] / s[PQ], PQOLD = PQ; mode 3: PCG alpha = s[ZR] / s[PQ], ZROLD = ZR
 
-// p = z + sign * beta * p  (first iteration: p = z); z in the multigrid precision
+// p = z + sign * beta * p  (first iteration: p = z); z in the multigrid
+// precision; four entries per thread with wide loads and stores
+constexpr int UP_K = 4;
 template <typename T>
-__global__ void k_update_p(int64_t m, const T* __restrict__ z, double* __restrict__ p, const double* __restrict__ s,
-                           double sign, int first) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  const double zi = (double)__builtin_nontemporal_load(z + i);
-  p[i] = first ? zi : zi + sign * s[SC_BETA] * p[i];
+__global__ __launch_bounds__(TPB) void k_update_p(int64_t m, const T* __restrict__ z, double* __restrict__ p,
+                                                  const double* __restrict__ s, double sign, int first) {
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * UP_K;
+  if (i0 >= m) return;
+  const double c = first ? 0.0 : sign * s[SC_BETA];
+  if (i0 + UP_K <= m) {
+    T zv[UP_K];
+    double pv[UP_K];
+    load_row<T, UP_K>(z + i0, zv);
+    if (!first) load_row<double, UP_K>(p + i0, pv);
+#pragma unroll
+    for (int k = 0; k < UP_K; ++k) pv[k] = first ? (double)zv[k] : (double)zv[k] + c * pv[k];
+    store_row<double, UP_K>(p + i0, pv);
+  } else {
+    for (int64_t i = i0; i < m; ++i) {
+      const double zi = (double)z[i];
+      p[i] = first ? zi : zi + c * p[i];
+    }
+  }
 }
 
 // partial sums of (z, v), z in the multigrid precision, grid-stride

@@ -1354,12 +1354,13 @@ int krylov_cg(cdgmg_handle* h, cdgmg_solve_info* info) {
       launch(h, CDGMG_K_VECTOR, k_reduce, dim3(1), dim3(RED_T), (const double*)h->part, nz, 1, h->scal,
              fcg ? (int)SC_ZQ : (int)SC_ZR, iter > 0 ? (fcg ? 0 : 1) : -1);
     const double sign = fcg ? -1.0 : 1.0;
+    const dim3 gp(grid_for((m + UP_K - 1) / UP_K));
     if (h->o.mg_precision == CDGMG_MG_FP32)
-      launch(h, CDGMG_K_VECTOR, k_update_p<float>, dim3(grid_for(m)), dim3(TPB), m, (const float*)z, h->p,
-             (const double*)h->scal, sign, iter == 0 ? 1 : 0);
+      launch(h, CDGMG_K_VECTOR, k_update_p<float>, gp, dim3(TPB), m, (const float*)z, h->p, (const double*)h->scal,
+             sign, iter == 0 ? 1 : 0);
     else
-      launch(h, CDGMG_K_VECTOR, k_update_p<double>, dim3(grid_for(m)), dim3(TPB), m, (const double*)z, h->p,
-             (const double*)h->scal, sign, iter == 0 ? 1 : 0);
+      launch(h, CDGMG_K_VECTOR, k_update_p<double>, gp, dim3(TPB), m, (const double*)z, h->p, (const double*)h->scal,
+             sign, iter == 0 ? 1 : 0);
     const unsigned g = (unsigned)d0.ns;
     if (accurate) {
       NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv0<NP, H, NF, SYM, true>, dim3(g), dim3(WAVE * H),
