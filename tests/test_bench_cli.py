@@ -45,3 +45,20 @@ def test_iteration_byte_model_adds_up():
     spmv = n0 * pk * 8 + off * 40 * 8 + 15 * n0 + 3 * n0 * 10 * 8
     assert b.spmv_bytes(nnzb[0], n0, 10, 4, 3) == spmv
     assert t["outer"] == (n0 * 10 * 4 + 2 * n0 * 10 * 8) + spmv + 6 * n0 * 10 * 8
+
+
+def test_byte_model_3d_p3_figures():
+    # the 3D p = 3 (n_p = 20) workload of 384 000 tetrahedra, 1 900 800 block
+    # slots and 22 569 level-1 aggregates: facet-trace blocks keep 10 of 20
+    # rows or columns, the packed blocks 210 of 400 values, each element's
+    # map 3 + 9 values; these are the per-launch figures the kernel-trace
+    # summaries quote
+    from paper_2012_08024_amd import bytemodel as bm
+    n0, nnzb0, n1 = 384000, 1900800, 22569
+    assert bm.facet_nodes(3, 20) == 10 and bm.row_block(20) == 210
+    sweep = bm.smoother_bytes(nnzb0, n0, 20, 4, 10, 4)
+    assert sweep == (nnzb0 - n0) * 20 * 10 * 4 + 5 * 4 * n0 + n0 * 210 * 4 + 3 * n0 * 20 * 4 == 1635840000
+    tr = bm.transfer0_bytes(n0, n1, 20, 4, 4)
+    assert tr == n0 * 12 * 4 + 4 * n0 + n1 * 400 * 4
+    assert bm.restrict_bytes(nnzb0, n0, 20, 4, 10, 4, True, n1) + n0 * 20 * 4 == 1722638400
+    assert bm.spmv_bytes(nnzb0, n0, 20, 10, 4) == 3264000000
