@@ -1011,7 +1011,7 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed) {
 // wavefront per slice up to n_p = 10; the n_p = 20 rows are split in two,
 // measured fastest on the 3D p = 3 workload)
 int pick_h0(int np, int variant) {
-  if (variant == 0) return np >= 20 ? 2 : 1;
+  if (variant == 0) return 1;
   if ((variant == 1 || variant == 2 || variant == 4 || variant == 5) && np % variant == 0) return variant;
   return 0;
 }

@@ -14,13 +14,13 @@ CASES = {
     "2d_p1": (2, 11, 1, 3, 5),
     "3d_p2": (3, 4, 2, 3, 13),
     "3d_p1": (3, 5, 1, 3, 7),
-    # n_p = 20: two (automatic) or 4, 5 wavefronts per level-0 slice (750 tetrahedra, 12 slices, ragged)
+    # n_p = 20: one (automatic) or 2, 4, 5 wavefronts per level-0 slice (750 tetrahedra, 12 slices, ragged)
     "3d_p3": (3, 5, 3, 3, 17),
 }
 NP = {"2d_p1": 3, "2d_p2": 6, "2d_p3": 10, "3d_p1": 4, "3d_p2": 10, "3d_p3": 20}
 
-# level-0 wavefronts per slice: kernel_variant values (0 = automatic: 1 up to
-# n_p = 10, 2 for n_p = 20) run in FP64 on every case, and these in FP32
+# level-0 wavefronts per slice: kernel_variant values (0 = automatic: 1) run in
+# FP64 on every case, and these in FP32
 VARIANTS = [0, 1, 2, 4, 5]
 FP32_VARIANT_CASES = [("2d_p3", 0), ("2d_p3", 1), ("2d_p3", 2), ("2d_p3", 5), ("3d_p2", 0), ("3d_p3", 0),
                       ("3d_p3", 2), ("3d_p3", 4), ("3d_p3", 5)]
@@ -33,7 +33,7 @@ GROUP_CASES = ["2d_p2", "2d_p3", "3d_p2", "3d_p3"]
 
 
 def auto_wavefronts(npb):
-    return 2 if npb >= 20 else 1
+    return 1
 
 
 def _covered():

@@ -3,7 +3,7 @@ p = 2 on 105 456 Kuhn tetrahedra (n_p = 10, 1 054 560 DOFs, 5 levels) and
 p = 3 on 384 000 (n_p = 20, 7 680 000 DOFs, 6 levels, a coefficient with
 10^3 jumps across 32 spheres): sampled rows of the GPU-built level-0 product
 A_0 x against the oracle row by row, and properties that hold at any size
-for the V-cycle (n_p = 20 runs two wavefronts per slice)."""
+for the V-cycle (one wavefront per 64-row slice, as at n_p = 10)."""
 import numpy as np
 import pytest
 
