@@ -101,7 +101,8 @@ typedef struct cdgmg_options {
   int max_iter;        /* default 500 */
   int profile;         /* nonzero: time kernel classes with HIP events */
   int kernel_variant;  /* wavefronts per 64-row slice of the level-0 V-cycle kernels and of the
-                          outer FP64 product: 0 auto (1), or
+                          outer FP64 product: 0 auto (1; 2 for the compensated outer product and
+                          true residual at n_p = 20, which need more registers), or
                           1, 2, 4, 5 where it divides n_p (else setup fails with
                           CDGMG_ERR_ARG); coarse levels give each row a group of lanes
                           (coarse_group) */

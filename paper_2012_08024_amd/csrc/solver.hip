@@ -68,22 +68,25 @@ constexpr bool l0_pair(int np, int nf) {
     constexpr bool SYM = false;         \
     __VA_ARGS__;                        \
   }
-#define L0_DISPATCH(hh, ...)                                                                                \
+#define L0_DISPATCH_H(hh, hv, ...)                                                                          \
   switch ((hh)->P.nf) {                                                                                     \
     case 3: {                                                                                               \
       constexpr int NF = 3;                                                                                 \
-      SYM_DISPATCH((hh)->sym0, H_DISPATCH((hh)->H0, if constexpr (NP % H == 0 && l0_pair(NP, NF)) {         \
+      SYM_DISPATCH((hh)->sym0, H_DISPATCH((hv), if constexpr (NP % H == 0 && l0_pair(NP, NF)) {             \
         __VA_ARGS__;                                                                                        \
       }));                                                                                                  \
     } break;                                                                                                \
     case 4: {                                                                                               \
       constexpr int NF = 4;                                                                                 \
-      SYM_DISPATCH((hh)->sym0, H_DISPATCH((hh)->H0, if constexpr (NP % H == 0 && l0_pair(NP, NF)) {         \
+      SYM_DISPATCH((hh)->sym0, H_DISPATCH((hv), if constexpr (NP % H == 0 && l0_pair(NP, NF)) {             \
         __VA_ARGS__;                                                                                        \
       }));                                                                                                  \
     } break;                                                                                                \
     default: break;                                                                                         \
   }
+#define L0_DISPATCH(hh, ...) L0_DISPATCH_H(hh, (hh)->H0, __VA_ARGS__)
+// the compensated (double-double) outer kernels use their own split (H0c)
+#define L0C_DISPATCH(hh, ...) L0_DISPATCH_H(hh, (hh)->H0c, __VA_ARGS__)
 
 // hp front end: (n_p at degree q, n_p at the next lower degree) pairs
 #define HP_DISPATCH(np0, np1, ...)                                                   \
@@ -201,7 +204,8 @@ struct cdgmg_handle {
   cdgmg_options o;
   hipStream_t stream = nullptr;
   int np = 0, d = 0, W0 = 0, L = 0;
-  int H0 = 1;  // wavefronts per slice of the level-0 kernels
+  int H0 = 1;   // wavefronts per slice of the level-0 kernels
+  int H0c = 1;  // the same for the compensated outer product and true residual
   int64_t N0 = 0;
   std::vector<DLevel> lv;
   Workspace own_ws;
@@ -1010,8 +1014,12 @@ int build_operators(cdgmg_handle* h, const double* kappa_dev, bool transposed) {
 // wavefronts per 64-row slice of the level-0 kernels: 0 picks by n_p (one
 // wavefront per slice up to n_p = 10; the n_p = 20 rows are split in two,
 // measured fastest on the 3D p = 3 workload)
-int pick_h0(int np, int variant) {
-  if (variant == 0) return 1;
+// wavefronts per 64-row slice of the level-0 kernels: one unless the option
+// asks otherwise (measured fastest at every n_p); the compensated outer
+// kernels (comp) at n_p = 20 hold too many double-double accumulators for one
+// wavefront per slice (they spill) and take two
+int pick_h0(int np, int variant, bool comp = false) {
+  if (variant == 0) return comp && np >= 20 ? 2 : 1;
   if ((variant == 1 || variant == 2 || variant == 4 || variant == 5) && np % variant == 0) return variant;
   return 0;
 }
@@ -1263,7 +1271,7 @@ int read_scalar(cdgmg_handle* h, int slot, double* out) {
 // recursive residual is replaced by it); ||r||^2 lands in scal[SC_TMP]
 void enqueue_true_residual(cdgmg_handle* h) {
   DLevel& d = h->lv[0];
-  NP_DISPATCH(h->np, L0_DISPATCH(h, launch(h, CDGMG_K_VECTOR, k_residual0<NP, H, NF, SYM>, dim3((unsigned)d.ns),
+  NP_DISPATCH(h->np, L0C_DISPATCH(h, launch(h, CDGMG_K_VECTOR, k_residual0<NP, H, NF, SYM>, dim3((unsigned)d.ns),
                                             dim3(WAVE * H), d.n, (const int32_t*)d.cols, (const int8_t*)d.meta,
                                             (const double*)(SYM ? h->A0d : d.A64), (const double*)h->A0c, (const double*)h->b,
                                             (const double*)h->x, (const double*)h->xl, h->r, h->part)));
@@ -1363,7 +1371,7 @@ int krylov_cg(cdgmg_handle* h, cdgmg_solve_info* info) {
              sign, iter == 0 ? 1 : 0);
     const unsigned g = (unsigned)d0.ns;
     if (accurate) {
-      NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv0<NP, H, NF, SYM, true>, dim3(g), dim3(WAVE * H),
+      NP_DISPATCH(np, L0C_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv0<NP, H, NF, SYM, true>, dim3(g), dim3(WAVE * H),
                                             d0.n, (const int32_t*)d0.cols, (const int8_t*)d0.meta,
                                             (const double*)(SYM ? h->A0d : d0.A64), (const double*)h->A0c, (const double*)h->p,
                                             (const double*)h->r, h->q, h->part)));
@@ -1535,7 +1543,7 @@ int krylov_gmres(cdgmg_handle* h, cdgmg_solve_info* info) {
       const double* zj = Z + (int64_t)j * ld;
       const unsigned gs = (unsigned)d0.ns;
       if (accurate) {
-        NP_DISPATCH(np, L0_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv0<NP, H, NF, SYM, true, false>, dim3(gs),
+        NP_DISPATCH(np, L0C_DISPATCH(h, launch(h, CDGMG_K_SPMV, k_spmv0<NP, H, NF, SYM, true, false>, dim3(gs),
                                               dim3(WAVE * H), d0.n, (const int32_t*)d0.cols, (const int8_t*)d0.meta,
                                               (const double*)(SYM ? h->A0d : d0.A64), (const double*)h->A0c, zj,
                                               (const double*)nullptr, w, (double*)nullptr)));
@@ -1667,6 +1675,7 @@ int setup_inner(cdgmg_handle* h, const cdgmg_mesh& mesh, const cdgmg_hierarchy& 
   }
   if (rc) return rc;
   in->H0 = pick_h0(in->P.np, 0);
+  in->H0c = pick_h0(in->P.np, 0, true);
   const Level &a = h->P.lv[0], &b = in->P.lv[0];
   if (a.perm != b.perm || a.cols != b.cols || a.slice_blk != b.slice_blk) {
     set_error("setup: the lower-degree level does not share the level-0 order and pattern");
@@ -1749,6 +1758,7 @@ int prepare(const cdgmg_mesh* mesh, int p, const cdgmg_hierarchy* hier, const cd
   }
   if (!rc) {
     h->H0 = pick_h0(h->P.np, o.kernel_variant);
+    h->H0c = pick_h0(h->P.np, o.kernel_variant, true);
     if (!h->H0) {
       set_error("setup: kernel_variant must be 0 or one of 1, 2, 4, 5 dividing n_p = " + std::to_string(h->P.np));
       rc = CDGMG_ERR_ARG;
