@@ -127,12 +127,12 @@ typedef struct cdgmg_options {
                           (p, p - 1, ..., 1); 1 goes from p straight to p = 1 */
   int coarse_group;    /* lanes per row of the damped block-Jacobi sweep and of the residual +
                           restriction on levels 1 .. L-1: 0 (default) chooses by the level's
-                          mean row length and size, or 8, 16, 32, 64 for every such level
+                          mean row length (32, or 64 for long rows), or 8, 16, 32, 64 for every such level
                           (else CDGMG_ERR_ARG).  Results do not depend on it beyond rounding
                           order */
   int row_threads;     /* workgroup size of the thread-per-row transfer kernels (prolongation
-                          and correction, coarse-level entry): 0 (default) 64 on levels below
-                          100 000 rows and 256 above, or 64 or 256 on every level */
+                          and correction, coarse-level entry): 0 (default) 64, or 64 or 256
+                          on every level */
   int coarse_fp64;     /* with the FP32 V-cycle: 1 keeps the coarsest solve (the explicit
                           inverse of A_L, Alg. 3) in FP64, products summed in FP64 and the
                           result rounded to FP32 once; 0 (default) rounds the inverse to FP32 */

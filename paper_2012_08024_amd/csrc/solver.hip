@@ -641,18 +641,14 @@ int upload_problem(cdgmg_handle* h) {
       void* tmp;
       RETURN_IF(dalloc(h, (char**)&tmp, nr * (fp32 ? sizeof(float) : sizeof(double))));
       D.R = tmp;
-      // lanes per row by the mean strip width (measured on n_p = 10 strips of
-      // 53 columns: the sweep is fastest with 32 lanes on large levels and 16
-      // on smaller ones, the restriction, which also reads D^T L_e, with 16)
+      // lanes per row by the mean strip width (measured: 32 for the n_p = 10
+      // strips of about 60 columns of the 2D p = 3 hierarchy, at every level
+      // and for both kernels; 64 for the n_p = 20 strips of 3D p = 3)
       const double kmean = (double)(H.nnzb - H.n) * np / std::max<int64_t>(H.n, 1);
-      if (h->o.coarse_group) {
+      if (h->o.coarse_group)
         D.grp_s = D.grp_r = h->o.coarse_group;
-      } else if (kmean <= 96) {
-        D.grp_s = H.n >= 16384 ? 32 : 16;
-        D.grp_r = 16;
-      } else {
+      else
         D.grp_s = D.grp_r = kmean <= 192 ? 32 : 64;
-      }
     }
     if (l >= 1) {
       std::vector<int32_t> cs(H.child_start.begin(), H.child_start.end());
@@ -1078,8 +1074,8 @@ void dot_t(cdgmg_handle* h, const T* z, const double* dv, int* nparts) {
 constexpr size_t COARSEST_LDS = 48 * 1024;
 
 inline int row_tpb(const cdgmg_handle* h, int l) {
-  if (h->o.row_threads) return h->o.row_threads;
-  return h->lv[l].n < 100000 ? WAVE : TPB;
+  (void)l;
+  return h->o.row_threads ? h->o.row_threads : WAVE;
 }
 
 void* vcycle(cdgmg_handle* h, const double* r64, const double* dv, int* nparts);

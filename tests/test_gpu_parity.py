@@ -139,10 +139,9 @@ def test_fp64_coarsest_one_level():
 
 
 # Every kernel instantiation of the coarse levels: G lanes per row in the sweep
-# and in the residual + restriction (the automatic choice takes 16, 32 or 64 by
-# the level's size and mean row length), and both workgroup sizes of the
-# thread-per-row transfer kernels (the automatic choice takes 256 from 100 000
-# rows on).  The full-size tests check the benchmark workloads' launch
+# and in the residual + restriction (the automatic choice takes 32 or 64 by
+# the level's mean row length), and both workgroup sizes of the thread-per-row
+# transfer kernels (the automatic choice takes 64).  The full-size tests check the benchmark workloads' launch
 # configurations against kernel_coverage.COVERED.
 @pytest.mark.parametrize("rt", ROW_THREADS)
 @pytest.mark.parametrize("group", GROUPS)
